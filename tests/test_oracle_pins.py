@@ -1,0 +1,420 @@
+"""Pins of the FP64 oracle against closed forms, invariants, limits, brute
+force and finite differences (CPU only).
+
+Each test names the part of the paper it checks. None re-types the oracle's
+own expression and compares it with itself: the expected values come from an
+independent special case, a property the mathematics fixes, or a separate
+evaluation route.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+from scipy.special import erf
+
+import oracle
+import scenes
+from oracle.binning import bin_surfels
+from oracle.constants import ALPHA_MIN, PRIMES
+from oracle.geometry import kernel
+from oracle.hashgrid import downweight, encode, map_positive, spatial_hash
+from oracle.mlp import mlp_forward
+from tests.oracle_cases import (constant_grid, facing_scene, identity_camera, random_grid, random_mlp,
+                                scene_from)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _sigmoid(x):
+    return 1.0 / (1.0 + np.exp(-x))
+
+
+def _np_mlp(z, ws):
+    h = z
+    for i, w in enumerate(ws):
+        h = h @ np.asarray(w, dtype=np.float64).T
+        h = _sigmoid(h) if i == len(ws) - 1 else np.maximum(h, 0.0)
+    return h
+
+
+# ---------------------------------------------------------------- single surfel
+
+def _single_surfel_expect(cam, mu, sig, opac):
+    """Closed form for an axis-aligned surfel facing an identity camera.
+
+    The plane is z = mu_z, so t* = mu_z for every pixel; the hit point is
+    (mu_z dx, mu_z dy) and u, v are its offsets from the centre in units of
+    the scales (Preliminaries: (u, v) in primitive space; Geometry: alpha).
+    """
+    W, H = cam.width, cam.height
+    py, px = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    dx = (px + 0.5 - cam.cx) / cam.fx
+    dy = (py + 0.5 - cam.cy) / cam.fy
+    u = (mu[2] * dx - mu[0]) / sig[0]
+    v = (mu[2] * dy - mu[1]) / sig[1]
+    G = np.exp(-0.5 * (u * u + v * v))
+    a = opac * G
+    ok = (np.abs(u) <= 3) & (np.abs(v) <= 3) & (a >= ALPHA_MIN)
+    return np.where(ok, a, 0.0).reshape(-1), np.where(ok, G, 0.0).reshape(-1), dx.reshape(-1), dy.reshape(-1)
+
+
+def test_single_surfel_plain_closed_form():
+    """K=0: C = alpha c, T_final = 1 - alpha (eq. composite with one surfel)."""
+    cam = identity_camera(32, 32, 40.0)
+    mu, sig, opac, col = [0.05, -0.03, 2.0], [0.2, 0.3], 0.8, [0.2, 0.5, 0.7]
+    sc = scene_from([mu], [[1, 0, 0, 0]], [sig], [opac], [[1, 1]], [col])
+    rng = np.random.default_rng(1)
+    grid = random_grid(rng)
+    mlp = random_mlp(rng, [4, 8, 8, 3])
+    out = oracle.render(sc, cam, grid, mlp, K=0)
+    a, _, _, _ = _single_surfel_expect(cam, mu, sig, opac)
+    assert (a > 0).sum() > 50
+    np.testing.assert_allclose(out.image, a[:, None] * np.array(col)[None], atol=1e-14)
+    np.testing.assert_allclose(out.t_final, 1.0 - a, atol=1e-14)
+
+
+def test_single_surfel_textured_closed_form():
+    """K=1: C = alpha Tex(x*), W = alpha, D = t* = mu_z, N = 0 (eq. final).
+
+    A constant grid makes every level's interpolated feature equal that
+    constant (trilinear weights sum to one), so the texture is the MLP of
+    Delta_l(t*) * constant_l, evaluated here with numpy.
+    """
+    cam = identity_camera(32, 32, 40.0)
+    mu, sig, opac, col = [0.05, -0.03, 2.0], [0.2, 0.3], 0.8, [0.2, 0.5, 0.7]
+    sc = scene_from([mu], [[1, 0, 0, 0]], [sig], [opac], [[1, 1]], [col])
+    lvl = [[0.3, -0.2], [0.1, 0.4]]
+    grid = constant_grid(lvl)
+    rng = np.random.default_rng(2)
+    mlp = random_mlp(rng, [4, 8, 8, 3])
+    out = oracle.render(sc, cam, grid, mlp, K=1)
+    a, _, _, _ = _single_surfel_expect(cam, mu, sig, opac)
+    s = grid.level_scales.double().numpy()
+    delta = 1.0 - np.exp(-((cam.fx / (s * mu[2])) ** 2) / (2.0 * math.pi))
+    z = np.concatenate([delta[l] * np.array(lvl[l]) for l in range(2)])
+    tex = _np_mlp(z[None], [w.numpy() for w in mlp.weights])[0]
+    hit = a > 0
+    np.testing.assert_allclose(out.image, a[:, None] * tex[None], atol=1e-13)
+    np.testing.assert_allclose(out.weights[:, 0], a, atol=1e-14)
+    np.testing.assert_allclose(out.depths[hit, 0], mu[2], rtol=1e-14)
+    assert np.all(out.ids[hit, 0] == 0) and np.all(out.ids[~hit, 0] == -1)
+    np.testing.assert_allclose(out.plain, 0.0, atol=1e-15)
+
+
+def test_single_surfel_gradients_closed_form():
+    """dC/dc = alpha and dC/do = G c for a lone surfel (K=0)."""
+    cam = identity_camera(32, 32, 40.0)
+    mu, sig, opac, col = [0.05, -0.03, 2.0], [0.2, 0.3], 0.8, [0.2, 0.5, 0.7]
+    sc = scene_from([mu], [[1, 0, 0, 0]], [sig], [opac], [[1, 1]], [col])
+    rng = np.random.default_rng(3)
+    grid = random_grid(rng)
+    mlp = random_mlp(rng, [4, 8, 8, 3])
+    g = rng.standard_normal((32 * 32, 3))
+    out = oracle.render_and_grad(sc, cam, grid, mlp, K=0, grad_image=g)
+    a, G, _, _ = _single_surfel_expect(cam, mu, sig, opac)
+    np.testing.assert_allclose(out.grads["colors"][0], (a[:, None] * g).sum(0), rtol=1e-12)
+    np.testing.assert_allclose(out.grads["opacities"][0], (G * (g @ np.array(col))).sum(), rtol=1e-12)
+
+
+def test_two_surfels_front_to_back():
+    """w1 = alpha1, w2 = alpha2 (1 - alpha1); slots in compositing order."""
+    cam = identity_camera(8, 8, 10.0)
+    sc = scene_from([[0, 0, 2.0], [0, 0, 3.0]], [[1, 0, 0, 0]] * 2, [[1.0, 1.0], [1.5, 1.5]], [0.6, 0.7],
+                    [[1, 1]] * 2, [[1, 0, 0], [0, 1, 0]])
+    rng = np.random.default_rng(4)
+    out0 = oracle.render(sc, cam, random_grid(rng), random_mlp(rng, [4, 8, 8, 3]), K=0)
+    rng = np.random.default_rng(4)
+    out2 = oracle.render(sc, cam, random_grid(rng), random_mlp(rng, [4, 8, 8, 3]), K=2)
+    W, H = 8, 8
+    py, px = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    dx = ((px + 0.5 - 4) / 10.0).reshape(-1)
+    dy = ((py + 0.5 - 4) / 10.0).reshape(-1)
+    a1 = 0.6 * np.exp(-0.5 * ((2 * dx) ** 2 + (2 * dy) ** 2))
+    a2 = 0.7 * np.exp(-0.5 * ((3 * dx / 1.5) ** 2 + (3 * dy / 1.5) ** 2))
+    np.testing.assert_allclose(out0.image[:, 0], a1, atol=1e-14)
+    np.testing.assert_allclose(out0.image[:, 1], a2 * (1 - a1), atol=1e-14)
+    np.testing.assert_allclose(out0.t_final, (1 - a1) * (1 - a2), atol=1e-14)
+    np.testing.assert_allclose(out2.weights[:, 0], a1, atol=1e-14)
+    np.testing.assert_allclose(out2.weights[:, 1], a2 * (1 - a1), atol=1e-14)
+    assert np.all(out2.ids[:, 0] == 0) and np.all(out2.ids[:, 1] == 1)
+
+
+# ---------------------------------------------------------------- kernel limits
+
+def test_kernel_gamma_one_is_gaussian():
+    """gamma = 1 gives the 2DGS Gaussian exp(-(u^2 + v^2)/2) (Geometry)."""
+    u = torch.linspace(-3, 3, 61, dtype=torch.float64)
+    v = torch.linspace(-2, 2, 61, dtype=torch.float64)
+    G = kernel(u, v, torch.ones(61, 2, dtype=torch.float64))
+    np.testing.assert_allclose(G.numpy(), np.exp(-0.5 * (u.numpy() ** 2 + v.numpy() ** 2)), rtol=1e-14)
+
+
+def test_kernel_large_gamma_is_quad_indicator():
+    """gamma -> infinity approaches the indicator of the unit quad (Geometry)."""
+    u = torch.tensor([0.0, 0.5, 0.9, 1.1, 2.0], dtype=torch.float64)
+    v = torch.tensor([0.0, 0.2, 0.85, 0.3, 0.1], dtype=torch.float64)
+    G = kernel(u, v, torch.full((5, 2), 50.0, dtype=torch.float64)).numpy()
+    np.testing.assert_allclose(G[:3], 1.0, atol=2e-3)
+    np.testing.assert_allclose(G[3:], 0.0, atol=1e-300)
+
+
+# ---------------------------------------------------------------- invariants on a scene
+
+@pytest.fixture(scope="module")
+def c1_small():
+    wl = scenes.make_workload(1, seed=0, width=64, height=48)
+    return wl
+
+
+def test_weights_plus_transmittance_is_one(c1_small):
+    """sum_i w_i + T_final = 1 (eq. composite, telescoping product)."""
+    wl = c1_small
+    sc = scenes.Scene(*[t.clone() for t in wl.scene.tensors()])
+    sc.colors = torch.ones_like(sc.colors)
+    out = oracle.render(sc, wl.cameras[0], wl.grid, wl.mlp, K=4)
+    total = out.weights.sum(1) + out.plain[:, 0] + out.t_final
+    np.testing.assert_allclose(total, 1.0, atol=1e-12)
+    assert out.weights.min() >= 0 and out.weights.max() <= 1
+    assert out.t_final.min() >= 0 and out.t_final.max() <= 1
+
+
+def test_final_versus_notexture(c1_small):
+    """C(K=0) = N(K) + sum_j W_j c_{I_j} (eq. notexture against eq. composite)."""
+    wl = c1_small
+    cam = wl.cameras[0]
+    out0 = oracle.render(wl.scene, cam, wl.grid, wl.mlp, K=0)
+    out4 = oracle.render(wl.scene, cam, wl.grid, wl.mlp, K=4)
+    col = wl.scene.colors.double().numpy()
+    sel = np.where(out4.ids[..., None] >= 0, col[np.maximum(out4.ids, 0)], 0.0)
+    recon = out4.plain + (out4.weights[..., None] * sel).sum(1)
+    np.testing.assert_allclose(recon, out0.image, atol=1e-13)
+    np.testing.assert_allclose(out0.t_final, out4.t_final, atol=0)
+
+
+def test_topk_is_prefix_of_full_sort(c1_small):
+    """The K slots are the K largest weights under (w desc, id asc) (Collection Pass)."""
+    wl = c1_small
+    cam = wl.cameras[0]
+    full = oracle.render(wl.scene, cam, wl.grid, wl.mlp, K=64)
+    assert full.n_comp.max() < 64
+    np.testing.assert_allclose(full.plain, 0.0, atol=1e-15)  # everything selected: N = 0
+    out = oracle.render(wl.scene, cam, wl.grid, wl.mlp, K=4)
+    for p in range(full.pixels.shape[0]):
+        entries = [(full.weights[p, j], full.ids[p, j], j) for j in range(64) if full.ids[p, j] >= 0]
+        best = sorted(entries, key=lambda e: (-e[0], e[1]))[:4]
+        best = sorted(best, key=lambda e: e[2])  # compositing order
+        ids = [e[1] for e in best] + [-1] * (4 - len(best))
+        assert list(out.ids[p]) == ids
+
+
+def test_tiled_equals_untiled(c1_small):
+    """Binning is conservative: restricting candidates to tile lists changes nothing."""
+    wl = c1_small
+    cam = wl.cameras[0]
+    a = oracle.render(wl.scene, cam, wl.grid, wl.mlp, K=4)
+    b = oracle.render(wl.scene, cam, wl.grid, wl.mlp, K=4, tiled=True)
+    np.testing.assert_array_equal(a.ids, b.ids)
+    np.testing.assert_allclose(a.image, b.image, atol=1e-13)
+    np.testing.assert_allclose(a.t_final, b.t_final, atol=1e-13)
+
+
+def test_tiled_equals_untiled_near_plane_crossing():
+    """Camera inside the cloud: many surfels cross the near plane and get clipped."""
+    wl = scenes.make_workload(1, seed=5, width=48, height=48, n_surfels=3000)
+    cam = scenes.look_at((0.0, 0.0, -0.3), (0.0, 0.0, 1.0), (0.0, -1.0, 0.0), 48, 48)
+    info = bin_surfels(wl.scene, cam)
+    a = oracle.render(wl.scene, cam, wl.grid, wl.mlp, K=4, bins=info)
+    b = oracle.render(wl.scene, cam, wl.grid, wl.mlp, K=4, tiled=True, bins=info)
+    assert (a.n_comp > 0).mean() > 0.5
+    np.testing.assert_array_equal(a.ids, b.ids)
+    np.testing.assert_allclose(a.image, b.image, atol=1e-13)
+
+
+def test_binning_matches_brute_force_lists(c1_small):
+    """Each tile's list is exactly the surfels whose rectangle covers it, by (key, id)."""
+    wl = c1_small
+    info = bin_surfels(wl.scene, wl.cameras[0])
+    rect, count, key = info["rect"], info["count"], info["key"]
+    for t in range(info["ntx"] * info["nty"]):
+        tx, ty = t % info["ntx"], t // info["ntx"]
+        members = [i for i in range(rect.shape[0]) if count[i] > 0 and rect[i, 0] <= tx <= rect[i, 2]
+                   and rect[i, 1] <= ty <= rect[i, 3]]
+        members.sort(key=lambda i: (float(key[i]), i))
+        s, e = info["ranges"][t]
+        assert list(info["ids"][s:e]) == members
+
+
+# ---------------------------------------------------------------- hash grid
+
+def test_map_positive_is_bijection():
+    """MapPositive maps Z one-to-one onto N (supplementary, Architecture)."""
+    z = np.arange(-10**6, 10**6 + 1)
+    m = map_positive(z)
+    assert m.min() == 0 and m.max() == 2 * 10**6
+    assert np.unique(m).shape[0] == z.shape[0]
+    assert list(map_positive(np.array([0, 1, -1, 2, -2]))) == [0, 1, 2, 3, 4]
+
+
+def test_spatial_hash_matches_big_integer_arithmetic():
+    rng = np.random.default_rng(7)
+    k = rng.integers(0, 2**31, (1000, 3))
+    got = spatial_hash(k[:, 0], k[:, 1], k[:, 2], 19)
+    for i in range(1000):
+        h = ((int(k[i, 0]) * PRIMES[0]) ^ (int(k[i, 1]) * PRIMES[1]) ^ (int(k[i, 2]) * PRIMES[2])) % (1 << 32)
+        assert got[i] == h & ((1 << 19) - 1)
+
+
+def test_constant_table_partition_of_unity():
+    """Trilinear weights sum to one: a constant table yields Delta * constant."""
+    grid = constant_grid([[0.25, -0.5], [1.5, 0.125]])
+    rng = np.random.default_rng(8)
+    x = torch.from_numpy(rng.uniform(-30, 30, (500, 3)))
+    D = torch.from_numpy(rng.uniform(0.3, 40, 500))
+    z = encode(x, D, grid.table.double(), grid.level_scales.double(), 500.0).numpy()
+    for l, vals in enumerate([[0.25, -0.5], [1.5, 0.125]]):
+        dl = downweight(D, float(grid.level_scales[l]), 500.0).numpy()
+        np.testing.assert_allclose(z[:, 2 * l:2 * l + 2], dl[:, None] * np.array(vals)[None], rtol=1e-13)
+
+
+def test_lattice_points_read_single_entry():
+    """At a lattice point the interpolation returns the entry of that corner."""
+    rng = np.random.default_rng(9)
+    grid = random_grid(rng, levels=1, log2_size=10)
+    s = float(grid.level_scales[0])
+    k = rng.integers(-5000, 5000, (200, 3))
+    x = torch.from_numpy(k / s)
+    D = torch.full((200,), 1e-6, dtype=torch.float64)  # Delta = 1 to double precision
+    z = encode(x, D, grid.table.double(), grid.level_scales.double(), 1.0).numpy()
+    mp = map_positive(k)
+    h = spatial_hash(mp[:, 0], mp[:, 1], mp[:, 2], 10)
+    np.testing.assert_array_equal(z, grid.table.numpy()[0, h])
+
+
+def test_interpolation_is_linear_inside_a_cell():
+    rng = np.random.default_rng(10)
+    grid = random_grid(rng, levels=1, log2_size=8)
+    s = float(grid.level_scales[0])
+    base = np.array([[3.25, -7.5, 11.75]]) / s
+    e = np.array([[1.0, 0.0, 0.0]]) / s
+    pts = torch.from_numpy(np.concatenate([base, base + 0.25 * e, base + 0.5 * e]))
+    D = torch.full((3,), 1e-6, dtype=torch.float64)
+    z = encode(pts, D, grid.table.double(), grid.level_scales.double(), 1.0).numpy()
+    np.testing.assert_allclose(z[1], 0.5 * (z[0] + z[2]), rtol=1e-13)
+
+
+def test_downweight_matches_erf_squared_and_limits():
+    """Delta approximates erf(f / (2 sqrt2 s t))^2 (supplementary, Anti-aliasing)."""
+    f = 1662.77
+    s = torch.tensor(16.0 * 1.5 ** np.arange(16), dtype=torch.float64)
+    t = torch.logspace(-2, 3, 400, dtype=torch.float64)
+    D = downweight(t[:, None], s[None, :], f).numpy()
+    ref = erf(f / (2 * np.sqrt(2) * s.numpy()[None] * t.numpy()[:, None])) ** 2
+    assert np.max(np.abs(D - ref)) <= 0.0116
+    assert np.all(np.diff(D, axis=0) <= 0) and np.all(np.diff(D, axis=1) <= 0)  # decreasing in t and s
+    assert downweight(torch.tensor(1e-9, dtype=torch.float64), 7000.0, f).item() == 1.0
+    assert downweight(torch.tensor(1e9, dtype=torch.float64), 16.0, f).item() < 1e-12
+
+
+def test_mlp_matches_numpy_chain_and_zero_input():
+    rng = np.random.default_rng(11)
+    mlp = random_mlp(rng, [32, 64, 64, 3])
+    z = rng.standard_normal((100, 32))
+    got = mlp_forward(torch.from_numpy(z), mlp.weights).numpy()
+    np.testing.assert_allclose(got, _np_mlp(z, [w.numpy() for w in mlp.weights]), rtol=1e-12)
+    # bias-free: G(0) is the head's activation at zero
+    z0 = mlp_forward(torch.zeros(1, 32, dtype=torch.float64), mlp.weights).numpy()
+    np.testing.assert_allclose(z0, 0.5)
+
+
+# ---------------------------------------------------------------- finite differences
+
+def _fd_setup(seed, gamma_range=None):
+    rng = np.random.default_rng(seed)
+    cam = identity_camera(32, 32, 40.0)
+    sc = facing_scene(rng, 14, tilt=0.35)
+    if gamma_range is not None:
+        sc.gammas = torch.from_numpy(rng.uniform(*gamma_range, (14, 2)))
+    grid = random_grid(rng, levels=2, log2_size=8, scale=0.5)
+    mlp = random_mlp(rng, [4, 16, 16, 3])
+    gi = rng.standard_normal((32 * 32, 3))
+    gw = rng.standard_normal((32 * 32, 2))
+    gt = rng.standard_normal((32 * 32, 2, 3))
+    return rng, cam, sc, grid, mlp, gi, gw, gt
+
+
+def _loss(out, gi, gw, gt):
+    return float((out.image * gi).sum() + (out.weights * gw).sum() + (out.tex * gt).sum())
+
+
+@pytest.mark.parametrize("seed,gamma_range", [(20, None), (21, (1.0, 4.0))])
+def test_gradients_match_central_differences(seed, gamma_range):
+    """Autograd gradients of the oracle equal central differences of its forward."""
+    rng, cam, sc, grid, mlp, gi, gw, gt = _fd_setup(seed, gamma_range)
+    K = 2
+    out = oracle.render_and_grad(sc, cam, grid, mlp, K, grad_image=gi, grad_weights=gw, grad_tex=gt)
+    assert (out.n_comp > 0).mean() > 0.4
+    h = 1e-8  # small enough that no hash-cell face or ReLU kink is crossed
+
+    def run(scn, grd, mp):
+        return oracle.render(scn, cam, grd, mp, K)
+
+    names = ["means", "quats", "scales", "opacities", "gammas", "colors"]
+    for nm in names + ["table", "mlp0", "mlp1", "mlp2"]:
+        for trial in range(2):
+            if nm in names:
+                base = getattr(sc, nm)
+                vdir = torch.from_numpy(rng.standard_normal(tuple(base.shape)))
+                g = out.grads[nm]
+
+                def make(sign):
+                    s2 = scenes.Scene(*[t.clone() for t in sc.tensors()])
+                    setattr(s2, nm, base + sign * h * vdir)
+                    return run(s2, grid, mlp)
+            elif nm == "table":
+                base = grid.table
+                vdir = torch.from_numpy(rng.standard_normal(tuple(base.shape)))
+                g = out.grads["table"]
+
+                def make(sign):
+                    return run(sc, scenes.HashGrid(base + sign * h * vdir, grid.level_scales), mlp)
+            else:
+                li = int(nm[-1])
+                base = mlp.weights[li]
+                vdir = torch.from_numpy(rng.standard_normal(tuple(base.shape)))
+                g = out.grads["mlp"][li]
+
+                def make(sign):
+                    ws = list(mlp.weights)
+                    ws[li] = base + sign * h * vdir
+                    return run(sc, grid, scenes.MLP(ws))
+            op, om = make(+1), make(-1)
+            assert np.array_equal(op.ids, out.ids) and np.array_equal(om.ids, out.ids), nm
+            assert np.array_equal(op.n_comp, out.n_comp) and np.array_equal(om.n_comp, out.n_comp), nm
+            fd = (_loss(op, gi, gw, gt) - _loss(om, gi, gw, gt)) / (2 * h)
+            an = float((np.asarray(g) * vdir.numpy()).sum())
+            assert abs(fd - an) <= 2e-6 * max(1.0, abs(an)), (nm, fd, an)
+
+
+# ---------------------------------------------------------------- parameter layout
+
+def test_storage_count_matches_paper_figures():
+    """Two bytes per Instant-NGP parameter, four per other parameter
+    (supplementary, Other details) reproduce the printed 160/100/90 MB.
+    60 floats per surfel: mean 3, quaternion 4, scale 2, opacity 1, gamma 2, SH 48."""
+    g = json.load(open(os.path.join(HERE, "golden", "paper_storage.json")))
+    n = g["n_primitives"]
+    per_surfel = 3 + 4 + 2 + 1 + 2 + g["sh_values_per_primitive"]
+    dims = g["mlp_dims"]
+    ngp = g["levels"] * (1 << g["log2_table"]) * g["feat"] + sum(dims[i] * dims[i + 1] for i in range(3))
+    full = (n * per_surfel * 4 + ngp * 2) / 1e6
+    no_tex = n * per_surfel * 4 / 1e6
+    no_sh = (n * (per_surfel - 45) * 4 + ngp * 2) / 1e6
+    tol = g["printed_rounding_mb"]
+    assert abs(full - g["printed_mb"]["full"]) <= tol
+    assert abs(no_tex - g["printed_mb"]["no_texture"]) <= tol
+    assert abs(no_sh - g["printed_mb"]["no_prim_sh"]) <= tol
