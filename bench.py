@@ -1,0 +1,227 @@
+"""Throughput of one forward+backward rendering step on one MI355X.
+
+A step is the whole rendering path for one camera: collection pass
+(preprocess, depth sort, tile binning and sort, raster), texturing pass
+(hash grid + MLP + composite), the L2 image-loss gradient, and the backward
+of both passes (hash-grid, MLP and surfel gradients). Inputs are resident in
+HBM before the timed region.
+
+Workload: 400k surfels (ground plane + 50 boxes, depths 0.5-50 m, scales
+spanning three decades), 1920x1080, K=4, hash grid 16 x 2^19 x 2,
+MLP 32-64-64-3. The headline form stores the grid in FP16 and runs the MLP
+on BF16 matrix cores; the FP32 form (FP32 grid, FP32 matrix cores) is timed
+beside it.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu-baseline]
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Mpix/s fwd+bwd at 400k surfels 1080p K=4 (BF16 vs FP32); % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
+FP32_PEAK_TFLOPS = 157.3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic(phase, st):
+    """(HBM bytes, matrix flops) one launch of `phase` must move / compute.
+
+    Counts each input read once and each output written once at its storage
+    width; the hash table is counted once per launch (its re-reads are cache
+    traffic); atomically updated buffers count a read and a write."""
+    N, P, K, I, T = st["N"], st["P"], st["K"], st["I"], st["n_tiles"]
+    S = P * K
+    table = st["L"] * st["T"] * st["F"] * st["tb"]
+    gtable = st["L"] * st["T"] * st["F"] * 4
+    mlp_flops = 2.0 * S * (st["in"] * st["H"] + st["H"] * st["H"] + 3 * st["H"])
+    rec = 80
+    b = {
+        "preprocess": N * (60 + 4 + 4 + 16 + rec),
+        "depth_sort": N * (8 + 4 * 16),
+        "instance_scan": N * 12,
+        "duplicate": N * 24 + I * 8,
+        "tile_sort": I * 16 * st["tile_passes"],
+        "tile_ranges": I * 4 + T * 8,
+        "raster_forward": I * (4 + rec) + T * 8 + P * (12 + 12 * K + 8),
+        "texture_forward": S * 24 + P * 24 + table,
+        "zero_record_grads": N * 64,
+        "texture_backward": S * 16 + P * 12 + table + 2 * gtable,
+        "raster_backward": I * (4 + rec) + T * 8 + P * (28 + 24 * K) + N * 120,
+        "preprocess_backward": N * (36 + 4 + 64 + 2 * 60),
+    }
+    f = {"texture_forward": mlp_flops, "texture_backward": 3.0 * mlp_flops}
+    return float(b.get(phase, 0)), float(f.get(phase, 0.0))
+
+
+def setup(form):
+    import torch
+
+    import paper_2512_13796_amd as nx
+    import scenes
+
+    if form == "bf16":
+        wl = scenes.make_workload(3)  # FP16 grid, BF16 MLP
+    else:
+        wl = scenes.make_workload(3, feat_dtype=torch.float32, mlp_dtype=torch.float32)
+    dev = torch.device("cuda:0")
+    surf = tuple(t.to(dev).contiguous() for t in wl.scene.tensors())
+    table = wl.grid.table.to(dev).contiguous()
+    weights = [w.to(dev).contiguous() for w in wl.mlp.weights]
+    target = wl.target[0].reshape(-1, 3).to(dev).contiguous()
+    ctx = nx.Context(wl.K, table.dtype, weights[0].dtype)
+    z = lambda t: torch.zeros(t.shape, device=dev, dtype=torch.float32)
+    grads = {"means": z(surf[0]), "quats": z(surf[1]), "scales": z(surf[2]), "opacities": z(surf[3]),
+             "gammas": z(surf[4]), "colors": z(surf[5]), "table": z(table), "mlp": [z(w) for w in weights]}
+    return nx, wl, ctx, surf, table, weights, target, grads
+
+
+def make_step(nx, wl, ctx, surf, table, weights, target, grads):
+    cam = wl.cameras[0]
+    P = cam.width * cam.height
+    scale = 2.0 / (3.0 * P)
+    state = {}
+
+    def step():
+        res = nx.render_forward(ctx, surf, cam, table, wl.grid.level_scales, weights)
+        g = (res.image - target).mul_(scale)
+        for k, t in grads.items():
+            if k == "mlp":
+                for w in t:
+                    w.zero_()
+            else:
+                t.zero_()
+        nx.render_backward(ctx, surf, res, table, wl.grid.level_scales, weights, g, None, None, grads)
+        state["res"] = res
+        return res
+
+    return step, state
+
+
+def time_form(form, steps, warmup):
+    import torch
+
+    nx, wl, ctx, surf, table, weights, target, grads = setup(form)
+    step, state = make_step(nx, wl, ctx, surf, table, weights, target, grads)
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    ctx.timing_reset()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / steps
+    phases = ctx.timings()
+    ctx.timing(False)
+    cam = wl.cameras[0]
+    res = state["res"]
+    st = {"N": wl.scene.n, "P": cam.width * cam.height, "K": wl.K, "I": res.n_instances,
+          "n_tiles": ((cam.width + 15) // 16) * ((cam.height + 15) // 16), "L": wl.grid.levels,
+          "T": 1 << wl.grid.log2_size, "F": wl.grid.feat, "tb": table.element_size(),
+          "in": weights[0].shape[1], "H": weights[0].shape[0], "tile_passes": 2}
+    return {"ms": ms, "wall_ms": 1000.0 * wall / steps, "phases": phases, "stats": st, "workload": wl}
+
+
+def cpu_baseline(sample_pixels=192, seed=0):
+    """The FP64 oracle, as it stands, on a bounded pixel sample of the same workload."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import scenes
+
+    wl = scenes.make_workload(3)
+    cam = wl.cameras[0]
+    P = cam.width * cam.height
+    rng = np.random.default_rng(seed)
+    pix = np.sort(rng.choice(P, sample_pixels, replace=False))
+    target = wl.target[0].reshape(-1, 3).double().numpy()
+    t0 = time.perf_counter()
+    out = oracle.render(wl.scene, cam, wl.grid, wl.mlp, wl.K, pixels=pix)
+    g = 2.0 * (out.image - target[pix]) / (3.0 * P)
+    oracle.render_and_grad(wl.scene, cam, wl.grid, wl.mlp, wl.K, pixels=pix, grad_image=g)
+    dt = time.perf_counter() - t0
+    return {"value": sample_pixels / dt / 1e6, "unit": "Mpix/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"{sample_pixels} random pixels of the 1920x1080 400k-surfel frame, forward (every surfel "
+                      f"tested per pixel) then forward+backward with the L2 gradient: {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=192)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (the rendering path has no multi-GPU code); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    log("bf16 form ...")
+    bf = time_form("bf16", args.steps, args.warmup)
+    st = bf["stats"]
+    P = st["P"]
+    value = P / (bf["ms"] / 1000.0) / 1e6
+    phases = {k: v[0] / max(v[1], 1) for k, v in bf["phases"].items()}
+    dom = max(phases, key=lambda k: phases[k])
+    nbytes, nflops = algorithmic(dom, st)
+    dur_s = phases[dom] / 1000.0
+    achieved = nbytes / dur_s / 1e9
+    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "avg_ms": round(phases[dom], 4),
+            "algorithmic_bytes": nbytes}
+    if nflops:
+        roof["mfma_tflops"] = round(nflops / dur_s / 1e12, 2)
+        roof["mfma_frac"] = round(nflops / dur_s / 1e12 / BF16_PEAK_TFLOPS, 5)
+    line = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(bf["ms"], 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "outdoor 400k surfels 1920x1080 K=4, grid 16x2^19x2 fp16, MLP 32-64-64-3 bf16",
+                   "surfels": st["N"], "width": 1920, "height": 1080, "K": st["K"], "instances": st["I"]},
+        "roofline": roof,
+        "phases_ms": {k: round(v, 4) for k, v in sorted(phases.items(), key=lambda kv: -kv[1])},
+    }
+    if not args.no_fp32:
+        log("fp32 form ...")
+        f32 = time_form("fp32", max(3, args.steps // 2), max(1, args.warmup // 2))
+        ph32 = {k: v[0] / max(v[1], 1) for k, v in f32["phases"].items()}
+        line["fp32_form"] = {"value": round(P / (f32["ms"] / 1000.0) / 1e6, 2), "ms_per_step": round(f32["ms"], 4),
+                             "phases_ms": {k: round(v, 4) for k, v in sorted(ph32.items(), key=lambda kv: -kv[1])}}
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        line["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,205 @@
+/*
+ * nexels.h -- C ABI of the MI355X (gfx950) Nexels rendering library.
+ *
+ * The library renders neurally-textured surfels (Nexels, arXiv 2512.13796)
+ * with two passes and differentiates them:
+ *   collection pass  (Rendering, Collection Pass; eq. composite, eq. notexture):
+ *                    per pixel, front-to-back alpha compositing of the
+ *                    surfels' plain colours in centre-depth order, keeping the
+ *                    K intersections of highest blending weight;
+ *   texturing pass   (Rendering, Texturing Pass; eq. texture, eq. final):
+ *                    hash-grid features at the K intersection points, scaled
+ *                    by the down-weighting factor (eq. downweighting), decoded
+ *                    by a bias-free ReLU MLP, and composited into the image.
+ *
+ * Conventions for every entry point:
+ *   - Return value is an nx_status. Arguments are validated on the host
+ *     before anything is launched; a failed call launches nothing and
+ *     nx_last_error() describes the failure. A device fault from earlier
+ *     asynchronous work is reported as NX_ERR_HIP by a later call.
+ *   - "device" pointers must point to GPU memory of the current HIP device;
+ *     "host" pointers to CPU memory. All device buffers are owned by the
+ *     caller; the library allocates no device memory except a small pinned
+ *     host word per context.
+ *   - Arrays are dense and row-major; [a,b] means a rows of b elements.
+ *   - Work is enqueued on the HIP stream passed as `stream` (NULL = the null
+ *     stream). nx_render_forward synchronises that stream once to read the
+ *     number of tile instances; nx_render_backward does not synchronise.
+ *   - Calls that share a workspace must not overlap.
+ */
+#ifndef NEXELS_H
+#define NEXELS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NX_OK = 0,
+  NX_ERR_INVALID = -1,     /* bad argument (null pointer, size, dtype, ...)  */
+  NX_ERR_WORKSPACE = -2,   /* workspace too small; *workspace_required set  */
+  NX_ERR_HIP = -3,         /* a HIP runtime call failed                     */
+  NX_ERR_UNSUPPORTED = -4  /* valid but not implemented (e.g. K=3, F!=2)    */
+} nx_status;
+
+typedef enum { NX_F32 = 0, NX_F16 = 1, NX_BF16 = 2 } nx_dtype;
+
+/* Surfel parameters, already activated (Representation, Geometry):
+ * device pointers, float32.
+ *   means     [n,3]  centres mu (world)
+ *   quats     [n,4]  rotations (w,x,y,z), used as given (caller normalises);
+ *                    R = [v1 v2 v3], v1/v2 span the surfel, v3 its normal
+ *   scales    [n,2]  s1, s2 > 0 along v1, v2
+ *   opacities [n]    in [0,1]
+ *   gammas    [n,2]  generalised-Gaussian exponents, >= 1
+ *   colors    [n,3]  plain (non-textured) RGB colour
+ * Surfels with a non-finite parameter, a scale <= 0 or a centre at camera
+ * depth <= near are culled (never drawn, zero gradient). */
+typedef struct {
+  const float *means, *quats, *scales, *opacities, *gammas, *colors;
+  int64_t n;
+} nx_surfels;
+
+/* Pinhole camera (host struct). world_to_cam is the row-major 3x4 [R | t]
+ * with x_cam = R x_world + t in the OpenCV frame (x right, y down, z
+ * forward). Pixel (px, py) casts the ray through (px+0.5, py+0.5); its
+ * parameter t is the camera-space depth. near is the near-plane depth. */
+typedef struct {
+  double world_to_cam[12];
+  double fx, fy, cx, cy;
+  double near_z;
+  int32_t width, height;
+} nx_camera;
+
+/* Multiresolution hash grid (Preliminaries, Instant-NGP; supplementary
+ * Implementation Details). table: device, [levels][1<<log2_size][feat] in
+ * `dtype`. level_scales: HOST pointer, [levels] float32 scales s_l.
+ * Supported: feat == 2, 1 <= levels <= 16, 4 <= log2_size <= 24. */
+typedef struct {
+  const void *table;
+  nx_dtype dtype;
+  int32_t levels, log2_size, feat;
+  const float *level_scales;
+} nx_hashgrid;
+
+/* Texture MLP without biases (Results, implementation): w[i] is a device
+ * [dims[i+1]][dims[i]] matrix in `dtype` (NX_F32 or NX_BF16). Hidden layers
+ * use ReLU, the 3-channel head a sigmoid.
+ * Supported: dims = {levels*feat (<= 32), 64 or 128, same, 3}. NX_F32 runs
+ * on FP32 matrix cores, NX_BF16 on BF16 matrix cores with FP32 accumulation. */
+typedef struct {
+  const void *w[3];
+  nx_dtype dtype;
+  int32_t dims[4];
+} nx_mlp;
+
+/* Forward outputs (device, float32 unless noted), P = width*height:
+ *   image   [P,3]    C = N + sum_j W_j Tex_j                    (eq. final)
+ *   plain   [P,3]    N: plain colours of the unselected surfels (eq. notexture)
+ *   ids     [P,K]    int32 ids of the selected surfels, compositing order, -1 empty
+ *   weights [P,K]    blending weights W of the selected surfels (0 if empty)
+ *   depths  [P,K]    intersection depths D (camera z, 0 if empty)
+ *   t_final [P]      transmittance after the last composited surfel
+ *   tex     [P,K,3]  decoded textures (0 if empty)
+ *   n_iter  [P]      uint32, entries of the pixel's tile list the collection
+ *                    pass consumed (bounds the backward replay)
+ *   cells   [P,K,levels,3]  OPTIONAL (NULL = not written) int32 lattice cell
+ *                    floor(s_l x) the texturing pass used per slot and level,
+ *                    for inspecting the hash-cell decisions (0 for empty slots)
+ *   relu_masks [P,K,2*hidden/32]  OPTIONAL (NULL = not written) uint32 bit
+ *                    masks of the hidden units with a positive pre-activation,
+ *                    layer 1 words then layer 2 words, bit i of word w for
+ *                    unit 32 w + i (0 for empty slots)
+ *   n_instances      host scalar written by nx_render_forward: number of
+ *                    (surfel, tile) pairs; read by nx_render_backward. */
+typedef struct {
+  float *image, *plain;
+  int32_t *ids;
+  float *weights, *depths, *t_final, *tex;
+  uint32_t *n_iter;
+  int32_t *cells;
+  uint32_t *relu_masks;
+  int64_t n_instances;
+} nx_fwd_out;
+
+/* Gradients, device float32, ACCUMULATED (+=) into caller-initialised
+ * buffers: means [n,3], quats [n,4], scales [n,2], opacities [n],
+ * gammas [n,2], colors [n,3], table [levels][1<<log2_size][feat] (always
+ * float32 whatever the table's storage dtype), mlp[i] [dims[i+1]][dims[i]].
+ * Any pointer may be NULL to skip that gradient. */
+typedef struct {
+  float *means, *quats, *scales, *opacities, *gammas, *colors;
+  float *table;
+  float *mlp[3];
+} nx_grads;
+
+/* Opaque context: fixed configuration plus one pinned host word. */
+typedef struct nx_ctx nx_ctx;
+
+/* Create a context. K in {0,1,2,4,8,16} is the number of textured
+ * intersections per pixel (Collection Pass); tile must be 16. feat_dtype and
+ * mlp_dtype are the storage dtypes later calls must use. */
+int nx_create(nx_ctx **out, int32_t K, int32_t tile, nx_dtype feat_dtype, nx_dtype mlp_dtype);
+int nx_destroy(nx_ctx *ctx);
+
+/* Workspace bytes for n_surfels surfels seen by one camera with at most
+ * max_instances (surfel, tile) pairs. The same workspace carries the
+ * forward's sorted tile lists and per-surfel records to the backward. */
+int nx_workspace_size(nx_ctx *ctx, int64_t n_surfels, const nx_camera *cams, int32_t n_cams,
+                      int64_t max_instances, size_t *bytes);
+
+/* Collection pass, then texturing pass (Rendering). cams: host array of
+ * n_cams cameras (n_cams == 1 is supported). If the workspace is too small
+ * the call returns NX_ERR_WORKSPACE, stores the required size in
+ * *workspace_required and leaves the outputs undefined; call again with a
+ * large enough workspace. */
+int nx_render_forward(nx_ctx *ctx, const nx_surfels *surfels, const nx_camera *cams, int32_t n_cams,
+                      const nx_hashgrid *grid, const nx_mlp *mlp, nx_fwd_out *out, void *workspace,
+                      size_t workspace_bytes, size_t *workspace_required, void *stream);
+
+/* Gradients of L through both passes given dL/dimage [P,3] (device) and the
+ * optional dL/dweights [P,K] and dL/dtex [P,K,3] (device, NULL = zero). saved
+ * and workspace must be those of the matching forward call, unmodified.
+ * Discrete choices (stop, top-K, hash cell) are those the forward took.
+ * Atomic accumulation makes results deterministic up to float32 summation
+ * order. */
+int nx_render_backward(nx_ctx *ctx, const nx_surfels *surfels, const nx_camera *cams, int32_t n_cams,
+                       const nx_hashgrid *grid, const nx_mlp *mlp, const nx_fwd_out *saved,
+                       const void *workspace, size_t workspace_bytes, const float *grad_image,
+                       const float *grad_weights, const float *grad_tex, const nx_grads *grads, void *stream);
+
+/* Byte offsets of the forward's intermediate arrays inside the workspace,
+ * for inspection: depth keys [n] uint32 (float32 bits of the camera-space
+ * centre depth), tile counts [n] uint32, tile rectangles [n,4] int32
+ * (tx0,ty0,tx1,ty1), records [n,20] float32, sorted tile index [I] uint32,
+ * sorted surfel id [I] uint32 (ordered by tile, then depth key, then id),
+ * tile ranges [n_tiles,2] uint32 (start, end). */
+typedef struct {
+  size_t depth_keys, tile_counts, rects, records, sorted_tiles, sorted_ids, tile_ranges, total;
+} nx_ws_layout;
+int nx_workspace_layout(nx_ctx *ctx, int64_t n_surfels, const nx_camera *cams, int32_t n_cams,
+                        int64_t n_instances, nx_ws_layout *layout);
+
+/* Per-phase timing for diagnostics and benchmarks. While enabled, every
+ * kernel group a call launches (e.g. "raster_forward") is bracketed by two
+ * hipEvents recorded on the call's stream; nx_timing_get syncs on them and
+ * returns, for entry `index`, the phase name (static storage), the summed
+ * milliseconds and the number of launches since the last reset. It returns
+ * NX_ERR_INVALID when index is past the last entry. Not thread-safe. */
+int nx_timing_enable(nx_ctx *ctx, int enabled);
+int nx_timing_reset(nx_ctx *ctx);
+int nx_timing_get(nx_ctx *ctx, int32_t index, const char **name, double *total_ms, int64_t *launches);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *nx_last_error(void);
+
+/* ABI version (major*100 + minor). */
+int nx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NEXELS_H */

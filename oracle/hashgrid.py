@@ -49,13 +49,18 @@ def downweight(depth, level_scale, focal):
     return -torch.expm1(-y)
 
 
-def encode(x, depth, table, level_scales, focal):
+def encode(x, depth, table, level_scales, focal, cells=None):
     """Concatenation over levels of Delta_l * H_l(s_l x), shape [S, L*F].
 
     x [S,3] and depth [S] are float64 (differentiable); table [L,T,F] float64.
     Per level: p = s_l x, c0 = floor(p), fr = p - c0; each of the 8 cell
     corners c0 + b is hashed after MapPositive and weighted by
     prod_axis (b ? fr : 1 - fr).
+
+    cells [S,L,3] (optional, int) replaces floor(p) by a given lattice cell:
+    the same trilinear polynomial of that cell is evaluated at p (fr may
+    leave [0,1] by a rounding-sized amount). Used to evaluate a sample under
+    the cell decision another implementation took.
     """
     L, Tsz, F = table.shape
     log2_size = int(Tsz).bit_length() - 1
@@ -64,7 +69,10 @@ def encode(x, depth, table, level_scales, focal):
     wts = []
     for l in range(L):
         p = float(level_scales[l]) * x
-        c0 = torch.floor(p).detach()
+        if cells is None:
+            c0 = torch.floor(p).detach()
+        else:
+            c0 = torch.as_tensor(np.asarray(cells)[:, l, :], dtype=torch.float64)
         fr = p - c0
         c0i = c0.numpy().astype(np.int64)
         wl = []

@@ -7,13 +7,34 @@ converted exactly from their storage dtype to float64.
 """
 from __future__ import annotations
 
+import numpy as np
 import torch
 
 
-def mlp_forward(z, weights):
+def unpack_masks(words, hidden, n_hidden_layers):
+    """[S, n_hidden_layers*hidden/32] uint32 bit words -> list of [S, hidden] float64 0/1 masks."""
+    words = np.asarray(words).astype(np.uint32).reshape(words.shape[0], n_hidden_layers, hidden // 32)
+    bits = (words[:, :, :, None] >> np.arange(32, dtype=np.uint32)[None, None, None, :]) & 1
+    bits = bits.reshape(words.shape[0], n_hidden_layers, hidden)
+    return [torch.from_numpy(bits[:, i].astype(np.float64)) for i in range(n_hidden_layers)]
+
+
+def mlp_forward(z, weights, relu_masks=None):
+    """sigmoid(W_n ... ReLU(W_1 z)), no biases.
+
+    relu_masks (optional, per hidden layer [S, hidden] 0/1) replaces the ReLU
+    decision h > 0 by a given one: the layer output is pre * mask. At a
+    decision that differs from the natural one the pre-activation is within
+    rounding of 0, so the value changes by a rounding-sized amount while the
+    gradient follows the given branch."""
     h = z
     last = len(weights) - 1
     for i, w in enumerate(weights):
         h = h @ w.t()
-        h = torch.sigmoid(h) if i == last else torch.relu(h)
+        if i == last:
+            h = torch.sigmoid(h)
+        elif relu_masks is None:
+            h = torch.relu(h)
+        else:
+            h = h * relu_masks[i]
     return h

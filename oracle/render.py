@@ -25,10 +25,27 @@ every discrete choice (support test, alpha threshold, stop, top-K, hash
 cell) held at the value the forward took; tests pin them to central finite
 differences.
 
-Each pixel also reports the smallest relative margin of the decisions it
-took (alpha threshold and clamp, support box and near plane, the stop test,
-the K-th versus (K+1)-th weight). A pixel whose margin exceeds a small
-delta has decisions that FP32 rounding cannot flip.
+Each pixel also reports how robust its discrete decisions are: for every
+decision (alpha threshold and clamp, support box and near plane, the stop
+test, the K-th versus (K+1)-th weight, the sign of every hidden MLP
+pre-activation of its textured samples) the relative distance to the
+threshold is divided by an estimate of the relative error an FP32
+evaluation makes in that quantity, and the smallest ratio is returned. A
+pixel whose ratio is well above 1 has decisions FP32 rounding cannot flip.
+Error scales (relative worst-case bounds): u, v and t 3e-7 (a few FP32
+roundings of offsets from the projected centre); alpha 3e-7 + 4e-7 g E
+(E = |u|^2g1 + |v|^2g2 is the kernel exponent, g the larger gamma: the
+exponent inherits the relative error of u and v times 2g, plus the exp2
+rounding); transmittance and weights the sum of 1.2e-7 + e_alpha
+alpha / (1 - alpha) over the surfels composited so far (1 - alpha inherits
+alpha's absolute error); MLP pre-activations `mlp_rel_err` times
+sum_j |W_ij x_j| (a 64-term FP32 accumulation plus the feature errors). The ReLU
+decisions change gradients only (the forward is continuous in them), so
+they are reported separately as `mlp_margin`.
+
+force_cells pins the hash-grid lattice cell of each textured sample to the
+one another implementation reports, so that positional gradients are
+compared on the same branch of the piecewise-trilinear interpolation.
 """
 from __future__ import annotations
 
@@ -41,7 +58,7 @@ from .binning import bin_surfels
 from .constants import ALPHA_MAX, ALPHA_MIN, NEAR, SUPPORT, T_MIN
 from .geometry import camera_origin_and_rays, intersect, kernel, quat_columns
 from .hashgrid import encode
-from .mlp import mlp_forward
+from .mlp import mlp_forward, unpack_masks
 
 
 @dataclasses.dataclass
@@ -55,7 +72,8 @@ class OracleOutputs:
     t_final: np.ndarray  # [P]
     tex: np.ndarray      # [P,K,3]
     n_comp: np.ndarray   # [P] number of composited surfels
-    margin: np.ndarray   # [P] smallest relative decision margin
+    margin: np.ndarray   # [P] collection-pass decisions: smallest margin / FP32 error scale
+    mlp_margin: np.ndarray = None  # [P] MLP ReLU decisions of the textured samples, same units
     grads: dict | None = None
 
 
@@ -75,7 +93,8 @@ def render(scene, cam, grid, mlp, K, pixels=None, tiled=False, bins=None, **kw):
 
 
 def render_and_grad(scene, cam, grid, mlp, K, pixels=None, grad_image=None, grad_weights=None,
-                    grad_tex=None, tiled=False, bins=None, outer_pixels=2048, pair_budget=3_000_000):
+                    grad_tex=None, tiled=False, bins=None, outer_pixels=2048, pair_budget=3_000_000,
+                    force_cells=None, force_relu=None, mlp_rel_err=5e-6):
     """Render the given pixels (all by default) and optionally back-propagate.
 
     grad_image [P,3], grad_weights [P,K] and grad_tex [P,K,3] are upstream
@@ -85,6 +104,11 @@ def render_and_grad(scene, cam, grid, mlp, K, pixels=None, grad_image=None, grad
     table's shape) and mlp (list of [out,in]).
     tiled=True restricts each pixel's candidates to its tile list from the
     binning step (used to check that binning loses no surfel).
+    force_cells [P,K,L,3] (int, aligned with ``pixels``) fixes the hash-grid
+    cell per textured slot and level; force_relu [P,K,2*hidden/32] (uint32
+    bit words, layer 1 then layer 2) fixes the ReLU decisions per slot;
+    mlp_rel_err is the relative error scale of the MLP pre-activations used
+    for the decision margins.
     """
     need_grad = grad_image is not None or grad_weights is not None or grad_tex is not None
     W, H = cam.width, cam.height
@@ -111,6 +135,7 @@ def render_and_grad(scene, cam, grid, mlp, K, pixels=None, grad_image=None, grad
         "image": np.zeros((P, 3)), "plain": np.zeros((P, 3)), "ids": np.full((P, K), -1, dtype=np.int64),
         "weights": np.zeros((P, K)), "depths": np.zeros((P, K)), "t_final": np.ones(P),
         "tex": np.zeros((P, K, 3)), "n_comp": np.zeros(P, dtype=np.int64), "margin": np.full(P, np.inf),
+        "mlp_margin": np.full(P, np.inf),
     }
     if P == 0:
         return OracleOutputs(pixels=pixels, grads=_collect_grads(prm, table, weights) if need_grad else None, **out)
@@ -158,10 +183,13 @@ def render_and_grad(scene, cam, grid, mlp, K, pixels=None, grad_image=None, grad
         pp = np.concatenate(pair_p) if pair_p else np.zeros(0, dtype=np.int64)
         ss = np.concatenate(pair_s) if pair_s else np.zeros(0, dtype=np.int64)
 
-        res = _composite_chunk(pp, ss, Pc, o, d, prm, key_np, K, table, level_scales, cam.fx, weights)
+        fc = None if force_cells is None else np.asarray(force_cells)[sel]
+        fr = None if force_relu is None else np.asarray(force_relu)[sel]
+        res = _composite_chunk(pp, ss, Pc, o, d, prm, key_np, K, table, level_scales, cam.fx, weights, fc,
+                               mlp_rel_err, fr)
         for nm in ("image", "plain", "weights", "depths", "t_final", "tex"):
             out[nm][sel] = res[nm].detach().numpy()
-        for nm in ("ids", "n_comp", "margin"):
+        for nm in ("ids", "n_comp", "margin", "mlp_margin"):
             out[nm][sel] = res[nm]
 
         if need_grad:
@@ -189,7 +217,8 @@ def _collect_grads(prm, table, weights):
     return g
 
 
-def _composite_chunk(pp, ss, Pc, o, d, prm, key_np, K, table, level_scales, focal, weights):
+def _composite_chunk(pp, ss, Pc, o, d, prm, key_np, K, table, level_scales, focal, weights, force_cells=None,
+                     mlp_rel_err=5e-6, force_relu=None):
     """Phase 2 for one chunk of pixels: exact decisions, compositing, texture."""
     E = pp.shape[0]
     order = np.lexsort((ss, key_np[ss].astype(np.float64), pp))
@@ -264,54 +293,88 @@ def _composite_chunk(pp, ss, Pc, o, d, prm, key_np, K, table, level_scales, foca
     # Texturing pass on the selected slots.
     rows, slots = np.nonzero(has)
     tex = torch.zeros(Pc, K, 3, dtype=torch.float64)
+    relu_margin = np.full(Pc, np.inf)
     if rows.shape[0] > 0:
         rt, stt = torch.from_numpy(rows), torch.from_numpy(slots)
         D = Dk[rt, stt]
         x = o + D.unsqueeze(1) * d[rt]
-        z = encode(x, D, table, level_scales, focal)
-        out = mlp_forward(z, weights)
+        cells = None if force_cells is None else force_cells[rows, slots]
+        z = encode(x, D, table, level_scales, focal, cells=cells)
+        masks = None
+        if force_relu is not None:
+            masks = unpack_masks(force_relu[rows, slots], weights[0].shape[0], len(weights) - 1)
+        out = mlp_forward(z, weights, relu_masks=masks)
         tex = tex.index_put((rt, stt), out)
+        with torch.no_grad():
+            sm = _relu_margins(z.detach(), [w.detach() for w in weights]) / mlp_rel_err
+        np.minimum.at(relu_margin, rows, sm)
     image = plain + (Wk.unsqueeze(-1) * tex).sum(dim=1)
 
+    E = (-2.0 * torch.log(G.detach().clamp_min(1e-300))).numpy()
+    gmax = prm["gammas"][st].detach().max(dim=1).values.numpy()
     margin = _margins(pp, col, Pc, M, s.numpy(), supp.numpy(), alpha.detach().numpy(), a_raw.detach().numpy(),
                       u.detach().numpy(), v.detach().numpy(), t.detach().numpy(), Ta.detach().numpy(),
-                      compn, wn, K)
+                      compn, wn, K, E, gmax)
     return {"image": image, "plain": plain, "weights": Wk, "depths": Dk, "t_final": t_final, "tex": tex,
-            "ids": Ik, "n_comp": n_comp, "margin": margin}
+            "ids": Ik, "n_comp": n_comp, "margin": margin, "mlp_margin": relu_margin}
 
 
-def _margins(pp, col, Pc, M, s, supp, alpha, a_raw, u, v, t, Ta, comp, w, K):
-    """Smallest relative margin of every decision each pixel took."""
+def _relu_margins(z, weights):
+    """Per sample: min over hidden units of |h_i| / sum_j |W_ij x_j| (inf if all inputs are 0)."""
+    m = torch.full((z.shape[0],), float("inf"), dtype=torch.float64)
+    h = z
+    for w in weights[:-1]:
+        pre = h @ w.t()
+        scale = h.abs() @ w.abs().t()
+        r = torch.where(scale > 0, pre.abs() / scale, torch.full_like(pre, float("inf")))
+        m = torch.minimum(m, r.min(dim=1).values)
+        h = torch.relu(pre)
+    return m.numpy()
+
+
+def _margins(pp, col, Pc, M, s, supp, alpha, a_raw, u, v, t, Ta, comp, w, K, E, gmax):
+    """Smallest (relative margin / FP32 relative error scale) over every decision of each pixel."""
     m = np.full(Pc, np.inf)
     considered = col < s[pp]
     big = np.inf
+    e_alpha = 3e-7 + 4e-7 * gmax * E
+    e_geo = 3e-7
     with np.errstate(divide="ignore", invalid="ignore"):
-        ma = np.where(considered & supp, np.abs(alpha - ALPHA_MIN) / ALPHA_MIN, big)
-        mc = np.where(considered & supp, np.abs(a_raw - ALPHA_MAX) / ALPHA_MAX, big)
+        ma = np.where(considered & supp, np.abs(alpha - ALPHA_MIN) / ALPHA_MIN / e_alpha, big)
+        mc = np.where(considered & supp, np.abs(a_raw - ALPHA_MAX) / ALPHA_MAX / e_alpha, big)
         matters = considered & (a_raw >= 0.5 * ALPHA_MIN)
-        ms = np.minimum(np.abs(np.abs(u) - SUPPORT), np.abs(np.abs(v) - SUPPORT)) / SUPPORT
-        mn = np.abs(t - NEAR) / NEAR
+        ms = np.minimum(np.abs(np.abs(u) - SUPPORT), np.abs(np.abs(v) - SUPPORT)) / SUPPORT / e_geo
+        mn = np.abs(t - NEAR) / NEAR / e_geo
         msn = np.where(matters, np.minimum(ms, mn), big)
     per_pair = np.minimum(np.minimum(ma, mc), msn)
     np.minimum.at(m, pp, per_pair)
+    # Transmittance error accumulated along each pixel's list (composited entries and the stop entry).
+    ea = np.zeros((Pc, M))
+    ea[pp, col] = np.where(supp, e_alpha, 0.0)
+    al = np.zeros((Pc, M))
+    al[pp, col] = np.where(supp, alpha, 0.0)
     rows = np.arange(Pc)
     stopped = s < M
+    incl = comp.copy()
+    incl[rows[stopped], s[stopped]] = True
+    step_err = np.where(incl, 1.2e-7 + ea * al / np.maximum(1.0 - al, 1e-12), 0.0)
+    e_T = np.cumsum(step_err, axis=1)
     if stopped.any():
         r = rows[stopped]
-        m[r] = np.minimum(m[r], (T_MIN - Ta[r, s[r]]) / T_MIN)
-    # last composited entry: its transmittance after compositing must stay >= T_MIN
+        m[r] = np.minimum(m[r], (T_MIN - Ta[r, s[r]]) / T_MIN / e_T[r, s[r]])
     lastc = np.where(comp, np.arange(M)[None, :], -1).max(axis=1)
     hasc = lastc >= 0
     if hasc.any():
         r = rows[hasc]
-        m[r] = np.minimum(m[r], (Ta[r, lastc[r]] - T_MIN) / T_MIN)
+        m[r] = np.minimum(m[r], (Ta[r, lastc[r]] - T_MIN) / T_MIN / e_T[r, lastc[r]])
     # K-th versus (K+1)-th weight
-    ws = np.sort(np.where(comp, w, -np.inf), axis=1)[:, ::-1]
     if M > K:
-        wk = ws[:, K - 1]
+        ws = np.sort(np.where(comp, w, -np.inf), axis=1)[:, ::-1]
+        wk = ws[:, K - 1] if K > 0 else np.full(Pc, np.inf)
         wk1 = ws[:, K]
-        ok = np.isfinite(wk1) & (wk > 0)
+        e_w = np.where(hasc, e_T[rows, np.maximum(lastc, 0)], 0.0) + np.max(np.where(comp, ea, 0.0), axis=1)
+        ok = np.isfinite(wk1) & (wk > 0) & (K > 0)
         with np.errstate(divide="ignore", invalid="ignore"):
-            mk = np.where(ok, (wk - wk1) / wk, np.inf)
+            mk = np.where(ok, (wk - wk1) / wk / np.maximum(e_w, 1e-12), np.inf)
         m = np.minimum(m, mk)
     return m

@@ -1,0 +1,15 @@
+"""MI355X (gfx950) implementation of the Nexels rendering path.
+
+Importing the package loads libnexels.so (built by
+``python paper_2512_13796_amd/build.py``) and raises ImportError if it is
+missing: there is no CPU or eager-PyTorch fallback.
+"""
+from . import _lib
+
+_lib.load()
+
+from .render import (Context, ForwardResult, RenderFunction, camera_struct, render,  # noqa: E402,F401
+                     render_backward, render_forward)
+
+__all__ = ["Context", "ForwardResult", "RenderFunction", "camera_struct", "render", "render_backward",
+           "render_forward"]

@@ -1,0 +1,525 @@
+// C ABI of libnexels: argument validation, workspace layout and the launch
+// sequence of the two rendering passes and their backward.
+#include <math.h>
+#include <stdio.h>
+
+#include <string>
+#include <vector>
+
+#include "nx_internal.h"
+
+struct nx_phase {
+  const char* name;
+  double ms;
+  int64_t launches;
+};
+
+struct nx_pending {
+  int phase;
+  hipEvent_t a, b;
+};
+
+struct nx_ctx {
+  int32_t K;
+  int32_t tile;
+  nx_dtype feat_dtype, mlp_dtype;
+  uint32_t* pinned;  // one host word for the instance-count readback
+  bool timing;
+  std::vector<nx_phase> phases;
+  std::vector<nx_pending> pending;
+  std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define NX_CHECK_HIP(expr)                                                                 \
+  do {                                                                                     \
+    hipError_t _e = (expr);                                                                \
+    if (_e != hipSuccess) return fail(NX_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  // N-part
+  size_t depth_keys, tile_counts, rects, records, sort_k, sort_v, sort_tk, sort_tv, offsets, scan_blocks;
+  // fixed-size parts
+  size_t tile_ranges, rec_grad, grad_depth;
+  // I-part
+  size_t hist, inst_tiles, inst_ids, inst_tmp_tiles, inst_tmp_ids;
+  size_t total;
+};
+
+Layout make_layout(int64_t n, int64_t n_pix, int K, int n_tiles, int64_t n_inst) {
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  const size_t nn = (size_t)(n > 0 ? n : 1);
+  L.depth_keys = take(4 * nn);
+  L.tile_counts = take(4 * nn);
+  L.rects = take(16 * nn);
+  L.records = take(sizeof(float) * nx::kRecFloats * nn);
+  L.sort_k = take(4 * nn);
+  L.sort_v = take(4 * nn);
+  L.sort_tk = take(4 * nn);
+  L.sort_tv = take(4 * nn);
+  L.offsets = take(4 * (nn + 1));
+  L.scan_blocks = take(4 * nx::scan_block_words((int64_t)nn));
+  L.tile_ranges = take(8 * (size_t)n_tiles);
+  L.rec_grad = take(sizeof(float) * nx::kRecGrad * nn);
+  L.grad_depth = take(sizeof(float) * (size_t)(n_pix * (K > 0 ? K : 1)));
+  const int64_t ni = n_inst > 0 ? n_inst : 1;
+  const int64_t hist_n = ni > (int64_t)nn ? ni : (int64_t)nn;
+  L.hist = take(4 * nx::radix_hist_words(hist_n));
+  L.inst_tiles = take(4 * (size_t)ni);
+  L.inst_ids = take(4 * (size_t)ni);
+  L.inst_tmp_tiles = take(4 * (size_t)ni);
+  L.inst_tmp_ids = take(4 * (size_t)ni);
+  L.total = o;
+  return L;
+}
+
+bool finite_d(double x) { return isfinite(x); }
+
+int check_ctx(const nx_ctx* ctx) {
+  if (!ctx) return fail(NX_ERR_INVALID, "ctx is NULL");
+  return NX_OK;
+}
+
+int check_camera(const nx_camera* cams, int32_t n_cams) {
+  if (!cams) return fail(NX_ERR_INVALID, "cams is NULL");
+  if (n_cams != 1) return fail(n_cams < 1 ? NX_ERR_INVALID : NX_ERR_UNSUPPORTED, "n_cams must be 1");
+  const nx_camera& c = cams[0];
+  if (c.width <= 0 || c.height <= 0) return fail(NX_ERR_INVALID, "camera width/height must be positive");
+  if ((int64_t)c.width * c.height > (int64_t)1 << 28) return fail(NX_ERR_UNSUPPORTED, "image larger than 2^28 px");
+  for (int i = 0; i < 12; ++i)
+    if (!finite_d(c.world_to_cam[i])) return fail(NX_ERR_INVALID, "camera matrix not finite");
+  if (!(c.fx > 0 && c.fy > 0 && finite_d(c.fx) && finite_d(c.fy) && finite_d(c.cx) && finite_d(c.cy)))
+    return fail(NX_ERR_INVALID, "camera intrinsics invalid");
+  if (!(c.near_z > 0 && finite_d(c.near_z))) return fail(NX_ERR_INVALID, "near_z must be positive");
+  return NX_OK;
+}
+
+int check_surfels(const nx_surfels* s) {
+  if (!s) return fail(NX_ERR_INVALID, "surfels is NULL");
+  if (s->n < 0) return fail(NX_ERR_INVALID, "negative surfel count");
+  if (s->n >= ((int64_t)1 << 31)) return fail(NX_ERR_UNSUPPORTED, "more than 2^31-1 surfels");
+  if (s->n > 0 && (!s->means || !s->quats || !s->scales || !s->opacities || !s->gammas || !s->colors))
+    return fail(NX_ERR_INVALID, "a surfel parameter pointer is NULL");
+  return NX_OK;
+}
+
+int check_grid_mlp(const nx_ctx* ctx, const nx_hashgrid* g, const nx_mlp* m) {
+  if (ctx->K == 0) return NX_OK;  // no texturing pass
+  if (!g || !m) return fail(NX_ERR_INVALID, "grid or mlp is NULL");
+  if (!g->table || !g->level_scales) return fail(NX_ERR_INVALID, "grid table or level_scales is NULL");
+  if (g->dtype != ctx->feat_dtype) return fail(NX_ERR_INVALID, "grid dtype differs from the context's feat_dtype");
+  if (g->feat != 2) return fail(NX_ERR_UNSUPPORTED, "only feat == 2 is supported");
+  if (g->levels < 1 || g->levels > 16) return fail(NX_ERR_UNSUPPORTED, "levels must be in [1, 16]");
+  if (g->log2_size < 4 || g->log2_size > 24) return fail(NX_ERR_UNSUPPORTED, "log2_size must be in [4, 24]");
+  for (int l = 0; l < g->levels; ++l)
+    if (!(g->level_scales[l] > 0.0f) || !isfinite(g->level_scales[l]))
+      return fail(NX_ERR_INVALID, "level scales must be positive and finite");
+  if (m->dtype != ctx->mlp_dtype) return fail(NX_ERR_INVALID, "mlp dtype differs from the context's mlp_dtype");
+  if (!m->w[0] || !m->w[1] || !m->w[2]) return fail(NX_ERR_INVALID, "an MLP weight pointer is NULL");
+  if (m->dims[0] != g->levels * g->feat) return fail(NX_ERR_INVALID, "mlp dims[0] must equal levels * feat");
+  if (m->dims[1] != m->dims[2] || (m->dims[1] != 64 && m->dims[1] != 128))
+    return fail(NX_ERR_UNSUPPORTED, "hidden widths must be equal and 64 or 128");
+  if (m->dims[3] != 3) return fail(NX_ERR_UNSUPPORTED, "the MLP head must have 3 outputs");
+  return NX_OK;
+}
+
+nx::CamDev make_cam(const nx_camera& c) {
+  nx::CamDev d;
+  for (int i = 0; i < 12; ++i) d.m[i] = c.world_to_cam[i];
+  d.fx = c.fx;
+  d.fy = c.fy;
+  d.cx = c.cx;
+  d.cy = c.cy;
+  d.near_z = c.near_z;
+  d.width = c.width;
+  d.height = c.height;
+  d.ntx = (c.width + nx::kTile - 1) / nx::kTile;
+  d.nty = (c.height + nx::kTile - 1) / nx::kTile;
+  return d;
+}
+
+nx::GridDev make_grid(const nx_camera& c, const nx_hashgrid* g) {
+  nx::GridDev d{};
+  const double* m = c.world_to_cam;
+  // camera centre in world: o = -R^T t
+  double o[3];
+  for (int k = 0; k < 3; ++k) o[k] = -(m[0 + k] * m[3] + m[4 + k] * m[7] + m[8 + k] * m[11]);
+  d.levels = g ? g->levels : 0;
+  d.log2_size = g ? g->log2_size : 0;
+  for (int l = 0; l < d.levels; ++l) {
+    const double s = g->level_scales[l];
+    d.lv[l].scale = g->level_scales[l];
+    for (int k = 0; k < 3; ++k) {
+      const double so = s * o[k];
+      const double fl = floor(so);
+      d.lv[l].oint[k] = (int)fl;
+      d.lv[l].ofrac[k] = (float)(so - fl);
+    }
+    const double r = c.fx / s;
+    d.lv[l].kappa = (float)(r * r / (2.0 * M_PI));
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) d.rot[3 * i + j] = (float)m[4 * j + i];
+  d.fx = (float)c.fx;
+  d.fy = (float)c.fy;
+  d.cx = (float)c.cx;
+  d.cy = (float)c.cy;
+  d.width = c.width;
+  d.height = c.height;
+  return d;
+}
+
+int tile_bits(int n_tiles) {
+  int b = 0;
+  while (b < 31 && ((int64_t)1 << b) < n_tiles) ++b;
+  return b;
+}
+
+hipEvent_t take_event(nx_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+int phase_index(nx_ctx* c, const char* name) {
+  for (size_t i = 0; i < c->phases.size(); ++i)
+    if (c->phases[i].name == name) return (int)i;
+  c->phases.push_back({name, 0.0, 0});
+  return (int)c->phases.size() - 1;
+}
+
+// Brackets the launches of one phase with events when timing is enabled.
+struct PhaseTimer {
+  nx_ctx* c;
+  hipStream_t s;
+  int phase = -1;
+  hipEvent_t a = nullptr;
+  PhaseTimer(nx_ctx* ctx, const char* name, hipStream_t stream) : c(ctx), s(stream) {
+    if (!c->timing) return;
+    a = take_event(c);
+    if (a && hipEventRecord(a, s) == hipSuccess) phase = phase_index(c, name);
+  }
+  ~PhaseTimer() {
+    if (phase < 0) return;
+    hipEvent_t b = take_event(c);
+    if (b && hipEventRecord(b, s) == hipSuccess) c->pending.push_back({phase, a, b});
+  }
+};
+
+template <typename T>
+T* at(void* base, size_t off) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off);
+}
+template <typename T>
+const T* at(const void* base, size_t off) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
+}
+
+}  // namespace
+
+extern "C" {
+
+int nx_version(void) { return 100; }
+
+const char* nx_last_error(void) { return g_last_error.c_str(); }
+
+int nx_create(nx_ctx** out, int32_t K, int32_t tile, nx_dtype feat_dtype, nx_dtype mlp_dtype) {
+  if (!out) return fail(NX_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!(K == 0 || K == 1 || K == 2 || K == 4 || K == 8 || K == 16))
+    return fail(K < 0 ? NX_ERR_INVALID : NX_ERR_UNSUPPORTED, "K must be one of 0, 1, 2, 4, 8, 16");
+  if (tile != 16) return fail(NX_ERR_UNSUPPORTED, "tile must be 16");
+  if (feat_dtype != NX_F32 && feat_dtype != NX_F16 && feat_dtype != NX_BF16)
+    return fail(NX_ERR_INVALID, "unknown feat_dtype");
+  if (mlp_dtype != NX_F32 && mlp_dtype != NX_BF16) return fail(NX_ERR_UNSUPPORTED, "mlp_dtype must be F32 or BF16");
+  nx_ctx* c = new nx_ctx();
+  c->K = K;
+  c->tile = tile;
+  c->feat_dtype = feat_dtype;
+  c->mlp_dtype = mlp_dtype;
+  c->pinned = nullptr;
+  c->timing = false;
+  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&c->pinned), sizeof(uint32_t) * 4, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(NX_ERR_HIP, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+  }
+  *out = c;
+  g_last_error.clear();
+  return NX_OK;
+}
+
+int nx_destroy(nx_ctx* ctx) {
+  if (!ctx) return NX_OK;
+  for (auto& p : ctx->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (auto e : ctx->pool) (void)hipEventDestroy(e);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  delete ctx;
+  return NX_OK;
+}
+
+int nx_timing_enable(nx_ctx* ctx, int enabled) {
+  int r;
+  if ((r = check_ctx(ctx)) != NX_OK) return r;
+  ctx->timing = enabled != 0;
+  return NX_OK;
+}
+
+static int drain_timing(nx_ctx* ctx) {
+  for (auto& p : ctx->pending) {
+    NX_CHECK_HIP(hipEventSynchronize(p.b));
+    float ms = 0.f;
+    NX_CHECK_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+    ctx->phases[p.phase].ms += ms;
+    ctx->phases[p.phase].launches += 1;
+    ctx->pool.push_back(p.a);
+    ctx->pool.push_back(p.b);
+  }
+  ctx->pending.clear();
+  return NX_OK;
+}
+
+int nx_timing_reset(nx_ctx* ctx) {
+  int r;
+  if ((r = check_ctx(ctx)) != NX_OK) return r;
+  if ((r = drain_timing(ctx)) != NX_OK) return r;
+  for (auto& p : ctx->phases) {
+    p.ms = 0.0;
+    p.launches = 0;
+  }
+  return NX_OK;
+}
+
+int nx_timing_get(nx_ctx* ctx, int32_t index, const char** name, double* total_ms, int64_t* launches) {
+  int r;
+  if ((r = check_ctx(ctx)) != NX_OK) return r;
+  if ((r = drain_timing(ctx)) != NX_OK) return r;
+  if (index < 0 || index >= (int32_t)ctx->phases.size()) return fail(NX_ERR_INVALID, "timing index out of range");
+  if (name) *name = ctx->phases[index].name;
+  if (total_ms) *total_ms = ctx->phases[index].ms;
+  if (launches) *launches = ctx->phases[index].launches;
+  return NX_OK;
+}
+
+int nx_workspace_size(nx_ctx* ctx, int64_t n_surfels, const nx_camera* cams, int32_t n_cams, int64_t max_instances,
+                      size_t* bytes) {
+  int r;
+  if ((r = check_ctx(ctx)) != NX_OK) return r;
+  if ((r = check_camera(cams, n_cams)) != NX_OK) return r;
+  if (!bytes) return fail(NX_ERR_INVALID, "bytes is NULL");
+  if (n_surfels < 0 || max_instances < 0) return fail(NX_ERR_INVALID, "negative size");
+  const nx::CamDev cd = make_cam(cams[0]);
+  const Layout L = make_layout(n_surfels, (int64_t)cd.width * cd.height, ctx->K, cd.ntx * cd.nty, max_instances);
+  *bytes = L.total;
+  return NX_OK;
+}
+
+int nx_workspace_layout(nx_ctx* ctx, int64_t n_surfels, const nx_camera* cams, int32_t n_cams, int64_t n_instances,
+                        nx_ws_layout* layout) {
+  int r;
+  if ((r = check_ctx(ctx)) != NX_OK) return r;
+  if ((r = check_camera(cams, n_cams)) != NX_OK) return r;
+  if (!layout) return fail(NX_ERR_INVALID, "layout is NULL");
+  if (n_surfels < 0 || n_instances < 0) return fail(NX_ERR_INVALID, "negative size");
+  const nx::CamDev cd = make_cam(cams[0]);
+  const Layout L = make_layout(n_surfels, (int64_t)cd.width * cd.height, ctx->K, cd.ntx * cd.nty, n_instances);
+  layout->depth_keys = L.depth_keys;
+  layout->tile_counts = L.tile_counts;
+  layout->rects = L.rects;
+  layout->records = L.records;
+  layout->sorted_tiles = L.inst_tiles;
+  layout->sorted_ids = L.inst_ids;
+  layout->tile_ranges = L.tile_ranges;
+  layout->total = L.total;
+  return NX_OK;
+}
+
+int nx_render_forward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* cams, int32_t n_cams,
+                      const nx_hashgrid* grid, const nx_mlp* mlp, nx_fwd_out* out, void* workspace,
+                      size_t workspace_bytes, size_t* workspace_required, void* stream) {
+  int r;
+  if ((r = check_ctx(ctx)) != NX_OK) return r;
+  if ((r = check_surfels(surfels)) != NX_OK) return r;
+  if ((r = check_camera(cams, n_cams)) != NX_OK) return r;
+  if ((r = check_grid_mlp(ctx, grid, mlp)) != NX_OK) return r;
+  if (!out || !out->image || !out->plain || !out->t_final || !out->n_iter)
+    return fail(NX_ERR_INVALID, "an output pointer is NULL");
+  if (ctx->K > 0 && (!out->ids || !out->weights || !out->depths || !out->tex))
+    return fail(NX_ERR_INVALID, "an output pointer is NULL");
+  const int K = ctx->K;
+  const nx::CamDev cd = make_cam(cams[0]);
+  const int n_tiles = cd.ntx * cd.nty;
+  const int64_t n = surfels->n;
+  const int64_t P = (int64_t)cd.width * cd.height;
+  const Layout L0 = make_layout(n, P, K, n_tiles, 0);
+  if (workspace_required) *workspace_required = L0.total;
+  if (!workspace || workspace_bytes < L0.total) {
+    if (!workspace_required) return fail(NX_ERR_INVALID, "workspace too small and workspace_required is NULL");
+    return fail(NX_ERR_WORKSPACE, "workspace too small");
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  NX_CHECK_HIP(hipGetLastError());
+  void* ws = workspace;
+
+  uint32_t* depth_keys = at<uint32_t>(ws, L0.depth_keys);
+  uint32_t* counts = at<uint32_t>(ws, L0.tile_counts);
+  int4* rects = at<int4>(ws, L0.rects);
+  float4* records = at<float4>(ws, L0.records);
+  {
+  PhaseTimer pt(ctx, "preprocess", s);
+  NX_CHECK_HIP(nx::launch_preprocess(surfels->means, surfels->quats, surfels->scales, surfels->opacities,
+                                     surfels->gammas, surfels->colors, n, cd, depth_keys, counts, rects, records, s));
+  }
+  uint32_t* sk = at<uint32_t>(ws, L0.sort_k);
+  uint32_t* sv = at<uint32_t>(ws, L0.sort_v);
+  uint32_t* offsets = at<uint32_t>(ws, L0.offsets);
+  if (n > 0) {
+    PhaseTimer pt(ctx, "depth_sort", s);
+    NX_CHECK_HIP(hipMemcpyAsync(sk, depth_keys, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    NX_CHECK_HIP(nx::launch_iota(sv, n, s));
+    // The I-part is not laid out yet: the histogram for the depth sort uses the
+    // instance area, which is at least as large as the N-sized histogram.
+    NX_CHECK_HIP(nx::radix_sort_pairs(sk, sv, at<uint32_t>(ws, L0.sort_tk), at<uint32_t>(ws, L0.sort_tv),
+                                      at<uint32_t>(ws, L0.hist), n, 32, s));
+  }
+  {
+    PhaseTimer pt(ctx, "instance_scan", s);
+    NX_CHECK_HIP(nx::launch_gather_scan(counts, sv, offsets, at<uint32_t>(ws, L0.scan_blocks), n, s));
+  }
+  NX_CHECK_HIP(hipMemcpyAsync(ctx->pinned, offsets + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  NX_CHECK_HIP(hipStreamSynchronize(s));
+  const int64_t n_inst = (int64_t)ctx->pinned[0];
+  const Layout L = make_layout(n, P, K, n_tiles, n_inst);
+  out->n_instances = n_inst;
+  if (workspace_required) *workspace_required = L.total;
+  if (workspace_bytes < L.total) return fail(NX_ERR_WORKSPACE, "workspace too small for the tile instances");
+
+  uint32_t* it = at<uint32_t>(ws, L.inst_tiles);
+  uint32_t* iid = at<uint32_t>(ws, L.inst_ids);
+  {
+    PhaseTimer pt(ctx, "duplicate", s);
+    NX_CHECK_HIP(nx::launch_duplicate(sv, offsets, rects, n, cd.ntx, it, iid, s));
+  }
+  {
+  PhaseTimer pt(ctx, "tile_sort", s);
+  NX_CHECK_HIP(nx::radix_sort_pairs(it, iid, at<uint32_t>(ws, L.inst_tmp_tiles), at<uint32_t>(ws, L.inst_tmp_ids),
+                                    at<uint32_t>(ws, L.hist), n_inst, tile_bits(n_tiles), s));
+  }
+  uint2* ranges = at<uint2>(ws, L.tile_ranges);
+  {
+    PhaseTimer pt(ctx, "tile_ranges", s);
+    NX_CHECK_HIP(nx::launch_tile_ranges(it, n_inst, ranges, n_tiles, s));
+  }
+  {
+  PhaseTimer pt(ctx, "raster_forward", s);
+  NX_CHECK_HIP(nx::launch_raster_forward(K, records, iid, ranges, cd, out->plain, out->ids, out->weights,
+                                         out->depths, out->t_final, out->n_iter, s));
+  }
+  nx::GridDev gd = make_grid(cams[0], grid);
+  nx::MlpDev md{};
+  if (K > 0) {
+    md.w[0] = mlp->w[0];
+    md.w[1] = mlp->w[1];
+    md.w[2] = mlp->w[2];
+    md.in_dim = mlp->dims[0];
+    md.hidden = mlp->dims[1];
+  }
+  {
+  PhaseTimer pt(ctx, "texture_forward", s);
+  NX_CHECK_HIP(nx::launch_texture_forward(K, ctx->feat_dtype, ctx->mlp_dtype, gd, K > 0 ? grid->table : nullptr, md,
+                                          out->ids, out->depths, out->weights, out->plain, out->tex, out->image,
+                                          out->cells, out->relu_masks, s));
+  }
+  g_last_error.clear();
+  return NX_OK;
+}
+
+int nx_render_backward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* cams, int32_t n_cams,
+                       const nx_hashgrid* grid, const nx_mlp* mlp, const nx_fwd_out* saved, const void* workspace,
+                       size_t workspace_bytes, const float* grad_image, const float* grad_weights,
+                       const float* grad_tex, const nx_grads* grads, void* stream) {
+  int r;
+  if ((r = check_ctx(ctx)) != NX_OK) return r;
+  if ((r = check_surfels(surfels)) != NX_OK) return r;
+  if ((r = check_camera(cams, n_cams)) != NX_OK) return r;
+  if ((r = check_grid_mlp(ctx, grid, mlp)) != NX_OK) return r;
+  if (!saved || !saved->plain || !saved->n_iter) return fail(NX_ERR_INVALID, "saved forward outputs are NULL");
+  if (ctx->K > 0 && (!saved->ids || !saved->weights || !saved->depths || !saved->tex))
+    return fail(NX_ERR_INVALID, "saved forward outputs are NULL");
+  if (!grad_image) return fail(NX_ERR_INVALID, "grad_image is NULL");
+  if (!grads) return fail(NX_ERR_INVALID, "grads is NULL");
+  if (ctx->K > 0 && mlp->dims[1] != 64) return fail(NX_ERR_UNSUPPORTED, "backward supports hidden width 64");
+  const int K = ctx->K;
+  const nx::CamDev cd = make_cam(cams[0]);
+  const int n_tiles = cd.ntx * cd.nty;
+  const int64_t n = surfels->n;
+  const int64_t P = (int64_t)cd.width * cd.height;
+  if (saved->n_instances < 0) return fail(NX_ERR_INVALID, "saved n_instances is negative");
+  const Layout L = make_layout(n, P, K, n_tiles, saved->n_instances);
+  if (!workspace || workspace_bytes < L.total) return fail(NX_ERR_INVALID, "workspace does not match the forward");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  NX_CHECK_HIP(hipGetLastError());
+  void* ws = const_cast<void*>(workspace);
+  float* rec_grad = at<float>(ws, L.rec_grad);
+  float* gdepth = at<float>(ws, L.grad_depth);
+  {
+    PhaseTimer pt(ctx, "zero_record_grads", s);
+    NX_CHECK_HIP(nx::launch_fill_f32(rec_grad, 0.0f, (int64_t)nx::kRecGrad * n, s));
+  }
+  if (K > 0) {
+    nx::GridDev gd = make_grid(cams[0], grid);
+    nx::MlpDev md{};
+    md.w[0] = mlp->w[0];
+    md.w[1] = mlp->w[1];
+    md.w[2] = mlp->w[2];
+    md.in_dim = mlp->dims[0];
+    md.hidden = mlp->dims[1];
+    PhaseTimer pt(ctx, "texture_backward", s);
+    NX_CHECK_HIP(nx::launch_texture_backward(K, ctx->feat_dtype, ctx->mlp_dtype, gd, grid->table, md, saved->ids,
+                                             saved->depths, saved->weights, saved->tex, grad_image, grad_tex,
+                                             grads->table, grads->mlp[0], grads->mlp[1], grads->mlp[2], gdepth, s));
+  }
+  {
+  PhaseTimer pt(ctx, "raster_backward", s);
+  NX_CHECK_HIP(nx::launch_raster_backward(K, at<float4>(ws, L.records), at<uint32_t>(ws, L.inst_ids),
+                                          at<uint2>(ws, L.tile_ranges), cd, saved->plain, saved->ids, saved->weights,
+                                          saved->tex, saved->n_iter, grad_image, grad_weights,
+                                          K > 0 ? gdepth : nullptr, rec_grad, s));
+  }
+  {
+  PhaseTimer pt(ctx, "preprocess_backward", s);
+  NX_CHECK_HIP(nx::launch_preprocess_backward(surfels->means, surfels->quats, surfels->scales, n, cd,
+                                              at<uint32_t>(ws, L.tile_counts), rec_grad, grads->means, grads->quats,
+                                              grads->scales, grads->opacities, grads->gammas, grads->colors, s));
+  }
+  g_last_error.clear();
+  return NX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+// Internal declarations shared by the HIP translation units of libnexels.
+// Device helpers live here; every kernel is launched through a host
+// function declared below so that the C-ABI layer stays free of kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nexels.h"
+
+namespace nx {
+
+// Constants of the method as this library reads them (the paper builds on
+// the 3D Gaussian splatting rasteriser and leaves them implicit).
+constexpr float kAlphaMin = 1.0f / 255.0f;   // skip intersections below this alpha
+constexpr float kAlphaMax = 0.99f;           // alpha clamp
+constexpr float kTMin = 1e-4f;               // stop before T would fall below this
+constexpr float kSupport = 3.0f;             // hard kernel support |u|,|v| <= 3
+constexpr int kTile = 16;                    // screen tile edge in pixels
+constexpr double kMarginPx = 1.0;            // bounding-box margin for binning
+constexpr uint32_t kPrime1 = 2654435761u;    // spatial hash primes (Instant-NGP)
+constexpr uint32_t kPrime2 = 805459861u;
+
+// Per-surfel record consumed by the collection pass: 5 float4.
+//  [0] mx_int, my_int, hx, hy   pixel position of the projected centre split
+//                               into an integer part and hx = 0.5 - frac
+//  [1] p1x, p1y, p2x, p2y       numerators of u and v per pixel offset
+//  [2] qx, qy, mz, opacity      denominator slope, centre depth, opacity
+//  [3] gamma1, gamma2, r, g     kernel exponents and colour
+//  [4] b, pad, pad, pad
+// For a pixel offset (dx, dy) = (px + 0.5 - m_x, py + 0.5 - m_y):
+//   den = 1 + dx qx + dy qy,  t = mz / den,
+//   u = (dx p1x + dy p1y) / den,  v = (dx p2x + dy p2y) / den.
+constexpr int kRecF4 = 5;
+constexpr int kRecFloats = 4 * kRecF4;
+// Record-gradient slots (float32, per surfel): d/d of
+//   0 m_x, 1 m_y, 2 p1x, 3 p1y, 4 p2x, 5 p2y, 6 qx, 7 qy, 8 mz,
+//   9 opacity, 10 gamma1, 11 gamma2, 12 r, 13 g, 14 b
+constexpr int kRecGrad = 16;
+
+struct CamDev {
+  double m[12];
+  double fx, fy, cx, cy, near_z;
+  int width, height, ntx, nty;
+};
+
+struct GridLevel {
+  float scale;      // s_l
+  float ofrac[3];   // frac(s_l * o): camera origin in level cells, fractional part
+  int oint[3];      // floor(s_l * o)
+  float kappa;      // (f / s_l)^2 / (2 pi), so Delta = -expm1(-kappa / D^2)
+};
+
+struct GridDev {
+  GridLevel lv[16];
+  int levels, log2_size;
+  float rot[9];     // camera-to-world rotation (R^T), row-major
+  float fx, fy, cx, cy;
+  int width, height;
+};
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_preprocess(const float* means, const float* quats, const float* scales, const float* opac,
+                             const float* gammas, const float* colors, int64_t n, const CamDev& cam,
+                             uint32_t* depth_keys, uint32_t* tile_counts, int4* rects, float4* records,
+                             hipStream_t s);
+
+hipError_t launch_preprocess_backward(const float* means, const float* quats, const float* scales,
+                                      int64_t n, const CamDev& cam, const uint32_t* tile_counts,
+                                      const float* rec_grad, float* g_means, float* g_quats, float* g_scales,
+                                      float* g_opac, float* g_gammas, float* g_colors, hipStream_t s);
+
+// Stable LSD radix sort of (key, value) pairs over bits [0, end_bit).
+// keys/vals hold the input and receive the output; tmp_* are scratch of the
+// same size; hist needs radix_hist_words(n) uint32 words.
+size_t radix_hist_words(int64_t n);
+hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals,
+                            uint32_t* hist, int64_t n, int end_bit, hipStream_t s);
+
+hipError_t launch_iota(uint32_t* out, int64_t n, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* out, uint32_t value, int64_t n, hipStream_t s);
+hipError_t launch_fill_f32(float* out, float value, int64_t n, hipStream_t s);
+// offsets[i] = exclusive prefix sum of counts[order[i]]; offsets[n] = total.
+hipError_t launch_gather_scan(const uint32_t* counts, const uint32_t* order, uint32_t* offsets,
+                              uint32_t* block_sums, int64_t n, hipStream_t s);
+size_t scan_block_words(int64_t n);
+hipError_t launch_duplicate(const uint32_t* order, const uint32_t* offsets, const int4* rects, int64_t n,
+                            int ntx, uint32_t* tile_keys, uint32_t* ids, hipStream_t s);
+hipError_t launch_tile_ranges(const uint32_t* tile_keys, int64_t n_inst, uint2* ranges, int n_tiles,
+                              hipStream_t s);
+
+hipError_t launch_raster_forward(int K, const float4* records, const uint32_t* sorted_ids, const uint2* ranges,
+                                 const CamDev& cam, float* plain, int32_t* ids, float* weights, float* depths,
+                                 float* t_final, uint32_t* n_iter, hipStream_t s);
+
+hipError_t launch_raster_backward(int K, const float4* records, const uint32_t* sorted_ids, const uint2* ranges,
+                                  const CamDev& cam, const float* plain, const int32_t* ids,
+                                  const float* weights, const float* tex, const uint32_t* n_iter,
+                                  const float* grad_image, const float* grad_weights, const float* grad_depth,
+                                  float* rec_grad, hipStream_t s);
+
+struct MlpDev {
+  const void* w[3];
+  int in_dim, hidden;
+};
+
+hipError_t launch_texture_forward(int K, int feat_dtype, int mlp_dtype, const GridDev& grid, const void* table,
+                                  const MlpDev& mlp, const int32_t* ids, const float* depths,
+                                  const float* weights, const float* plain, float* tex, float* image,
+                                  int32_t* cells, uint32_t* relu_masks, hipStream_t s);
+
+hipError_t launch_texture_backward(int K, int feat_dtype, int mlp_dtype, const GridDev& grid, const void* table,
+                                   const MlpDev& mlp, const int32_t* ids, const float* depths,
+                                   const float* weights, const float* tex, const float* grad_image,
+                                   const float* grad_tex, float* g_table, float* g_mlp0, float* g_mlp1,
+                                   float* g_mlp2, float* grad_depth, hipStream_t s);
+
+}  // namespace nx

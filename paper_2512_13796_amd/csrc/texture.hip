@@ -1,0 +1,857 @@
+// Texturing pass (forward) and its backward.
+//
+// Paper: Rendering, Texturing Pass and eq. texture: for every selected slot
+// x = o + D d, Tex = G(Delta * H(x)); eq. final: C = N + sum_j W_j Tex_j.
+// Hash grid (Preliminaries, Instant-NGP; supplementary Implementation
+// Details): per level l the point s_l x is interpolated trilinearly from the
+// 8 hashed cell corners (MapPositive on the integer corner coordinates, then
+// XOR with the primes 1, 2654435761, 805459861, masked to the table size),
+// scaled by Delta_l = 1 - exp(-(f / (s_l D))^2 / (2 pi)) (eq. downweighting).
+// The sample position gets a gradient through the interpolation
+// (supplementary, Other details). MLP: hidden layers without bias, ReLU; the
+// RGB head uses a sigmoid.
+//
+// Work split: one wavefront handles 16 samples at a time. Lane (g, c), with
+// g = lane / 16 and c = lane % 16, owns sample c and the four levels
+// {2g, 2g+1, 8+2g, 9+2g}; its eight features are exactly the K-slice a 16x16
+// matrix-core tile wants in that lane, so the MLP runs on the features in
+// registers with no LDS round trip. The MLP is evaluated transposed
+// (hidden x samples): each layer's output tile is already laid out as the
+// next layer's B operand once its K index is permuted, and the weight
+// operands are staged in LDS in the matching permuted order.
+//   BF16 form: v_mfma_f32_16x16x32_bf16 (FP32 accumulate), activations
+//              rounded to BF16 between layers.
+//   FP32 form: v_mfma_f32_16x16x4_f32 (full FP32).
+// The backward recomputes the features and the MLP, back-propagates through
+// the MLP with the transposed weights, forms the weight gradients with a
+// per-wave LDS transpose (samples become the K index), accumulates them in
+// LDS per workgroup and adds them to global memory once, and scatters the
+// hash-grid gradient with FP32 atomics.
+#include <hip/hip_fp16.h>
+#include <math.h>
+
+#include "nx_internal.h"
+
+namespace nx {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef short s8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTexThreads = 256;
+constexpr int kWaves = kTexThreads / 64;
+constexpr int kInPad = 32;
+constexpr float kInv2Pi = 0.15915494309189533577f;
+
+// float -> bfloat16 bits, round to nearest even (finite inputs).
+__device__ __forceinline__ short f2bf(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint32_t b16) { return __uint_as_float(b16 << 16); }
+
+template <int TDT>
+__device__ __forceinline__ float2 load_pair(const void* table, uint32_t idx) {
+  if constexpr (TDT == NX_F32) {
+    return reinterpret_cast<const float2*>(table)[idx];
+  } else {
+    const uint32_t b = reinterpret_cast<const uint32_t*>(table)[idx];
+    if constexpr (TDT == NX_F16) {
+      return make_float2(__half2float(__ushort_as_half((unsigned short)(b & 0xFFFFu))),
+                         __half2float(__ushort_as_half((unsigned short)(b >> 16))));
+    } else {
+      return make_float2(bf2f(b & 0xFFFFu), bf2f(b >> 16));
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t map_positive(int z) { return z > 0 ? (uint32_t)(2 * z - 1) : (uint32_t)(-2 * z); }
+
+// Feature index (0..31) held by lane group g in element e of a layer-1 operand.
+__device__ __forceinline__ int feat_index(int g, int e) { return e < 4 ? 4 * g + e : 16 + 4 * g + (e - 4); }
+// Hidden index held by lane group g in element e of K-chunk h (BF16 form).
+__device__ __forceinline__ int hid_index(int h, int g, int e) { return 16 * (2 * h + (e >> 2)) + 4 * g + (e & 3); }
+// Level handled by lane group g in slot i (0..3): levels {2g, 2g+1, 8+2g, 9+2g}.
+__device__ __forceinline__ int lane_level(int g, int i) { return (i < 2 ? 2 * g : 8 + 2 * g) + (i & 1); }
+
+__device__ __forceinline__ f4 mfma_bf16_k32(s8 a, s8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0,
+                                                 0);
+}
+__device__ __forceinline__ f4 mfma_bf16_k16(s4 a, s4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma_f32_k4(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <bool BF>
+__device__ __forceinline__ float load_w(const void* w, int idx) {
+  if constexpr (BF) {
+    return bf2f(reinterpret_cast<const unsigned short*>(w)[idx]);
+  } else {
+    return reinterpret_cast<const float*>(w)[idx];
+  }
+}
+
+// ------------------------------------------------------------------ weights in LDS
+// Operand slots. BF16 form: a slot is 64 lanes x 8 bf16 (one 16x16x32 A
+// operand). FP32 form: a slot is 64 lanes x 1 float (one 16x16x4 A operand).
+template <bool BF, int HID>
+struct WLayout {
+  static constexpr int MT = HID / 16;
+  static constexpr int HT = HID / 32;
+  // forward
+  static constexpr int nA1 = BF ? MT : MT * 8;
+  static constexpr int nA2 = BF ? MT * HT : MT * MT * 4;
+  static constexpr int nA3 = BF ? HT : MT * 4;
+  // backward (transposed)
+  static constexpr int nA3T = BF ? MT : MT * 4;
+  static constexpr int nA2T = BF ? MT * HT : MT * MT * 4;
+  static constexpr int nA1T = BF ? 2 * HT : 2 * MT * 4;
+  static constexpr int oA1 = 0, oA2 = oA1 + nA1, oA3 = oA2 + nA2;
+  static constexpr int nFwd = oA3 + nA3;
+  static constexpr int oA3T = nFwd, oA2T = oA3T + nA3T, oA1T = oA2T + nA2T;
+  static constexpr int nAll = oA1T + nA1T;
+  static constexpr int slot_bytes = BF ? 64 * 16 : 64 * 4;
+};
+
+// Value of element e of lane (g, c) in operand slot `slot`.
+template <bool BF, int HID>
+__device__ float weight_operand(int slot, int g, int c, int e, const void* w1, const void* w2, const void* w3,
+                                int in_dim) {
+  using LY = WLayout<BF, HID>;
+  constexpr int MT = LY::MT;
+  if constexpr (BF) {
+    if (slot < LY::oA2) {  // A1[mt]
+      const int mt = slot - LY::oA1, f = feat_index(g, e);
+      return f < in_dim ? load_w<BF>(w1, (16 * mt + c) * in_dim + f) : 0.f;
+    } else if (slot < LY::oA3) {  // A2[mt][h]
+      const int q = slot - LY::oA2, mt = q / LY::HT, h = q % LY::HT;
+      return load_w<BF>(w2, (16 * mt + c) * HID + hid_index(h, g, e));
+    } else if (slot < LY::oA3T) {  // A3[h]
+      const int h = slot - LY::oA3;
+      return c < 3 ? load_w<BF>(w3, c * HID + hid_index(h, g, e)) : 0.f;
+    } else if (slot < LY::oA2T) {  // A3T[mt]
+      const int mt = slot - LY::oA3T;
+      return (g == 0 && e < 3) ? load_w<BF>(w3, e * HID + 16 * mt + c) : 0.f;
+    } else if (slot < LY::oA1T) {  // A2T[mt][h]
+      const int q = slot - LY::oA2T, mt = q / LY::HT, h = q % LY::HT;
+      return load_w<BF>(w2, hid_index(h, g, e) * HID + 16 * mt + c);
+    } else {  // A1T[mz][h]
+      const int q = slot - LY::oA1T, mz = q / LY::HT, h = q % LY::HT;
+      const int f = 16 * mz + c;
+      return f < in_dim ? load_w<BF>(w1, hid_index(h, g, e) * in_dim + f) : 0.f;
+    }
+  } else {
+    if (slot < LY::oA2) {  // A1[mt][ks]
+      const int q = slot - LY::oA1, mt = q / 8, ks = q % 8, f = feat_index(g, ks);
+      return f < in_dim ? load_w<BF>(w1, (16 * mt + c) * in_dim + f) : 0.f;
+    } else if (slot < LY::oA3) {  // A2[mt][mi][r]
+      const int q = slot - LY::oA2, mt = q / (MT * 4), mi = (q / 4) % MT, r = q % 4;
+      return load_w<BF>(w2, (16 * mt + c) * HID + 16 * mi + 4 * g + r);
+    } else if (slot < LY::oA3T) {  // A3[mi][r]
+      const int q = slot - LY::oA3, mi = q / 4, r = q % 4;
+      return c < 3 ? load_w<BF>(w3, c * HID + 16 * mi + 4 * g + r) : 0.f;
+    } else if (slot < LY::oA2T) {  // A3T[mt][r]
+      const int q = slot - LY::oA3T, mt = q / 4, r = q % 4, o = 4 * g + r;
+      return o < 3 ? load_w<BF>(w3, o * HID + 16 * mt + c) : 0.f;
+    } else if (slot < LY::oA1T) {  // A2T[mt][mi][r]
+      const int q = slot - LY::oA2T, mt = q / (MT * 4), mi = (q / 4) % MT, r = q % 4;
+      return load_w<BF>(w2, (16 * mi + 4 * g + r) * HID + 16 * mt + c);
+    } else {  // A1T[mz][mi][r]
+      const int q = slot - LY::oA1T, mz = q / (MT * 4), mi = (q / 4) % MT, r = q % 4;
+      const int f = 16 * mz + c;
+      return f < in_dim ? load_w<BF>(w1, (16 * mi + 4 * g + r) * in_dim + f) : 0.f;
+    }
+  }
+}
+
+template <bool BF, int HID>
+__device__ void stage_weights(unsigned char* lds, int n_slots, const void* w1, const void* w2, const void* w3,
+                              int in_dim) {
+  constexpr int per = BF ? 8 : 1;
+  const int total = n_slots * 64 * per;
+  for (int i = threadIdx.x; i < total; i += kTexThreads) {
+    const int slot = i / (64 * per);
+    const int lane = (i / per) % 64;
+    const int e = i % per;
+    const float v = weight_operand<BF, HID>(slot, lane >> 4, lane & 15, e, w1, w2, w3, in_dim);
+    if constexpr (BF) {
+      reinterpret_cast<short*>(lds)[i] = f2bf(v);
+    } else {
+      reinterpret_cast<float*>(lds)[i] = v;
+    }
+  }
+}
+
+template <bool BF>
+struct Operand;
+template <>
+struct Operand<true> {
+  static __device__ __forceinline__ s8 get(const unsigned char* lds, int slot, int lane) {
+    return reinterpret_cast<const s8*>(lds)[slot * 64 + lane];
+  }
+};
+template <>
+struct Operand<false> {
+  static __device__ __forceinline__ float get(const unsigned char* lds, int slot, int lane) {
+    return reinterpret_cast<const float*>(lds)[slot * 64 + lane];
+  }
+};
+
+__device__ __forceinline__ s8 pack8(const float v[8]) {
+  s8 r;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) r[e] = f2bf(v[e]);
+  return r;
+}
+__device__ __forceinline__ s8 pack_tiles(f4 a, f4 b) {
+  s8 r;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    r[e] = f2bf(a[e]);
+    r[4 + e] = f2bf(b[e]);
+  }
+  return r;
+}
+__device__ __forceinline__ f4 relu4(f4 x) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) x[e] = fmaxf(x[e], 0.0f);
+  return x;
+}
+
+// MLP forward for 16 samples: z[8] are this lane's features; h1/h2 receive
+// the post-ReLU hidden tiles (rows 16 mt + 4 g + r); returns the head tile
+// (rows 4 g + r; logits in rows 0..2 of lane group 0).
+template <bool BF, int HID>
+__device__ __forceinline__ f4 mlp_forward(const unsigned char* lds, int lane, const float z[8], f4* h1, f4* h2) {
+  using LY = WLayout<BF, HID>;
+  constexpr int MT = LY::MT;
+  const f4 zero = {0.f, 0.f, 0.f, 0.f};
+  if constexpr (BF) {
+    constexpr int HT = LY::HT;
+    const s8 b0 = pack8(z);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) h1[mt] = relu4(mfma_bf16_k32(Operand<true>::get(lds, LY::oA1 + mt, lane), b0, zero));
+    s8 b1[HT];
+#pragma unroll
+    for (int h = 0; h < HT; ++h) b1[h] = pack_tiles(h1[2 * h], h1[2 * h + 1]);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      f4 acc = zero;
+#pragma unroll
+      for (int h = 0; h < HT; ++h) acc = mfma_bf16_k32(Operand<true>::get(lds, LY::oA2 + mt * HT + h, lane), b1[h], acc);
+      h2[mt] = relu4(acc);
+    }
+    s8 b2[HT];
+#pragma unroll
+    for (int h = 0; h < HT; ++h) b2[h] = pack_tiles(h2[2 * h], h2[2 * h + 1]);
+    f4 o = zero;
+#pragma unroll
+    for (int h = 0; h < HT; ++h) o = mfma_bf16_k32(Operand<true>::get(lds, LY::oA3 + h, lane), b2[h], o);
+    return o;
+  } else {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      f4 acc = zero;
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks) acc = mfma_f32_k4(Operand<false>::get(lds, LY::oA1 + mt * 8 + ks, lane), z[ks], acc);
+      h1[mt] = relu4(acc);
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      f4 acc = zero;
+#pragma unroll
+      for (int mi = 0; mi < MT; ++mi)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          acc = mfma_f32_k4(Operand<false>::get(lds, LY::oA2 + (mt * MT + mi) * 4 + r, lane), h1[mi][r], acc);
+      h2[mt] = relu4(acc);
+    }
+    f4 o = zero;
+#pragma unroll
+    for (int mi = 0; mi < MT; ++mi)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) o = mfma_f32_k4(Operand<false>::get(lds, LY::oA3 + mi * 4 + r, lane), h2[mi][r], o);
+    return o;
+  }
+}
+
+struct SampleInfo {
+  int64_t s, p;
+  bool valid, has;
+  float D, W;
+  float dx, dy, dz;  // world ray direction
+};
+
+__device__ __forceinline__ SampleInfo sample_info(const GridDev& gd, int K, int log2K, int64_t n_samples, int64_t s,
+                                                  const int32_t* ids, const float* depths, const float* weights) {
+  SampleInfo si;
+  si.s = s;
+  si.valid = s < n_samples;
+  si.p = si.valid ? (s >> log2K) : 0;
+  const int id = si.valid ? ids[s] : -1;
+  si.has = id >= 0;
+  si.D = si.has ? depths[s] : 1.0f;
+  si.W = si.has ? weights[s] : 0.0f;
+  const int px = (int)(si.p % gd.width), py = (int)(si.p / gd.width);
+  const float cx = ((float)px + 0.5f - gd.cx) / gd.fx;
+  const float cy = ((float)py + 0.5f - gd.cy) / gd.fy;
+  si.dx = gd.rot[0] * cx + gd.rot[1] * cy + gd.rot[2];
+  si.dy = gd.rot[3] * cx + gd.rot[4] * cy + gd.rot[5];
+  si.dz = gd.rot[6] * cx + gd.rot[7] * cy + gd.rot[8];
+  return si;
+}
+
+struct LevelGeom {
+  int cx, cy, cz;  // lattice cell floor(s_l x)
+  float frx, fry, frz;
+  uint32_t hx[2], hy[2], hz[2];  // hashed corner coordinates per axis (before XOR)
+  float delta, expo;             // Delta_l and exp(-kappa/D^2) = 1 - Delta_l
+};
+
+__device__ __forceinline__ LevelGeom level_geom(const GridLevel& L, const SampleInfo& si) {
+  LevelGeom g;
+  const float sD = L.scale * si.D;
+  const float Px = fmaf(sD, si.dx, L.ofrac[0]);
+  const float Py = fmaf(sD, si.dy, L.ofrac[1]);
+  const float Pz = fmaf(sD, si.dz, L.ofrac[2]);
+  const float fx = floorf(Px), fy = floorf(Py), fz = floorf(Pz);
+  g.frx = Px - fx;
+  g.fry = Py - fy;
+  g.frz = Pz - fz;
+  const int cx = L.oint[0] + (int)fx, cy = L.oint[1] + (int)fy, cz = L.oint[2] + (int)fz;
+  g.cx = cx;
+  g.cy = cy;
+  g.cz = cz;
+  g.hx[0] = map_positive(cx);
+  g.hx[1] = map_positive(cx + 1);
+  g.hy[0] = map_positive(cy) * kPrime1;
+  g.hy[1] = map_positive(cy + 1) * kPrime1;
+  g.hz[0] = map_positive(cz) * kPrime2;
+  g.hz[1] = map_positive(cz + 1) * kPrime2;
+  const float y = L.kappa / (si.D * si.D);
+  g.delta = -expm1f(-y);
+  g.expo = 1.0f - g.delta;
+  return g;
+}
+
+// Interpolated (un-scaled) features of one level.
+template <int TDT>
+__device__ __forceinline__ float2 level_feature(const void* table, uint32_t base, uint32_t mask, const LevelGeom& g) {
+  float f0 = 0.f, f1 = 0.f;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
+    const uint32_t h = (g.hx[bx] ^ g.hy[by] ^ g.hz[bz]) & mask;
+    const float w = (bx ? g.frx : 1.f - g.frx) * (by ? g.fry : 1.f - g.fry) * (bz ? g.frz : 1.f - g.frz);
+    const float2 th = load_pair<TDT>(table, base + h);
+    f0 = fmaf(w, th.x, f0);
+    f1 = fmaf(w, th.y, f1);
+  }
+  return make_float2(f0, f1);
+}
+
+template <int TDT, bool BF, int HID>
+__global__ __launch_bounds__(kTexThreads) void texture_forward_kernel(GridDev gd, const void* __restrict__ table,
+                                                                      const void* w1, const void* w2, const void* w3,
+                                                                      int in_dim, int K, int log2K, int64_t n_samples,
+                                                                      const int32_t* __restrict__ ids,
+                                                                      const float* __restrict__ depths,
+                                                                      const float* __restrict__ weights,
+                                                                      const float* __restrict__ plain,
+                                                                      float* __restrict__ tex,
+                                                                      float* __restrict__ image,
+                                                                      int32_t* __restrict__ cells,
+                                                                      uint32_t* __restrict__ relu_masks) {
+  using LY = WLayout<BF, HID>;
+  constexpr int MT = LY::MT;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[LY::nFwd * LY::slot_bytes];
+  stage_weights<BF, HID>(lds, LY::nFwd, w1, w2, w3, in_dim);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, c = lane & 15;
+  const uint32_t mask = (1u << gd.log2_size) - 1u;
+  const int64_t n_blk = (n_samples + 15) / 16;
+  for (int64_t blk = (int64_t)blockIdx.x * kWaves + wave; blk < n_blk; blk += (int64_t)gridDim.x * kWaves) {
+    const SampleInfo si = sample_info(gd, K, log2K, n_samples, blk * 16 + c, ids, depths, weights);
+    float z[8];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int l = lane_level(g, i);
+      float2 f = make_float2(0.f, 0.f);
+      if (si.has && l < gd.levels) {
+        const LevelGeom lg = level_geom(gd.lv[l], si);
+        f = level_feature<TDT>(table, (uint32_t)l << gd.log2_size, mask, lg);
+        f.x *= lg.delta;
+        f.y *= lg.delta;
+        if (cells) {
+          int32_t* cp = cells + (si.s * gd.levels + l) * 3;
+          cp[0] = lg.cx;
+          cp[1] = lg.cy;
+          cp[2] = lg.cz;
+        }
+      }
+      z[2 * i] = f.x;
+      z[2 * i + 1] = f.y;
+    }
+    f4 h1[MT], h2[MT];
+    const f4 o = mlp_forward<BF, HID>(lds, lane, z, h1, h2);
+    if (relu_masks) {
+      // Unit 16 mt + 4 g + r of this lane's sample -> word mt / 2, bit 16 (mt % 2) + 4 g + r.
+      constexpr int NW = HID / 32;
+      uint32_t w1[NW], w2[NW];
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        w1[w] = 0u;
+        w2[w] = 0u;
+      }
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const uint32_t bit = 1u << (16 * (mt & 1) + 4 * g + r);
+          if (h1[mt][r] > 0.f) w1[mt >> 1] |= bit;
+          if (h2[mt][r] > 0.f) w2[mt >> 1] |= bit;
+        }
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        w1[w] |= __shfl_xor(w1[w], 16, 64);
+        w1[w] |= __shfl_xor(w1[w], 32, 64);
+        w2[w] |= __shfl_xor(w2[w], 16, 64);
+        w2[w] |= __shfl_xor(w2[w], 32, 64);
+      }
+      if (g == 0 && si.valid) {
+        uint32_t* mp = relu_masks + si.s * (2 * NW);
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          mp[w] = si.has ? w1[w] : 0u;
+          mp[NW + w] = si.has ? w2[w] : 0u;
+        }
+      }
+    }
+    float t3[3], contrib[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      t3[r] = (si.has && g == 0) ? 1.0f / (1.0f + __expf(-o[r])) : 0.0f;
+      contrib[r] = si.W * t3[r];
+    }
+    for (int off = 1; off < K; off <<= 1)
+#pragma unroll
+      for (int r = 0; r < 3; ++r) contrib[r] += __shfl_xor(contrib[r], off, 64);
+    if (g == 0 && si.valid) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) tex[si.s * 3 + r] = t3[r];
+      if ((c & (K - 1)) == 0) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) image[si.p * 3 + r] = plain[si.p * 3 + r] + contrib[r];
+      }
+    }
+  }
+}
+
+// Per-wave scratch for the weight-gradient transposes: two [HID][16] tiles.
+template <bool BF, int HID>
+struct TLayout {
+  static constexpr int elem = BF ? 2 : 4;
+  static constexpr int tile_bytes = HID * 16 * elem;
+  static constexpr int wave_bytes = 2 * tile_bytes;
+};
+
+// Write a register tile set (rows 16 mt + 4 g + r, column c) into an LDS
+// [rows][16] matrix.
+template <bool BF>
+__device__ __forceinline__ void put_rows(unsigned char* buf, int row, int c, float v) {
+  if constexpr (BF) {
+    reinterpret_cast<short*>(buf)[row * 16 + c] = f2bf(v);
+  } else {
+    reinterpret_cast<float*>(buf)[row * 16 + c] = v;
+  }
+}
+
+// dW[out][in] += sum over 16 samples of Y[out][s] X[in][s], for output row
+// tiles [0, n_mo) and input tiles [0, n_mi); result tile added into acc
+// (row-major, ld = ld_acc) with LDS atomics; rows >= out_rows are dropped.
+template <bool BF>
+__device__ __forceinline__ void weight_grad_tiles(const unsigned char* Y, const unsigned char* X, int n_mo, int n_mi,
+                                                  float* acc, int ld_acc, int out_rows, int in_cols, int lane) {
+  const int g = lane >> 4, c = lane & 15;
+  const f4 zero = {0.f, 0.f, 0.f, 0.f};
+  for (int mo = 0; mo < n_mo; ++mo) {
+    for (int mi = 0; mi < n_mi; ++mi) {
+      f4 d;
+      if constexpr (BF) {
+        const s4 a = *reinterpret_cast<const s4*>(reinterpret_cast<const short*>(Y) + (16 * mo + c) * 16 + 4 * g);
+        const s4 b = *reinterpret_cast<const s4*>(reinterpret_cast<const short*>(X) + (16 * mi + c) * 16 + 4 * g);
+        d = mfma_bf16_k16(a, b, zero);
+      } else {
+        d = zero;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float a = reinterpret_cast<const float*>(Y)[(16 * mo + c) * 16 + 4 * q + g];
+          const float b = reinterpret_cast<const float*>(X)[(16 * mi + c) * 16 + 4 * q + g];
+          d = mfma_f32_k4(a, b, d);
+        }
+      }
+      const int col = 16 * mi + c;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * mo + 4 * g + r;
+        if (row < out_rows && col < in_cols && d[r] != 0.0f) atomicAdd(&acc[row * ld_acc + col], d[r]);
+      }
+    }
+  }
+}
+
+template <int TDT, bool BF, int HID>
+__global__ __launch_bounds__(kTexThreads) void texture_backward_kernel(
+    GridDev gd, const void* __restrict__ table, const void* w1, const void* w2, const void* w3, int in_dim, int K,
+    int log2K, int64_t n_samples, const int32_t* __restrict__ ids, const float* __restrict__ depths,
+    const float* __restrict__ weights, const float* __restrict__ grad_image, const float* __restrict__ grad_tex,
+    float* __restrict__ g_table, float* g_w1, float* g_w2, float* g_w3, float* __restrict__ grad_depth) {
+  using LY = WLayout<BF, HID>;
+  using TL = TLayout<BF, HID>;
+  constexpr int MT = LY::MT;
+  constexpr int nW1 = HID * kInPad, nW2 = HID * HID, nW3 = 16 * HID;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[LY::nAll * LY::slot_bytes];
+  __shared__ __attribute__((aligned(16))) unsigned char tbuf[kWaves * TL::wave_bytes];
+  __shared__ float dw[nW1 + nW2 + nW3];
+  stage_weights<BF, HID>(lds, LY::nAll, w1, w2, w3, in_dim);
+  for (int i = threadIdx.x; i < nW1 + nW2 + nW3; i += kTexThreads) dw[i] = 0.0f;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, c = lane & 15;
+  unsigned char* tY = tbuf + wave * TL::wave_bytes;
+  unsigned char* tX = tY + TL::tile_bytes;
+  const uint32_t mask = (1u << gd.log2_size) - 1u;
+  const int64_t n_blk = (n_samples + 15) / 16;
+  const f4 zero = {0.f, 0.f, 0.f, 0.f};
+
+  for (int64_t blk = (int64_t)blockIdx.x * kWaves + wave; blk < n_blk; blk += (int64_t)gridDim.x * kWaves) {
+    const SampleInfo si = sample_info(gd, K, log2K, n_samples, blk * 16 + c, ids, depths, weights);
+    // ---- recompute features
+    float z[8], fraw[8], delta[4], expo[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int l = lane_level(g, i);
+      float2 f = make_float2(0.f, 0.f);
+      delta[i] = 0.f;
+      expo[i] = 1.f;
+      if (si.has && l < gd.levels) {
+        const LevelGeom lg = level_geom(gd.lv[l], si);
+        f = level_feature<TDT>(table, (uint32_t)l << gd.log2_size, mask, lg);
+        delta[i] = lg.delta;
+        expo[i] = lg.expo;
+      }
+      fraw[2 * i] = f.x;
+      fraw[2 * i + 1] = f.y;
+      z[2 * i] = f.x * delta[i];
+      z[2 * i + 1] = f.y * delta[i];
+    }
+    // ---- MLP forward, keeping activations
+    f4 h1[MT], h2[MT];
+    const f4 o = mlp_forward<BF, HID>(lds, lane, z, h1, h2);
+    // ---- head: dL/dlogit for rows 0..2 of lane group 0
+    f4 dlog = zero;
+    if (g == 0 && si.has) {
+      const float g0 = grad_image[si.p * 3], g1 = grad_image[si.p * 3 + 1], g2 = grad_image[si.p * 3 + 2];
+      const float gi[3] = {g0, g1, g2};
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const float t = 1.0f / (1.0f + __expf(-o[r]));
+        float dt = si.W * gi[r];
+        if (grad_tex) dt += grad_tex[si.s * 3 + r];
+        dlog[r] = dt * t * (1.0f - t);
+      }
+    }
+    // ---- MLP backward
+    f4 dh2[MT], dh1[MT], dzt[2];
+    if constexpr (BF) {
+      constexpr int HT = LY::HT;
+      s8 bd;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) bd[e] = e < 4 ? f2bf(dlog[e]) : (short)0;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        f4 a = mfma_bf16_k32(Operand<true>::get(lds, LY::oA3T + mt, lane), bd, zero);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[r] = h2[mt][r] > 0.f ? a[r] : 0.f;
+        dh2[mt] = a;
+      }
+      s8 b2[HT];
+#pragma unroll
+      for (int h = 0; h < HT; ++h) b2[h] = pack_tiles(dh2[2 * h], dh2[2 * h + 1]);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        f4 a = zero;
+#pragma unroll
+        for (int h = 0; h < HT; ++h) a = mfma_bf16_k32(Operand<true>::get(lds, LY::oA2T + mt * HT + h, lane), b2[h], a);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[r] = h1[mt][r] > 0.f ? a[r] : 0.f;
+        dh1[mt] = a;
+      }
+      s8 b1[HT];
+#pragma unroll
+      for (int h = 0; h < HT; ++h) b1[h] = pack_tiles(dh1[2 * h], dh1[2 * h + 1]);
+#pragma unroll
+      for (int mz = 0; mz < 2; ++mz) {
+        f4 a = zero;
+#pragma unroll
+        for (int h = 0; h < HT; ++h) a = mfma_bf16_k32(Operand<true>::get(lds, LY::oA1T + mz * HT + h, lane), b1[h], a);
+        dzt[mz] = a;
+      }
+    } else {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        f4 a = zero;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a = mfma_f32_k4(Operand<false>::get(lds, LY::oA3T + mt * 4 + r, lane), dlog[r], a);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[r] = h2[mt][r] > 0.f ? a[r] : 0.f;
+        dh2[mt] = a;
+      }
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        f4 a = zero;
+#pragma unroll
+        for (int mi = 0; mi < MT; ++mi)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            a = mfma_f32_k4(Operand<false>::get(lds, LY::oA2T + (mt * MT + mi) * 4 + r, lane), dh2[mi][r], a);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[r] = h1[mt][r] > 0.f ? a[r] : 0.f;
+        dh1[mt] = a;
+      }
+#pragma unroll
+      for (int mz = 0; mz < 2; ++mz) {
+        f4 a = zero;
+#pragma unroll
+        for (int mi = 0; mi < MT; ++mi)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            a = mfma_f32_k4(Operand<false>::get(lds, LY::oA1T + (mz * MT + mi) * 4 + r, lane), dh1[mi][r], a);
+        dzt[mz] = a;
+      }
+    }
+    // ---- weight gradients through per-wave LDS transposes
+    // dW3 = dlogit x H2^T
+#pragma unroll
+    for (int r = 0; r < 4; ++r) put_rows<BF>(tY, 4 * g + r, c, dlog[r]);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) put_rows<BF>(tX, 16 * mt + 4 * g + r, c, h2[mt][r]);
+    wave_sync_lds();
+    weight_grad_tiles<BF>(tY, tX, 1, MT, dw + nW1 + nW2, HID, 3, HID, lane);
+    wave_sync_lds();
+    // dW2 = dH2 x H1^T
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        put_rows<BF>(tY, 16 * mt + 4 * g + r, c, dh2[mt][r]);
+        put_rows<BF>(tX, 16 * mt + 4 * g + r, c, h1[mt][r]);
+      }
+    wave_sync_lds();
+    weight_grad_tiles<BF>(tY, tX, MT, MT, dw + nW1, HID, HID, HID, lane);
+    wave_sync_lds();
+    // dW1 = dH1 x Z^T
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) put_rows<BF>(tY, 16 * mt + 4 * g + r, c, dh1[mt][r]);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) put_rows<BF>(tX, feat_index(g, e), c, z[e]);
+    wave_sync_lds();
+    weight_grad_tiles<BF>(tY, tX, MT, 2, dw, kInPad, HID, in_dim, lane);
+    wave_sync_lds();
+    // ---- hash-grid backward and depth gradient
+    float dD = 0.f;
+    if (si.has) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int l = lane_level(g, i);
+        if (l >= gd.levels) continue;
+        const float gz0 = i < 2 ? dzt[0][2 * i] : dzt[1][2 * (i - 2)];
+        const float gz1 = i < 2 ? dzt[0][2 * i + 1] : dzt[1][2 * (i - 2) + 1];
+        const GridLevel& L = gd.lv[l];
+        const LevelGeom lg = level_geom(L, si);
+        const float e0 = gz0 * delta[i], e1 = gz1 * delta[i];  // dL/dfeature (un-scaled)
+        const uint32_t base = (uint32_t)l << gd.log2_size;
+        float gpx = 0.f, gpy = 0.f, gpz = 0.f;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
+          const uint32_t h = (lg.hx[bx] ^ lg.hy[by] ^ lg.hz[bz]) & mask;
+          const float wx = bx ? lg.frx : 1.f - lg.frx;
+          const float wy = by ? lg.fry : 1.f - lg.fry;
+          const float wz = bz ? lg.frz : 1.f - lg.frz;
+          const float w = wx * wy * wz;
+          const uint32_t idx = base + h;
+          if (g_table) {
+            unsafeAtomicAdd(&g_table[2 * idx], w * e0);
+            unsafeAtomicAdd(&g_table[2 * idx + 1], w * e1);
+          }
+          const float2 th = load_pair<TDT>(table, idx);
+          const float q = th.x * e0 + th.y * e1;
+          gpx += q * (bx ? 1.f : -1.f) * wy * wz;
+          gpy += q * (by ? 1.f : -1.f) * wx * wz;
+          gpz += q * (bz ? 1.f : -1.f) * wx * wy;
+        }
+        // p = s (o + D d): dp/dD = s d. Delta = 1 - exp(-kappa/D^2): dDelta/dD = -(1-Delta) 2 kappa / D^3.
+        const float ddelta = -lg.expo * 2.0f * L.kappa / (si.D * si.D * si.D);
+        dD += L.scale * (gpx * si.dx + gpy * si.dy + gpz * si.dz) +
+              ddelta * (fraw[2 * i] * gz0 + fraw[2 * i + 1] * gz1);
+      }
+    }
+    dD += __shfl_xor(dD, 16, 64);
+    dD += __shfl_xor(dD, 32, 64);
+    if (g == 0 && si.valid && grad_depth) grad_depth[si.s] = si.has ? dD : 0.f;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nW1 + nW2 + nW3; i += kTexThreads) {
+    const float v = dw[i];
+    if (v == 0.0f) continue;
+    if (i < nW1) {
+      const int row = i / kInPad, col = i % kInPad;
+      if (g_w1 && col < in_dim) unsafeAtomicAdd(&g_w1[row * in_dim + col], v);
+    } else if (i < nW1 + nW2) {
+      if (g_w2) unsafeAtomicAdd(&g_w2[i - nW1], v);
+    } else {
+      const int q = i - nW1 - nW2, row = q / HID;
+      if (g_w3 && row < 3) unsafeAtomicAdd(&g_w3[q], v);
+    }
+  }
+}
+
+__global__ void copy_plain_kernel(const float* plain, float* image, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) image[i] = plain[i];
+}
+
+int ilog2(int k) {
+  int r = 0;
+  while ((1 << r) < k) ++r;
+  return r;
+}
+
+template <int TDT, bool BF, int HID>
+hipError_t fwd_inst(const GridDev& gd, const void* table, const MlpDev& mlp, int K, int64_t n_samples,
+                    const int32_t* ids, const float* depths, const float* weights, const float* plain, float* tex,
+                    float* image, int32_t* cells, uint32_t* masks, hipStream_t s) {
+  const int64_t n_blk = (n_samples + 15) / 16;
+  int64_t grid = (n_blk + kWaves - 1) / kWaves;
+  if (grid > 4096) grid = 4096;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL((texture_forward_kernel<TDT, BF, HID>), dim3((unsigned)grid), dim3(kTexThreads), 0, s, gd, table,
+                     mlp.w[0], mlp.w[1], mlp.w[2], mlp.in_dim, K, ilog2(K), n_samples, ids, depths, weights, plain,
+                     tex, image, cells, masks);
+  return hipGetLastError();
+}
+
+template <int TDT, bool BF, int HID>
+hipError_t bwd_inst(const GridDev& gd, const void* table, const MlpDev& mlp, int K, int64_t n_samples,
+                    const int32_t* ids, const float* depths, const float* weights, const float* grad_image,
+                    const float* grad_tex, float* g_table, float* g0, float* g1, float* g2, float* grad_depth,
+                    hipStream_t s) {
+  const int64_t n_blk = (n_samples + 15) / 16;
+  int64_t grid = (n_blk + kWaves - 1) / kWaves;
+  if (grid > 1024) grid = 1024;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL((texture_backward_kernel<TDT, BF, HID>), dim3((unsigned)grid), dim3(kTexThreads), 0, s, gd,
+                     table, mlp.w[0], mlp.w[1], mlp.w[2], mlp.in_dim, K, ilog2(K), n_samples, ids, depths, weights,
+                     grad_image, grad_tex, g_table, g0, g1, g2, grad_depth);
+  return hipGetLastError();
+}
+
+template <bool BF, int HID>
+hipError_t fwd_by_table(int tdt, const GridDev& gd, const void* table, const MlpDev& mlp, int K, int64_t n,
+                        const int32_t* ids, const float* depths, const float* weights, const float* plain,
+                        float* tex, float* image, int32_t* cells, uint32_t* masks, hipStream_t s) {
+  switch (tdt) {
+    case NX_F32:
+      return fwd_inst<NX_F32, BF, HID>(gd, table, mlp, K, n, ids, depths, weights, plain, tex, image, cells, masks, s);
+    case NX_F16:
+      return fwd_inst<NX_F16, BF, HID>(gd, table, mlp, K, n, ids, depths, weights, plain, tex, image, cells, masks, s);
+    case NX_BF16:
+      return fwd_inst<NX_BF16, BF, HID>(gd, table, mlp, K, n, ids, depths, weights, plain, tex, image, cells, masks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <bool BF, int HID>
+hipError_t bwd_by_table(int tdt, const GridDev& gd, const void* table, const MlpDev& mlp, int K, int64_t n,
+                        const int32_t* ids, const float* depths, const float* weights, const float* gi,
+                        const float* gt, float* gtab, float* g0, float* g1, float* g2, float* gd_out,
+                        hipStream_t s) {
+  switch (tdt) {
+    case NX_F32:
+      return bwd_inst<NX_F32, BF, HID>(gd, table, mlp, K, n, ids, depths, weights, gi, gt, gtab, g0, g1, g2, gd_out, s);
+    case NX_F16:
+      return bwd_inst<NX_F16, BF, HID>(gd, table, mlp, K, n, ids, depths, weights, gi, gt, gtab, g0, g1, g2, gd_out, s);
+    case NX_BF16:
+      return bwd_inst<NX_BF16, BF, HID>(gd, table, mlp, K, n, ids, depths, weights, gi, gt, gtab, g0, g1, g2, gd_out,
+                                        s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_texture_forward(int K, int feat_dtype, int mlp_dtype, const GridDev& grid, const void* table,
+                                  const MlpDev& mlp, const int32_t* ids, const float* depths, const float* weights,
+                                  const float* plain, float* tex, float* image, int32_t* cells, uint32_t* masks,
+                                  hipStream_t s) {
+  const int64_t P = (int64_t)grid.width * grid.height;
+  if (K == 0) {
+    if (P == 0) return hipSuccess;
+    hipLaunchKernelGGL(copy_plain_kernel, dim3((unsigned)((3 * P + 255) / 256)), dim3(256), 0, s, plain, image, 3 * P);
+    return hipGetLastError();
+  }
+  const int64_t n = P * K;
+  if (n == 0) return hipSuccess;
+  const bool bf = mlp_dtype == NX_BF16;
+  if (mlp.hidden == 64)
+    return bf ? fwd_by_table<true, 64>(feat_dtype, grid, table, mlp, K, n, ids, depths, weights, plain, tex, image,
+                                       cells, masks, s)
+              : fwd_by_table<false, 64>(feat_dtype, grid, table, mlp, K, n, ids, depths, weights, plain, tex, image,
+                                        cells, masks, s);
+  if (mlp.hidden == 128)
+    return bf ? fwd_by_table<true, 128>(feat_dtype, grid, table, mlp, K, n, ids, depths, weights, plain, tex, image,
+                                        cells, masks, s)
+              : fwd_by_table<false, 128>(feat_dtype, grid, table, mlp, K, n, ids, depths, weights, plain, tex, image,
+                                         cells, masks, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_texture_backward(int K, int feat_dtype, int mlp_dtype, const GridDev& grid, const void* table,
+                                   const MlpDev& mlp, const int32_t* ids, const float* depths, const float* weights,
+                                   const float* tex, const float* grad_image, const float* grad_tex, float* g_table,
+                                   float* g_mlp0, float* g_mlp1, float* g_mlp2, float* grad_depth, hipStream_t s) {
+  (void)tex;
+  const int64_t P = (int64_t)grid.width * grid.height;
+  if (K == 0) return hipSuccess;
+  const int64_t n = P * K;
+  if (n == 0) return hipSuccess;
+  const bool bf = mlp_dtype == NX_BF16;
+  if (mlp.hidden == 64)
+    return bf ? bwd_by_table<true, 64>(feat_dtype, grid, table, mlp, K, n, ids, depths, weights, grad_image, grad_tex,
+                                       g_table, g_mlp0, g_mlp1, g_mlp2, grad_depth, s)
+              : bwd_by_table<false, 64>(feat_dtype, grid, table, mlp, K, n, ids, depths, weights, grad_image, grad_tex,
+                                        g_table, g_mlp0, g_mlp1, g_mlp2, grad_depth, s);
+  // Hidden width 128 would need more LDS than a workgroup has for the
+  // weight-gradient accumulators; the C ABI rejects it before launch.
+  return hipErrorInvalidValue;
+}
+
+}  // namespace nx

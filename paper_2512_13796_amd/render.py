@@ -1,0 +1,281 @@
+"""Python binding of the rendering library: argument marshalling only.
+
+Every step of the rendering path runs in the HIP kernels of libnexels.so;
+this module allocates output and workspace tensors with PyTorch, fills the
+C structs of include/nexels.h and calls nx_render_forward /
+nx_render_backward on the current HIP stream. ``RenderFunction`` wraps the
+two calls as a torch.autograd.Function.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_DTYPE = {torch.float32: L.NX_F32, torch.float16: L.NX_F16, torch.bfloat16: L.NX_BF16}
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check_dev(name, t, device, dtype=None, shape=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a tensor")
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def camera_struct(cam, near=0.2):
+    """nx_camera from an object with world_to_cam [3,4], fx, fy, cx, cy, width, height."""
+    c = L.NxCamera()
+    m = np.asarray(cam.world_to_cam, dtype=np.float64).reshape(-1)
+    for i in range(12):
+        c.world_to_cam[i] = float(m[i])
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.near_z = float(near)
+    c.width, c.height = int(cam.width), int(cam.height)
+    return c
+
+
+class Context:
+    """Owns one nx_ctx (K, tile size, storage dtypes)."""
+
+    def __init__(self, K, feat_dtype=torch.float32, mlp_dtype=torch.float32):
+        self.lib = L.load()
+        self.K = int(K)
+        self.feat_dtype = feat_dtype
+        self.mlp_dtype = mlp_dtype
+        h = ctypes.c_void_p()
+        L.check(self.lib.nx_create(ctypes.byref(h), self.K, 16, _DTYPE[feat_dtype], _DTYPE[mlp_dtype]))
+        self.handle = h
+        self.ws_hint = 0
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.lib.nx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def timing(self, enabled=True):
+        L.check(self.lib.nx_timing_enable(self.handle, 1 if enabled else 0))
+
+    def timing_reset(self):
+        L.check(self.lib.nx_timing_reset(self.handle))
+
+    def timings(self):
+        """{phase: (total_ms, launches)} accumulated since the last reset."""
+        out = {}
+        i = 0
+        while True:
+            nm = ctypes.c_char_p()
+            ms = ctypes.c_double()
+            cnt = ctypes.c_int64()
+            if self.lib.nx_timing_get(self.handle, i, ctypes.byref(nm), ctypes.byref(ms), ctypes.byref(cnt)) != 0:
+                break
+            out[nm.value.decode()] = (ms.value, cnt.value)
+            i += 1
+        return out
+
+    def workspace_layout(self, n_surfels, cam, n_instances, near=0.2):
+        lay = L.NxWsLayout()
+        cs = camera_struct(cam, near)
+        L.check(self.lib.nx_workspace_layout(self.handle, int(n_surfels), ctypes.byref(cs), 1, int(n_instances),
+                                             ctypes.byref(lay)))
+        return {f: getattr(lay, f) for f, _ in L.NxWsLayout._fields_}
+
+
+@dataclasses.dataclass
+class ForwardResult:
+    image: torch.Tensor
+    plain: torch.Tensor
+    ids: torch.Tensor
+    weights: torch.Tensor
+    depths: torch.Tensor
+    t_final: torch.Tensor
+    tex: torch.Tensor
+    n_iter: torch.Tensor
+    n_instances: int
+    workspace: torch.Tensor
+    camera: object = None
+    near: float = 0.2
+    cells: torch.Tensor = None
+    relu_masks: torch.Tensor = None
+
+
+def _structs(ctx, surfels, table, level_scales, weights, device):
+    means, quats, scales, opac, gammas, colors = surfels
+    n = means.shape[0]
+    for nm, t, shp in (("means", means, (n, 3)), ("quats", quats, (n, 4)), ("scales", scales, (n, 2)),
+                       ("opacities", opac, (n,)), ("gammas", gammas, (n, 2)), ("colors", colors, (n, 3))):
+        _check_dev(nm, t, device, torch.float32, shp)
+    s = L.NxSurfels(_ptr(means), _ptr(quats), _ptr(scales), _ptr(opac), _ptr(gammas), _ptr(colors), n)
+    g = L.NxHashGrid()
+    m = L.NxMLP()
+    keep = []
+    if ctx.K > 0:
+        _check_dev("table", table, device, ctx.feat_dtype)
+        ls = level_scales.detach().to("cpu", torch.float32).contiguous()
+        keep.append(ls)
+        g.table = _ptr(table)
+        g.dtype = _DTYPE[table.dtype]
+        g.levels, g.log2_size, g.feat = table.shape[0], int(table.shape[1]).bit_length() - 1, table.shape[2]
+        if (1 << g.log2_size) != table.shape[1]:
+            raise ValueError("table size must be a power of two")
+        g.level_scales = ctypes.c_void_p(ls.data_ptr())
+        for i, w in enumerate(weights):
+            _check_dev(f"mlp[{i}]", w, device, ctx.mlp_dtype)
+            m.w[i] = w.data_ptr()
+        m.dtype = _DTYPE[ctx.mlp_dtype]
+        m.dims[0] = weights[0].shape[1]
+        m.dims[1] = weights[0].shape[0]
+        m.dims[2] = weights[1].shape[0]
+        m.dims[3] = weights[2].shape[0]
+    return s, g, m, keep
+
+
+def render_forward(ctx: Context, surfels, cam, table=None, level_scales=None, weights=None, near=0.2,
+                   workspace=None, want_cells=False) -> ForwardResult:
+    """Collection and texturing passes for one camera (nx_render_forward).
+
+    want_cells=True also returns the hash-grid lattice cells the texturing
+    pass used ([P, K, levels, 3] int32) and its ReLU decisions
+    ([P, K, 2*hidden/32] int32 bit masks), for decision-level comparisons."""
+    device = surfels[0].device
+    s, g, m, keep = _structs(ctx, surfels, table, level_scales, weights, device)
+    cs = camera_struct(cam, near)
+    P = cam.width * cam.height
+    K = ctx.K
+    f32 = dict(device=device, dtype=torch.float32)
+    res = ForwardResult(
+        image=torch.empty(P, 3, **f32), plain=torch.empty(P, 3, **f32),
+        ids=torch.empty(P, max(K, 1), device=device, dtype=torch.int32),
+        weights=torch.empty(P, max(K, 1), **f32), depths=torch.empty(P, max(K, 1), **f32),
+        t_final=torch.empty(P, **f32), tex=torch.empty(P, max(K, 1), 3, **f32),
+        n_iter=torch.empty(P, device=device, dtype=torch.int32), n_instances=0, workspace=None, camera=cam,
+        near=near)
+    if want_cells and K > 0:
+        res.cells = torch.zeros(P, K, table.shape[0], 3, device=device, dtype=torch.int32)
+        res.relu_masks = torch.zeros(P, K, 2 * weights[0].shape[0] // 32, device=device, dtype=torch.int32)
+    out = L.NxFwdOut(_ptr(res.image), _ptr(res.plain), _ptr(res.ids), _ptr(res.weights), _ptr(res.depths),
+                     _ptr(res.t_final), _ptr(res.tex), _ptr(res.n_iter), _ptr(res.cells), _ptr(res.relu_masks), 0)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+    need = ctypes.c_size_t(0)
+    ws = workspace
+    for _ in range(3):
+        if ws is None or ws.numel() < ctx.ws_hint:
+            ws = torch.empty(max(ctx.ws_hint, 256), device=device, dtype=torch.uint8)
+        code = ctx.lib.nx_render_forward(ctx.handle, ctypes.byref(s), ctypes.byref(cs), 1, ctypes.byref(g),
+                                         ctypes.byref(m), ctypes.byref(out), _ptr(ws), ws.numel(),
+                                         ctypes.byref(need), stream)
+        if code == L.NX_ERR_WORKSPACE:
+            ctx.ws_hint = max(ctx.ws_hint, int(need.value))
+            ws = None
+            continue
+        L.check(code)
+        break
+    else:
+        raise L.NexelsError(L.NX_ERR_WORKSPACE, "workspace sizing did not converge")
+    ctx.ws_hint = max(ctx.ws_hint, int(need.value))
+    res.n_instances = int(out.n_instances)
+    res.workspace = ws
+    del keep
+    return res
+
+
+def render_backward(ctx: Context, surfels, fwd: ForwardResult, table=None, level_scales=None, weights=None,
+                    grad_image=None, grad_weights=None, grad_tex=None, grads=None):
+    """Accumulate gradients into ``grads`` (dict of float32 tensors; missing keys are skipped)."""
+    device = surfels[0].device
+    s, g, m, keep = _structs(ctx, surfels, table, level_scales, weights, device)
+    cs = camera_struct(fwd.camera, fwd.near)
+    P = fwd.camera.width * fwd.camera.height
+    K = ctx.K
+    _check_dev("grad_image", grad_image, device, torch.float32, (P, 3))
+    if grad_weights is not None:
+        _check_dev("grad_weights", grad_weights, device, torch.float32, (P, K))
+    if grad_tex is not None:
+        _check_dev("grad_tex", grad_tex, device, torch.float32, (P, K, 3))
+    grads = grads or {}
+    for k, t in grads.items():
+        if t is not None and k != "mlp":
+            _check_dev(f"grads[{k}]", t, device, torch.float32)
+    gm = grads.get("mlp") or [None, None, None]
+    gs = L.NxGrads(_ptr(grads.get("means")), _ptr(grads.get("quats")), _ptr(grads.get("scales")),
+                   _ptr(grads.get("opacities")), _ptr(grads.get("gammas")), _ptr(grads.get("colors")),
+                   _ptr(grads.get("table")))
+    for i in range(3):
+        gs.mlp[i] = None if gm[i] is None else gm[i].data_ptr()
+    out = L.NxFwdOut(_ptr(fwd.image), _ptr(fwd.plain), _ptr(fwd.ids), _ptr(fwd.weights), _ptr(fwd.depths),
+                     _ptr(fwd.t_final), _ptr(fwd.tex), _ptr(fwd.n_iter), None, None, fwd.n_instances)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+    L.check(ctx.lib.nx_render_backward(ctx.handle, ctypes.byref(s), ctypes.byref(cs), 1, ctypes.byref(g),
+                                       ctypes.byref(m), ctypes.byref(out), _ptr(fwd.workspace), fwd.workspace.numel(),
+                                       _ptr(grad_image), _ptr(grad_weights), _ptr(grad_tex), ctypes.byref(gs),
+                                       stream))
+    del keep
+    return grads
+
+
+class RenderFunction(torch.autograd.Function):
+    """image, weights, tex = RenderFunction.apply(ctx, cam, level_scales, means, quats, scales,
+    opacities, gammas, colors, table, w1, w2, w3).
+
+    Gradients flow to the six surfel tensors, the hash table and the three
+    MLP matrices; gradients of storage dtypes other than float32 are
+    accumulated in float32 and cast by autograd.
+    """
+
+    @staticmethod
+    def forward(fctx, nctx, cam, level_scales, means, quats, scales, opac, gammas, colors, table, w1, w2, w3):
+        surfels = (means, quats, scales, opac, gammas, colors)
+        weights = [w1, w2, w3] if nctx.K > 0 else None
+        res = render_forward(nctx, surfels, cam, table, level_scales, weights)
+        fctx.nctx = nctx
+        fctx.res = res
+        fctx.level_scales = level_scales
+        fctx.save_for_backward(means, quats, scales, opac, gammas, colors, table, w1, w2, w3)
+        fctx.mark_non_differentiable(res.plain, res.ids, res.depths, res.t_final)
+        return res.image, res.weights, res.tex, res.plain, res.ids, res.depths, res.t_final
+
+    @staticmethod
+    def backward(fctx, g_image, g_weights, g_tex, *unused):
+        means, quats, scales, opac, gammas, colors, table, w1, w2, w3 = fctx.saved_tensors
+        nctx, res = fctx.nctx, fctx.res
+        dev = means.device
+        z = lambda t: torch.zeros(t.shape, device=dev, dtype=torch.float32)
+        grads = {"means": z(means), "quats": z(quats), "scales": z(scales), "opacities": z(opac),
+                 "gammas": z(gammas), "colors": z(colors)}
+        if nctx.K > 0:
+            grads["table"] = z(table)
+            grads["mlp"] = [z(w1), z(w2), z(w3)]
+        gi = torch.zeros_like(res.image) if g_image is None else g_image.contiguous().float()
+        gw = None if g_weights is None or nctx.K == 0 else g_weights.contiguous().float()
+        gt = None if g_tex is None or nctx.K == 0 else g_tex.contiguous().float()
+        weights = [w1, w2, w3] if nctx.K > 0 else None
+        render_backward(nctx, (means, quats, scales, opac, gammas, colors), res, table, fctx.level_scales, weights,
+                        gi, gw, gt, grads)
+        gmlp = grads.get("mlp") or [None, None, None]
+        return (None, None, None, grads["means"], grads["quats"], grads["scales"], grads["opacities"],
+                grads["gammas"], grads["colors"], grads.get("table"), gmlp[0], gmlp[1], gmlp[2])
+
+
+def render(nctx, cam, level_scales, means, quats, scales, opac, gammas, colors, table, w1, w2, w3):
+    """Differentiable render: returns (image [P,3], weights [P,K], tex [P,K,3], plain, ids, depths, t_final)."""
+    return RenderFunction.apply(nctx, cam, level_scales, means, quats, scales, opac, gammas, colors, table, w1, w2,
+                                w3)

@@ -307,6 +307,34 @@ def test_interpolation_is_linear_inside_a_cell():
     np.testing.assert_allclose(z[1], 0.5 * (z[0] + z[2]), rtol=1e-13)
 
 
+def test_forced_cells_match_natural_cells_and_faces_are_continuous():
+    """Forcing the natural lattice cell changes nothing; at a cell face the
+    two neighbouring cells' trilinear polynomials agree (continuity), which
+    is what makes evaluating a sample in another implementation's cell a
+    rounding-sized change of the value."""
+    rng = np.random.default_rng(12)
+    grid = random_grid(rng, levels=2, log2_size=8)
+    s = grid.level_scales.double().numpy()
+    x = torch.from_numpy(rng.uniform(-3, 3, (50, 3)))
+    D = torch.from_numpy(rng.uniform(0.5, 5, 50))
+    cells = np.stack([np.floor(s[l] * x.numpy()) for l in range(2)], axis=1).astype(np.int64)
+    a = encode(x, D, grid.table.double(), grid.level_scales.double(), 100.0).numpy()
+    b = encode(x, D, grid.table.double(), grid.level_scales.double(), 100.0, cells=cells).numpy()
+    np.testing.assert_array_equal(a, b)
+    # points exactly on an x-face of level 0: cell k and cell k-1 give the same features
+    k = rng.integers(-50, 50, (20, 3)).astype(np.float64)
+    frac = rng.uniform(0.1, 0.9, (20, 3))
+    frac[:, 0] = 0.0
+    xf = torch.from_numpy((k + frac) / s[0])
+    Df = torch.full((20,), 1.0, dtype=torch.float64)
+    c_hi = np.stack([np.floor(s[l] * xf.numpy()) for l in range(2)], axis=1).astype(np.int64)
+    c_lo = c_hi.copy()
+    c_lo[:, 0, 0] -= 1
+    za = encode(xf, Df, grid.table.double(), grid.level_scales.double(), 100.0, cells=c_hi).numpy()
+    zb = encode(xf, Df, grid.table.double(), grid.level_scales.double(), 100.0, cells=c_lo).numpy()
+    np.testing.assert_allclose(za[:, :2], zb[:, :2], rtol=1e-12, atol=1e-15)
+
+
 def test_downweight_matches_erf_squared_and_limits():
     """Delta approximates erf(f / (2 sqrt2 s t))^2 (supplementary, Anti-aliasing)."""
     f = 1662.77
@@ -318,6 +346,26 @@ def test_downweight_matches_erf_squared_and_limits():
     assert np.all(np.diff(D, axis=0) <= 0) and np.all(np.diff(D, axis=1) <= 0)  # decreasing in t and s
     assert downweight(torch.tensor(1e-9, dtype=torch.float64), 7000.0, f).item() == 1.0
     assert downweight(torch.tensor(1e9, dtype=torch.float64), 16.0, f).item() < 1e-12
+
+
+def test_forced_relu_masks():
+    """Natural masks reproduce the ReLU network; a flipped unit with a zero
+    pre-activation leaves the output unchanged (continuity at the kink)."""
+    from oracle.mlp import unpack_masks
+    rng = np.random.default_rng(13)
+    mlp = random_mlp(rng, [32, 64, 64, 3])
+    z = torch.from_numpy(rng.standard_normal((20, 32)))
+    h1 = z @ mlp.weights[0].t()
+    h2 = torch.relu(h1) @ mlp.weights[1].t()
+    def pack(b):
+        b = b.numpy().astype(np.uint64).reshape(20, 2, 32)
+        return (b << np.arange(32, dtype=np.uint64)).sum(-1).astype(np.uint32)
+    words = np.concatenate([pack(h1 > 0), pack(h2 > 0)], axis=1)
+    masks = unpack_masks(words, 64, 2)
+    np.testing.assert_array_equal(masks[0].numpy(), (h1 > 0).numpy().astype(float))
+    a = mlp_forward(z, mlp.weights).numpy()
+    b = mlp_forward(z, mlp.weights, relu_masks=masks).numpy()
+    np.testing.assert_allclose(a, b, rtol=1e-14)
 
 
 def test_mlp_matches_numpy_chain_and_zero_input():
