@@ -89,8 +89,12 @@ __device__ __forceinline__ f4 mfma_f32_k4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Orders this wave's LDS writes before its later LDS reads by other lanes:
+// wait for the wave's outstanding LDS operations only (global memory traffic
+// stays in flight) and stop the compiler moving memory accesses across.
 __device__ __forceinline__ void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
   __builtin_amdgcn_wave_barrier();
 }
 
@@ -294,23 +298,32 @@ struct SampleInfo {
   float dx, dy, dz;  // world ray direction
 };
 
-__device__ __forceinline__ SampleInfo sample_info(const GridDev& gd, int K, int log2K, int64_t n_samples, int64_t s,
+// Sample (pixel c of 4x4 patch q, slot j). Patches tile the image row-major;
+// lanes of a 16-lane row see the same slot of 16 neighbouring pixels, so at
+// coarse levels they usually share a hash-grid cell.
+__device__ __forceinline__ SampleInfo sample_info(const GridDev& gd, int K, int64_t q, int j, int c,
                                                   const int32_t* ids, const float* depths, const float* weights) {
   SampleInfo si;
-  si.s = s;
-  si.valid = s < n_samples;
-  si.p = si.valid ? (s >> log2K) : 0;
-  const int id = si.valid ? ids[s] : -1;
+  const int npx = (gd.width + 3) >> 2;
+  const int px = 4 * (int)(q % npx) + (c & 3);
+  const int py = 4 * (int)(q / npx) + (c >> 2);
+  si.valid = px < gd.width && py < gd.height;
+  si.p = si.valid ? (int64_t)py * gd.width + px : 0;
+  si.s = si.p * K + j;
+  const int id = si.valid ? ids[si.s] : -1;
   si.has = id >= 0;
-  si.D = si.has ? depths[s] : 1.0f;
-  si.W = si.has ? weights[s] : 0.0f;
-  const int px = (int)(si.p % gd.width), py = (int)(si.p / gd.width);
+  si.D = si.has ? depths[si.s] : 1.0f;
+  si.W = si.has ? weights[si.s] : 0.0f;
   const float cx = ((float)px + 0.5f - gd.cx) / gd.fx;
   const float cy = ((float)py + 0.5f - gd.cy) / gd.fy;
   si.dx = gd.rot[0] * cx + gd.rot[1] * cy + gd.rot[2];
   si.dy = gd.rot[3] * cx + gd.rot[4] * cy + gd.rot[5];
   si.dz = gd.rot[6] * cx + gd.rot[7] * cy + gd.rot[8];
   return si;
+}
+
+__host__ __device__ __forceinline__ int64_t n_patches(const GridDev& gd) {
+  return (int64_t)((gd.width + 3) >> 2) * ((gd.height + 3) >> 2);
 }
 
 struct LevelGeom {
@@ -346,20 +359,93 @@ __device__ __forceinline__ LevelGeom level_geom(const GridLevel& L, const Sample
   return g;
 }
 
-// Interpolated (un-scaled) features of one level.
+// One table entry (F = 2): a 16-bit pair is one 32-bit word, an FP32 pair two.
 template <int TDT>
-__device__ __forceinline__ float2 level_feature(const void* table, uint32_t base, uint32_t mask, const LevelGeom& g) {
-  float f0 = 0.f, f1 = 0.f;
-#pragma unroll
-  for (int b = 0; b < 8; ++b) {
-    const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
-    const uint32_t h = (g.hx[bx] ^ g.hy[by] ^ g.hz[bz]) & mask;
-    const float w = (bx ? g.frx : 1.f - g.frx) * (by ? g.fry : 1.f - g.fry) * (bz ? g.frz : 1.f - g.frz);
-    const float2 th = load_pair<TDT>(table, base + h);
-    f0 = fmaf(w, th.x, f0);
-    f1 = fmaf(w, th.y, f1);
+struct EntryT {
+  using type = uint32_t;
+};
+template <>
+struct EntryT<NX_F32> {
+  using type = float2;
+};
+
+template <int TDT>
+__device__ __forceinline__ typename EntryT<TDT>::type load_entry(const void* table, uint32_t idx) {
+  if constexpr (TDT == NX_F32) {
+    return reinterpret_cast<const float2*>(table)[idx];
+  } else {
+    return reinterpret_cast<const uint32_t*>(table)[idx];
   }
-  return make_float2(f0, f1);
+}
+
+template <int TDT>
+__device__ __forceinline__ float2 entry_value(typename EntryT<TDT>::type e) {
+  if constexpr (TDT == NX_F32) {
+    return e;
+  } else if constexpr (TDT == NX_F16) {
+    return make_float2(__half2float(__ushort_as_half((unsigned short)(e & 0xFFFFu))),
+                       __half2float(__ushort_as_half((unsigned short)(e >> 16))));
+  } else {
+    return make_float2(bf2f(e & 0xFFFFu), bf2f(e >> 16));
+  }
+}
+
+__device__ __forceinline__ uint32_t corner_hash(const LevelGeom& g, int b, uint32_t mask) {
+  return (g.hx[b & 1] ^ g.hy[(b >> 1) & 1] ^ g.hz[(b >> 2) & 1]) & mask;
+}
+
+__device__ __forceinline__ float corner_weight(const LevelGeom& g, int b) {
+  return ((b & 1) ? g.frx : 1.f - g.frx) * ((b & 2) ? g.fry : 1.f - g.fry) * ((b & 4) ? g.frz : 1.f - g.frz);
+}
+
+// A lane's four levels: whether each is active and its 8 corner entries.
+// All 32 reads are issued before any is used (inactive levels read entry 0).
+template <int TDT>
+struct LaneEntries {
+  typename EntryT<TDT>::type ent[4][8];
+  bool act[4];
+};
+
+template <int TDT>
+__device__ __forceinline__ void gather_lane(const GridDev& gd, const void* table, const SampleInfo& si, int g,
+                                            uint32_t mask, LaneEntries<TDT>& E, float fraw[8], float delta[4],
+                                            int32_t* cells_out) {
+  LevelGeom lg[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int l = lane_level(g, i);
+    E.act[i] = si.has && l < gd.levels;
+    lg[i] = level_geom(gd.lv[l < gd.levels ? l : 0], si);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t base = (uint32_t)lane_level(g, i) << gd.log2_size;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint32_t idx = E.act[i] ? base + corner_hash(lg[i], b, mask) : 0u;
+      E.ent[i][b] = load_entry<TDT>(table, idx);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    float f0 = 0.f, f1 = 0.f;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const float w = corner_weight(lg[i], b);
+      const float2 th = entry_value<TDT>(E.ent[i][b]);
+      f0 = fmaf(w, th.x, f0);
+      f1 = fmaf(w, th.y, f1);
+    }
+    fraw[2 * i] = E.act[i] ? f0 : 0.f;
+    fraw[2 * i + 1] = E.act[i] ? f1 : 0.f;
+    delta[i] = E.act[i] ? lg[i].delta : 0.f;
+    if (cells_out && E.act[i]) {
+      int32_t* cp = cells_out + lane_level(g, i) * 3;
+      cp[0] = lg[i].cx;
+      cp[1] = lg[i].cy;
+      cp[2] = lg[i].cz;
+    }
+  }
 }
 
 template <int TDT, bool BF, int HID>
@@ -382,80 +468,71 @@ __global__ __launch_bounds__(kTexThreads) void texture_forward_kernel(GridDev gd
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, c = lane & 15;
   const uint32_t mask = (1u << gd.log2_size) - 1u;
-  const int64_t n_blk = (n_samples + 15) / 16;
-  for (int64_t blk = (int64_t)blockIdx.x * kWaves + wave; blk < n_blk; blk += (int64_t)gridDim.x * kWaves) {
-    const SampleInfo si = sample_info(gd, K, log2K, n_samples, blk * 16 + c, ids, depths, weights);
-    float z[8];
+  const int64_t n_q = n_patches(gd);
+  for (int64_t q = (int64_t)blockIdx.x * kWaves + wave; q < n_q; q += (int64_t)gridDim.x * kWaves) {
+    float contrib[3] = {0.f, 0.f, 0.f};
+    bool pix_valid = false;
+    int64_t pix = 0;
+    for (int j = 0; j < K; ++j) {
+      const SampleInfo si = sample_info(gd, K, q, j, c, ids, depths, weights);
+      pix_valid = si.valid;
+      pix = si.p;
+      float z[8], fraw[8], delta[4];
+      LaneEntries<TDT> E;
+      gather_lane<TDT>(gd, table, si, g, mask, E, fraw, delta,
+                       cells && si.valid ? cells + si.s * gd.levels * 3 : nullptr);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int l = lane_level(g, i);
-      float2 f = make_float2(0.f, 0.f);
-      if (si.has && l < gd.levels) {
-        const LevelGeom lg = level_geom(gd.lv[l], si);
-        f = level_feature<TDT>(table, (uint32_t)l << gd.log2_size, mask, lg);
-        f.x *= lg.delta;
-        f.y *= lg.delta;
-        if (cells) {
-          int32_t* cp = cells + (si.s * gd.levels + l) * 3;
-          cp[0] = lg.cx;
-          cp[1] = lg.cy;
-          cp[2] = lg.cz;
-        }
+      for (int i = 0; i < 4; ++i) {
+        z[2 * i] = fraw[2 * i] * delta[i];
+        z[2 * i + 1] = fraw[2 * i + 1] * delta[i];
       }
-      z[2 * i] = f.x;
-      z[2 * i + 1] = f.y;
-    }
-    f4 h1[MT], h2[MT];
-    const f4 o = mlp_forward<BF, HID>(lds, lane, z, h1, h2);
-    if (relu_masks) {
-      // Unit 16 mt + 4 g + r of this lane's sample -> word mt / 2, bit 16 (mt % 2) + 4 g + r.
-      constexpr int NW = HID / 32;
-      uint32_t w1[NW], w2[NW];
-#pragma unroll
-      for (int w = 0; w < NW; ++w) {
-        w1[w] = 0u;
-        w2[w] = 0u;
-      }
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const uint32_t bit = 1u << (16 * (mt & 1) + 4 * g + r);
-          if (h1[mt][r] > 0.f) w1[mt >> 1] |= bit;
-          if (h2[mt][r] > 0.f) w2[mt >> 1] |= bit;
-        }
-#pragma unroll
-      for (int w = 0; w < NW; ++w) {
-        w1[w] |= __shfl_xor(w1[w], 16, 64);
-        w1[w] |= __shfl_xor(w1[w], 32, 64);
-        w2[w] |= __shfl_xor(w2[w], 16, 64);
-        w2[w] |= __shfl_xor(w2[w], 32, 64);
-      }
-      if (g == 0 && si.valid) {
-        uint32_t* mp = relu_masks + si.s * (2 * NW);
+      f4 h1[MT], h2[MT];
+      const f4 o = mlp_forward<BF, HID>(lds, lane, z, h1, h2);
+      if (relu_masks) {
+        // Unit 16 mt + 4 g + r of this lane's sample -> word mt / 2, bit 16 (mt % 2) + 4 g + r.
+        constexpr int NW = HID / 32;
+        uint32_t w1[NW], w2[NW];
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
-          mp[w] = si.has ? w1[w] : 0u;
-          mp[NW + w] = si.has ? w2[w] : 0u;
+          w1[w] = 0u;
+          w2[w] = 0u;
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const uint32_t bit = 1u << (16 * (mt & 1) + 4 * g + r);
+            if (h1[mt][r] > 0.f) w1[mt >> 1] |= bit;
+            if (h2[mt][r] > 0.f) w2[mt >> 1] |= bit;
+          }
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          w1[w] |= __shfl_xor(w1[w], 16, 64);
+          w1[w] |= __shfl_xor(w1[w], 32, 64);
+          w2[w] |= __shfl_xor(w2[w], 16, 64);
+          w2[w] |= __shfl_xor(w2[w], 32, 64);
+        }
+        if (g == 0 && si.valid) {
+          uint32_t* mp = relu_masks + si.s * (2 * NW);
+#pragma unroll
+          for (int w = 0; w < NW; ++w) {
+            mp[w] = si.has ? w1[w] : 0u;
+            mp[NW + w] = si.has ? w2[w] : 0u;
+          }
+        }
+      }
+      if (g == 0 && si.valid) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          const float t = si.has ? 1.0f / (1.0f + __expf(-o[r])) : 0.0f;
+          tex[si.s * 3 + r] = t;
+          contrib[r] = fmaf(si.W, t, contrib[r]);
         }
       }
     }
-    float t3[3], contrib[3];
+    if (g == 0 && pix_valid) {
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      t3[r] = (si.has && g == 0) ? 1.0f / (1.0f + __expf(-o[r])) : 0.0f;
-      contrib[r] = si.W * t3[r];
-    }
-    for (int off = 1; off < K; off <<= 1)
-#pragma unroll
-      for (int r = 0; r < 3; ++r) contrib[r] += __shfl_xor(contrib[r], off, 64);
-    if (g == 0 && si.valid) {
-#pragma unroll
-      for (int r = 0; r < 3; ++r) tex[si.s * 3 + r] = t3[r];
-      if ((c & (K - 1)) == 0) {
-#pragma unroll
-        for (int r = 0; r < 3; ++r) image[si.p * 3 + r] = plain[si.p * 3 + r] + contrib[r];
-      }
+      for (int r = 0; r < 3; ++r) image[pix * 3 + r] = plain[pix * 3 + r] + contrib[r];
     }
   }
 }
@@ -513,6 +590,40 @@ __device__ __forceinline__ void weight_grad_tiles(const unsigned char* Y, const 
   }
 }
 
+// Sum of v[0..15] over the 16 lanes of a row (c = lane % 16) with 15
+// exchanges; lane c ends with the row total of value 8 b3 + 4 b2 + 2 b1 + b0
+// (b = bits of c).
+__device__ __forceinline__ float row_transpose_sum16(const float v[16], int c, int* which) {
+  float a8[8];
+  const bool h8 = c & 8;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const float send = h8 ? v[i] : v[i + 8];
+    const float keep = h8 ? v[i + 8] : v[i];
+    a8[i] = keep + __shfl_xor(send, 8, 64);
+  }
+  float a4[4];
+  const bool h4 = c & 4;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float send = h4 ? a8[i] : a8[i + 4];
+    const float keep = h4 ? a8[i + 4] : a8[i];
+    a4[i] = keep + __shfl_xor(send, 4, 64);
+  }
+  float a2[2];
+  const bool h2 = c & 2;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const float send = h2 ? a4[i] : a4[i + 2];
+    const float keep = h2 ? a4[i + 2] : a4[i];
+    a2[i] = keep + __shfl_xor(send, 2, 64);
+  }
+  const bool h1 = c & 1;
+  const float x = (h1 ? a2[1] : a2[0]) + __shfl_xor(h1 ? a2[0] : a2[1], 1, 64);
+  *which = (h8 ? 8 : 0) + (h4 ? 4 : 0) + (h2 ? 2 : 0) + (h1 ? 1 : 0);
+  return x;
+}
+
 template <int TDT, bool BF, int HID>
 __global__ __launch_bounds__(kTexThreads) void texture_backward_kernel(
     GridDev gd, const void* __restrict__ table, const void* w1, const void* w2, const void* w3, int in_dim, int K,
@@ -534,29 +645,19 @@ __global__ __launch_bounds__(kTexThreads) void texture_backward_kernel(
   unsigned char* tY = tbuf + wave * TL::wave_bytes;
   unsigned char* tX = tY + TL::tile_bytes;
   const uint32_t mask = (1u << gd.log2_size) - 1u;
-  const int64_t n_blk = (n_samples + 15) / 16;
+  const int64_t n_q = n_patches(gd);
   const f4 zero = {0.f, 0.f, 0.f, 0.f};
 
-  for (int64_t blk = (int64_t)blockIdx.x * kWaves + wave; blk < n_blk; blk += (int64_t)gridDim.x * kWaves) {
-    const SampleInfo si = sample_info(gd, K, log2K, n_samples, blk * 16 + c, ids, depths, weights);
-    // ---- recompute features
-    float z[8], fraw[8], delta[4], expo[4];
+  for (int64_t qj = (int64_t)blockIdx.x * kWaves + wave; qj < n_q * K; qj += (int64_t)gridDim.x * kWaves) {
+    const SampleInfo si = sample_info(gd, K, qj / K, (int)(qj % K), c, ids, depths, weights);
+    // ---- recompute features (all corner reads in flight together)
+    float z[8], fraw[8], delta[4];
+    LaneEntries<TDT> E;
+    gather_lane<TDT>(gd, table, si, g, mask, E, fraw, delta, nullptr);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int l = lane_level(g, i);
-      float2 f = make_float2(0.f, 0.f);
-      delta[i] = 0.f;
-      expo[i] = 1.f;
-      if (si.has && l < gd.levels) {
-        const LevelGeom lg = level_geom(gd.lv[l], si);
-        f = level_feature<TDT>(table, (uint32_t)l << gd.log2_size, mask, lg);
-        delta[i] = lg.delta;
-        expo[i] = lg.expo;
-      }
-      fraw[2 * i] = f.x;
-      fraw[2 * i + 1] = f.y;
-      z[2 * i] = f.x * delta[i];
-      z[2 * i + 1] = f.y * delta[i];
+      z[2 * i] = fraw[2 * i] * delta[i];
+      z[2 * i + 1] = fraw[2 * i + 1] * delta[i];
     }
     // ---- MLP forward, keeping activations
     f4 h1[MT], h2[MT];
@@ -676,38 +777,65 @@ __global__ __launch_bounds__(kTexThreads) void texture_backward_kernel(
     weight_grad_tiles<BF>(tY, tX, MT, 2, dw, kInPad, HID, in_dim, lane);
     wave_sync_lds();
     // ---- hash-grid backward and depth gradient
+    // When every active sample of a 16-lane row lies in the same cell of a
+    // level, the row's 8 corners x 2 features are summed across the row
+    // first (one transpose-reduce) and the row issues 16 atomics instead of
+    // up to 256.
     float dD = 0.f;
-    if (si.has) {
+    const uint64_t has_mask = __ballot(si.has);
+    const uint32_t row_has = (uint32_t)(has_mask >> (16 * g)) & 0xFFFFu;
+    const int leader = 16 * g + (row_has ? __builtin_ctz(row_has) : 0);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int l = lane_level(g, i);
-        if (l >= gd.levels) continue;
-        const float gz0 = i < 2 ? dzt[0][2 * i] : dzt[1][2 * (i - 2)];
-        const float gz1 = i < 2 ? dzt[0][2 * i + 1] : dzt[1][2 * (i - 2) + 1];
-        const GridLevel& L = gd.lv[l];
-        const LevelGeom lg = level_geom(L, si);
-        const float e0 = gz0 * delta[i], e1 = gz1 * delta[i];  // dL/dfeature (un-scaled)
-        const uint32_t base = (uint32_t)l << gd.log2_size;
-        float gpx = 0.f, gpy = 0.f, gpz = 0.f;
+    for (int i = 0; i < 4; ++i) {
+      const int l = lane_level(g, i);
+      const bool lvl_ok = l < gd.levels;
+      const bool active = E.act[i];
+      const GridLevel& L = gd.lv[lvl_ok ? l : 0];
+      const LevelGeom lg = level_geom(L, si);
+      const int mcx = active ? lg.cx : 0, mcy = active ? lg.cy : 0, mcz = active ? lg.cz : 0;
+      const int lcx = __shfl(mcx, leader, 64), lcy = __shfl(mcy, leader, 64), lcz = __shfl(mcz, leader, 64);
+      const bool same = !active || (mcx == lcx && mcy == lcy && mcz == lcz);
+      const uint32_t row_same = (uint32_t)(__ballot(same) >> (16 * g)) & 0xFFFFu;
+      const bool uniform = row_same == 0xFFFFu && row_has != 0u && lvl_ok;
+      const float gz0 = i < 2 ? dzt[0][2 * i] : dzt[1][2 * (i - 2)];
+      const float gz1 = i < 2 ? dzt[0][2 * i + 1] : dzt[1][2 * (i - 2) + 1];
+      const float e0 = active ? gz0 * delta[i] : 0.f, e1 = active ? gz1 * delta[i] : 0.f;
+      const uint32_t base = (uint32_t)(lvl_ok ? l : 0) << gd.log2_size;
+      float v[16];
+      float gpx = 0.f, gpy = 0.f, gpz = 0.f;
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-          const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
-          const uint32_t h = (lg.hx[bx] ^ lg.hy[by] ^ lg.hz[bz]) & mask;
-          const float wx = bx ? lg.frx : 1.f - lg.frx;
-          const float wy = by ? lg.fry : 1.f - lg.fry;
-          const float wz = bz ? lg.frz : 1.f - lg.frz;
-          const float w = wx * wy * wz;
-          const uint32_t idx = base + h;
-          if (g_table) {
-            unsafeAtomicAdd(&g_table[2 * idx], w * e0);
-            unsafeAtomicAdd(&g_table[2 * idx + 1], w * e1);
+      for (int b = 0; b < 8; ++b) {
+        const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
+        const float wx = bx ? lg.frx : 1.f - lg.frx;
+        const float wy = by ? lg.fry : 1.f - lg.fry;
+        const float wz = bz ? lg.frz : 1.f - lg.frz;
+        const float w = wx * wy * wz;
+        v[2 * b] = w * e0;
+        v[2 * b + 1] = w * e1;
+        const float2 th = entry_value<TDT>(E.ent[i][b]);
+        const float qv = th.x * e0 + th.y * e1;
+        gpx += qv * (bx ? 1.f : -1.f) * wy * wz;
+        gpy += qv * (by ? 1.f : -1.f) * wx * wz;
+        gpz += qv * (bz ? 1.f : -1.f) * wx * wy;
+      }
+      if (g_table) {
+        if (uniform) {
+          int which;
+          const float tot = row_transpose_sum16(v, c, &which);
+          const int b = which >> 1, bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
+          const uint32_t h = (map_positive(lcx + bx) ^ (map_positive(lcy + by) * kPrime1) ^
+                              (map_positive(lcz + bz) * kPrime2)) & mask;
+          if (tot != 0.f) unsafeAtomicAdd(&g_table[2 * (base + h) + (which & 1)], tot);
+        } else if (active) {
+#pragma unroll
+          for (int b = 0; b < 8; ++b) {
+            const uint32_t h = corner_hash(lg, b, mask);
+            unsafeAtomicAdd(&g_table[2 * (base + h)], v[2 * b]);
+            unsafeAtomicAdd(&g_table[2 * (base + h) + 1], v[2 * b + 1]);
           }
-          const float2 th = load_pair<TDT>(table, idx);
-          const float q = th.x * e0 + th.y * e1;
-          gpx += q * (bx ? 1.f : -1.f) * wy * wz;
-          gpy += q * (by ? 1.f : -1.f) * wx * wz;
-          gpz += q * (bz ? 1.f : -1.f) * wx * wy;
         }
+      }
+      if (active) {
         // p = s (o + D d): dp/dD = s d. Delta = 1 - exp(-kappa/D^2): dDelta/dD = -(1-Delta) 2 kappa / D^3.
         const float ddelta = -lg.expo * 2.0f * L.kappa / (si.D * si.D * si.D);
         dD += L.scale * (gpx * si.dx + gpy * si.dy + gpz * si.dz) +
@@ -749,8 +877,8 @@ template <int TDT, bool BF, int HID>
 hipError_t fwd_inst(const GridDev& gd, const void* table, const MlpDev& mlp, int K, int64_t n_samples,
                     const int32_t* ids, const float* depths, const float* weights, const float* plain, float* tex,
                     float* image, int32_t* cells, uint32_t* masks, hipStream_t s) {
-  const int64_t n_blk = (n_samples + 15) / 16;
-  int64_t grid = (n_blk + kWaves - 1) / kWaves;
+  const int64_t n_q = n_patches(gd);
+  int64_t grid = (n_q + kWaves - 1) / kWaves;
   if (grid > 4096) grid = 4096;
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL((texture_forward_kernel<TDT, BF, HID>), dim3((unsigned)grid), dim3(kTexThreads), 0, s, gd, table,
@@ -764,8 +892,8 @@ hipError_t bwd_inst(const GridDev& gd, const void* table, const MlpDev& mlp, int
                     const int32_t* ids, const float* depths, const float* weights, const float* grad_image,
                     const float* grad_tex, float* g_table, float* g0, float* g1, float* g2, float* grad_depth,
                     hipStream_t s) {
-  const int64_t n_blk = (n_samples + 15) / 16;
-  int64_t grid = (n_blk + kWaves - 1) / kWaves;
+  const int64_t n_q = n_patches(gd) * K;
+  int64_t grid = (n_q + kWaves - 1) / kWaves;
   if (grid > 1024) grid = 1024;
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL((texture_backward_kernel<TDT, BF, HID>), dim3((unsigned)grid), dim3(kTexThreads), 0, s, gd,
