@@ -60,7 +60,8 @@ def algorithmic(phase, st):
         "raster_forward": I * (4 + rec) + T * 8 + P * (12 + 12 * K + 8),
         "texture_forward": S * 24 + P * 24 + table,
         "zero_record_grads": N * 64,
-        "texture_backward": S * 16 + P * 12 + table + 2 * gtable,
+        "texture_backward": S * 16 + P * 12 + table + S * st["L"] * 8,
+        "hash_scatter": S * st["L"] * 8 + S * 4 + 2 * gtable,
         "raster_backward": I * (4 + rec) + T * 8 + P * (28 + 24 * K) + N * 120,
         "preprocess_backward": N * (36 + 4 + 64 + 2 * 60),
     }
@@ -145,7 +146,7 @@ def time_form(form, steps, warmup):
     return {"ms": ms, "wall_ms": 1000.0 * wall / steps, "phases": phases, "stats": st, "workload": wl}
 
 
-def cpu_baseline(sample_pixels=192, seed=0):
+def cpu_baseline(sample_pixels=1024, seed=0):
     """The FP64 oracle, as it stands, on a bounded pixel sample of the same workload."""
     import numpy as np
     import torch
@@ -177,7 +178,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=192)
+    ap.add_argument("--cpu-sample", type=int, default=1024)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run a plain elementwise copy of MIB MiB (read MIB, write MIB) three times, as the "
+                         "reference for scaling hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the rendering path has no multi-GPU code); got --gpus {args.gpus}",
@@ -217,6 +221,14 @@ def main():
         ph32 = {k: v[0] / max(v[1], 1) for k, v in f32["phases"].items()}
         line["fp32_form"] = {"value": round(P / (f32["ms"] / 1000.0) / 1e6, 2), "ms_per_step": round(f32["ms"], 4),
                              "phases_ms": {k: round(v, 4) for k, v in sorted(ph32.items(), key=lambda kv: -kv[1])}}
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.rand(n, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        line["copy_calibration_mib"] = args.copy_calibration
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         line["cpu_baseline"] = cpu_baseline(args.cpu_sample)

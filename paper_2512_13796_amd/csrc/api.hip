@@ -52,14 +52,16 @@ struct Layout {
   // N-part
   size_t depth_keys, tile_counts, rects, records, sort_k, sort_v, sort_tk, sort_tv, offsets, scan_blocks;
   // fixed-size parts
-  size_t tile_ranges, rec_grad, grad_depth;
+  size_t tile_ranges, rec_grad, grad_depth, feat_grad, weight_ops;
   // I-part
   size_t hist, inst_tiles, inst_ids, inst_tmp_tiles, inst_tmp_ids;
   size_t total;
 };
 
-Layout make_layout(int64_t n, int64_t n_pix, int K, int n_tiles, int64_t n_inst) {
+Layout make_layout(int64_t n, const nx::CamDev& cd, int K, int64_t n_inst) {
   Layout L{};
+  const int64_t n_pix = (int64_t)cd.width * cd.height;
+  const int n_tiles = cd.ntx * cd.nty;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
@@ -80,6 +82,8 @@ Layout make_layout(int64_t n, int64_t n_pix, int K, int n_tiles, int64_t n_inst)
   L.tile_ranges = take(8 * (size_t)n_tiles);
   L.rec_grad = take(sizeof(float) * nx::kRecGrad * nn);
   L.grad_depth = take(sizeof(float) * (size_t)(n_pix * (K > 0 ? K : 1)));
+  L.feat_grad = take(sizeof(float2) * (size_t)nx::feat_grad_elems(cd.width, cd.height, K));
+  L.weight_ops = take(K > 0 ? nx::kWeightOperandBytes : 0);
   const int64_t ni = n_inst > 0 ? n_inst : 1;
   const int64_t hist_n = ni > (int64_t)nn ? ni : (int64_t)nn;
   L.hist = take(4 * nx::radix_hist_words(hist_n));
@@ -335,7 +339,7 @@ int nx_workspace_size(nx_ctx* ctx, int64_t n_surfels, const nx_camera* cams, int
   if (!bytes) return fail(NX_ERR_INVALID, "bytes is NULL");
   if (n_surfels < 0 || max_instances < 0) return fail(NX_ERR_INVALID, "negative size");
   const nx::CamDev cd = make_cam(cams[0]);
-  const Layout L = make_layout(n_surfels, (int64_t)cd.width * cd.height, ctx->K, cd.ntx * cd.nty, max_instances);
+  const Layout L = make_layout(n_surfels, cd, ctx->K, max_instances);
   *bytes = L.total;
   return NX_OK;
 }
@@ -348,7 +352,7 @@ int nx_workspace_layout(nx_ctx* ctx, int64_t n_surfels, const nx_camera* cams, i
   if (!layout) return fail(NX_ERR_INVALID, "layout is NULL");
   if (n_surfels < 0 || n_instances < 0) return fail(NX_ERR_INVALID, "negative size");
   const nx::CamDev cd = make_cam(cams[0]);
-  const Layout L = make_layout(n_surfels, (int64_t)cd.width * cd.height, ctx->K, cd.ntx * cd.nty, n_instances);
+  const Layout L = make_layout(n_surfels, cd, ctx->K, n_instances);
   layout->depth_keys = L.depth_keys;
   layout->tile_counts = L.tile_counts;
   layout->rects = L.rects;
@@ -377,7 +381,7 @@ int nx_render_forward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* c
   const int n_tiles = cd.ntx * cd.nty;
   const int64_t n = surfels->n;
   const int64_t P = (int64_t)cd.width * cd.height;
-  const Layout L0 = make_layout(n, P, K, n_tiles, 0);
+  const Layout L0 = make_layout(n, cd, K, 0);
   if (workspace_required) *workspace_required = L0.total;
   if (!workspace || workspace_bytes < L0.total) {
     if (!workspace_required) return fail(NX_ERR_INVALID, "workspace too small and workspace_required is NULL");
@@ -415,7 +419,7 @@ int nx_render_forward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* c
   NX_CHECK_HIP(hipMemcpyAsync(ctx->pinned, offsets + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   NX_CHECK_HIP(hipStreamSynchronize(s));
   const int64_t n_inst = (int64_t)ctx->pinned[0];
-  const Layout L = make_layout(n, P, K, n_tiles, n_inst);
+  const Layout L = make_layout(n, cd, K, n_inst);
   out->n_instances = n_inst;
   if (workspace_required) *workspace_required = L.total;
   if (workspace_bytes < L.total) return fail(NX_ERR_WORKSPACE, "workspace too small for the tile instances");
@@ -474,14 +478,13 @@ int nx_render_backward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* 
     return fail(NX_ERR_INVALID, "saved forward outputs are NULL");
   if (!grad_image) return fail(NX_ERR_INVALID, "grad_image is NULL");
   if (!grads) return fail(NX_ERR_INVALID, "grads is NULL");
-  if (ctx->K > 0 && mlp->dims[1] != 64) return fail(NX_ERR_UNSUPPORTED, "backward supports hidden width 64");
   const int K = ctx->K;
   const nx::CamDev cd = make_cam(cams[0]);
   const int n_tiles = cd.ntx * cd.nty;
   const int64_t n = surfels->n;
   const int64_t P = (int64_t)cd.width * cd.height;
   if (saved->n_instances < 0) return fail(NX_ERR_INVALID, "saved n_instances is negative");
-  const Layout L = make_layout(n, P, K, n_tiles, saved->n_instances);
+  const Layout L = make_layout(n, cd, K, saved->n_instances);
   if (!workspace || workspace_bytes < L.total) return fail(NX_ERR_INVALID, "workspace does not match the forward");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   NX_CHECK_HIP(hipGetLastError());
@@ -500,10 +503,18 @@ int nx_render_backward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* 
     md.w[2] = mlp->w[2];
     md.in_dim = mlp->dims[0];
     md.hidden = mlp->dims[1];
-    PhaseTimer pt(ctx, "texture_backward", s);
-    NX_CHECK_HIP(nx::launch_texture_backward(K, ctx->feat_dtype, ctx->mlp_dtype, gd, grid->table, md, saved->ids,
-                                             saved->depths, saved->weights, saved->tex, grad_image, grad_tex,
-                                             grads->table, grads->mlp[0], grads->mlp[1], grads->mlp[2], gdepth, s));
+    float2* fgrad = grads->table ? at<float2>(ws, L.feat_grad) : nullptr;
+    {
+      PhaseTimer pt(ctx, "texture_backward", s);
+      NX_CHECK_HIP(nx::launch_texture_backward(K, ctx->feat_dtype, ctx->mlp_dtype, gd, grid->table, md, saved->ids,
+                                               saved->depths, saved->weights, grad_image, grad_tex, fgrad,
+                                               grads->mlp[0], grads->mlp[1], grads->mlp[2], gdepth,
+                                               at<unsigned char>(ws, L.weight_ops), s));
+    }
+    if (grads->table) {
+      PhaseTimer pt(ctx, "hash_scatter", s);
+      NX_CHECK_HIP(nx::launch_hash_scatter(K, gd, saved->depths, fgrad, grads->table, s));
+    }
   }
   {
   PhaseTimer pt(ctx, "raster_backward", s);

@@ -51,8 +51,10 @@ struct GridLevel {
   float kappa;      // (f / s_l)^2 / (2 pi), so Delta = -expm1(-kappa / D^2)
 };
 
+constexpr int kMaxLevels = 16;
+
 struct GridDev {
-  GridLevel lv[16];
+  GridLevel lv[kMaxLevels];
   int levels, log2_size;
   float rot[9];     // camera-to-world rotation (R^T), row-major
   float fx, fy, cx, cy;
@@ -109,10 +111,33 @@ hipError_t launch_texture_forward(int K, int feat_dtype, int mlp_dtype, const Gr
                                   const float* weights, const float* plain, float* tex, float* image,
                                   int32_t* cells, uint32_t* relu_masks, hipStream_t s);
 
+// Texture backward, first half: recompute features and MLP, back-propagate,
+// accumulate the MLP weight gradients and the depth gradient, and write the
+// gradient with respect to each level's interpolated feature pair (already
+// scaled by Delta_l) to feat_grad (layout below).
 hipError_t launch_texture_backward(int K, int feat_dtype, int mlp_dtype, const GridDev& grid, const void* table,
                                    const MlpDev& mlp, const int32_t* ids, const float* depths,
-                                   const float* weights, const float* tex, const float* grad_image,
-                                   const float* grad_tex, float* g_table, float* g_mlp0, float* g_mlp1,
-                                   float* g_mlp2, float* grad_depth, hipStream_t s);
+                                   const float* weights, const float* grad_image, const float* grad_tex,
+                                   float2* feat_grad, float* g_mlp0, float* g_mlp1, float* g_mlp2,
+                                   float* grad_depth, unsigned char* weight_ops, hipStream_t s);
+
+// Workspace section for the backward's MLP operand slots in global memory
+// (used for hidden width 128).
+constexpr size_t kWeightOperandBytes = 192 * 1024;
+
+// Texture backward, second half: distribute feat_grad over the 8 cell
+// corners of every level and add the result into g_table.
+hipError_t launch_hash_scatter(int K, const GridDev& grid, const float* depths, const float2* feat_grad,
+                               float* g_table, hipStream_t s);
+
+// The per-level feature gradients are stored for 4x4 pixel patches (row-major
+// over the image, ragged at the right and bottom edges): element
+// ((l * n_patches + q) * K + j) * 16 + c holds pixel c of patch q, slot j.
+inline int64_t feat_grad_patches(int width, int height) {
+  return (int64_t)((width + 3) / 4) * ((height + 3) / 4);
+}
+inline int64_t feat_grad_elems(int width, int height, int K) {
+  return (int64_t)kMaxLevels * feat_grad_patches(width, height) * (K > 0 ? K : 0) * 16;
+}
 
 }  // namespace nx

@@ -180,23 +180,39 @@ __device__ float weight_operand(int slot, int g, int c, int e, const void* w1, c
   }
 }
 
+// Writes operand slots [0, n_slots) to dst (LDS or global memory); this
+// thread handles elements first, first + stride, ...
 template <bool BF, int HID>
-__device__ void stage_weights(unsigned char* lds, int n_slots, const void* w1, const void* w2, const void* w3,
-                              int in_dim) {
+__device__ void stage_weights(unsigned char* dst, int n_slots, const void* w1, const void* w2, const void* w3,
+                              int in_dim, int first = threadIdx.x, int stride = kTexThreads) {
   constexpr int per = BF ? 8 : 1;
   const int total = n_slots * 64 * per;
-  for (int i = threadIdx.x; i < total; i += kTexThreads) {
+  for (int i = first; i < total; i += stride) {
     const int slot = i / (64 * per);
     const int lane = (i / per) % 64;
     const int e = i % per;
     const float v = weight_operand<BF, HID>(slot, lane >> 4, lane & 15, e, w1, w2, w3, in_dim);
     if constexpr (BF) {
-      reinterpret_cast<short*>(lds)[i] = f2bf(v);
+      reinterpret_cast<short*>(dst)[i] = f2bf(v);
     } else {
-      reinterpret_cast<float*>(lds)[i] = v;
+      reinterpret_cast<float*>(dst)[i] = v;
     }
   }
 }
+
+// The backward's operand slots in global memory, for widths whose slots do
+// not fit in LDS next to the weight-gradient accumulators.
+template <bool BF, int HID>
+__global__ void stage_weight_operands_kernel(unsigned char* wop, const void* w1, const void* w2, const void* w3,
+                                             int in_dim) {
+  stage_weights<BF, HID>(wop, WLayout<BF, HID>::nAll, w1, w2, w3, in_dim, blockIdx.x * blockDim.x + threadIdx.x,
+                         gridDim.x * blockDim.x);
+}
+
+static_assert(WLayout<false, 128>::nAll * WLayout<false, 128>::slot_bytes <= (int)kWeightOperandBytes,
+              "operand slots exceed their workspace section");
+static_assert(WLayout<true, 128>::nAll * WLayout<true, 128>::slot_bytes <= (int)kWeightOperandBytes,
+              "operand slots exceed their workspace section");
 
 template <bool BF>
 struct Operand;
@@ -300,9 +316,10 @@ struct SampleInfo {
 
 // Sample (pixel c of 4x4 patch q, slot j). Patches tile the image row-major;
 // lanes of a 16-lane row see the same slot of 16 neighbouring pixels, so at
-// coarse levels they usually share a hash-grid cell.
-__device__ __forceinline__ SampleInfo sample_info(const GridDev& gd, int K, int64_t q, int j, int c,
-                                                  const int32_t* ids, const float* depths, const float* weights) {
+// coarse levels they usually share a hash-grid cell. This part needs only the
+// sample's depth: has = valid, W = 0.
+__device__ __forceinline__ SampleInfo sample_ray(const GridDev& gd, int K, int64_t q, int j, int c,
+                                                 const float* depths) {
   SampleInfo si;
   const int npx = (gd.width + 3) >> 2;
   const int px = 4 * (int)(q % npx) + (c & 3);
@@ -310,15 +327,24 @@ __device__ __forceinline__ SampleInfo sample_info(const GridDev& gd, int K, int6
   si.valid = px < gd.width && py < gd.height;
   si.p = si.valid ? (int64_t)py * gd.width + px : 0;
   si.s = si.p * K + j;
-  const int id = si.valid ? ids[si.s] : -1;
-  si.has = id >= 0;
-  si.D = si.has ? depths[si.s] : 1.0f;
-  si.W = si.has ? weights[si.s] : 0.0f;
+  si.has = si.valid;
+  si.D = si.valid ? depths[si.s] : 1.0f;
+  si.W = 0.0f;
   const float cx = ((float)px + 0.5f - gd.cx) / gd.fx;
   const float cy = ((float)py + 0.5f - gd.cy) / gd.fy;
   si.dx = gd.rot[0] * cx + gd.rot[1] * cy + gd.rot[2];
   si.dy = gd.rot[3] * cx + gd.rot[4] * cy + gd.rot[5];
   si.dz = gd.rot[6] * cx + gd.rot[7] * cy + gd.rot[8];
+  return si;
+}
+
+__device__ __forceinline__ SampleInfo sample_info(const GridDev& gd, int K, int64_t q, int j, int c,
+                                                  const int32_t* ids, const float* depths, const float* weights) {
+  SampleInfo si = sample_ray(gd, K, q, j, c, depths);
+  const int id = si.valid ? ids[si.s] : -1;
+  si.has = id >= 0;
+  si.D = si.has ? si.D : 1.0f;
+  si.W = si.has ? weights[si.s] : 0.0f;
   return si;
 }
 
@@ -624,20 +650,30 @@ __device__ __forceinline__ float row_transpose_sum16(const float v[16], int c, i
   return x;
 }
 
-template <int TDT, bool BF, int HID>
+// WLDS: operand slots staged in LDS by every workgroup (hidden width 64), or
+// read from wop in global memory (L2-resident; hidden width 128, whose slots
+// and FP32 weight-gradient accumulators do not fit in LDS together).
+template <int TDT, bool BF, int HID, bool WLDS>
 __global__ __launch_bounds__(kTexThreads) void texture_backward_kernel(
-    GridDev gd, const void* __restrict__ table, const void* w1, const void* w2, const void* w3, int in_dim, int K,
+    GridDev gd, const void* __restrict__ table, const void* w1, const void* w2, const void* w3,
+    const unsigned char* __restrict__ wop, int in_dim, int K,
     int log2K, int64_t n_samples, const int32_t* __restrict__ ids, const float* __restrict__ depths,
     const float* __restrict__ weights, const float* __restrict__ grad_image, const float* __restrict__ grad_tex,
-    float* __restrict__ g_table, float* g_w1, float* g_w2, float* g_w3, float* __restrict__ grad_depth) {
+    float2* __restrict__ feat_grad, float* g_w1, float* g_w2, float* g_w3, float* __restrict__ grad_depth) {
   using LY = WLayout<BF, HID>;
   using TL = TLayout<BF, HID>;
   constexpr int MT = LY::MT;
   constexpr int nW1 = HID * kInPad, nW2 = HID * HID, nW3 = 16 * HID;
-  __shared__ __attribute__((aligned(16))) unsigned char lds[LY::nAll * LY::slot_bytes];
+  __shared__ __attribute__((aligned(16))) unsigned char lds[WLDS ? LY::nAll * LY::slot_bytes : 16];
   __shared__ __attribute__((aligned(16))) unsigned char tbuf[kWaves * TL::wave_bytes];
   __shared__ float dw[nW1 + nW2 + nW3];
-  stage_weights<BF, HID>(lds, LY::nAll, w1, w2, w3, in_dim);
+  const unsigned char* W;
+  if constexpr (WLDS) {
+    stage_weights<BF, HID>(lds, LY::nAll, w1, w2, w3, in_dim);
+    W = lds;
+  } else {
+    W = wop;
+  }
   for (int i = threadIdx.x; i < nW1 + nW2 + nW3; i += kTexThreads) dw[i] = 0.0f;
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -661,7 +697,7 @@ __global__ __launch_bounds__(kTexThreads) void texture_backward_kernel(
     }
     // ---- MLP forward, keeping activations
     f4 h1[MT], h2[MT];
-    const f4 o = mlp_forward<BF, HID>(lds, lane, z, h1, h2);
+    const f4 o = mlp_forward<BF, HID>(W, lane, z, h1, h2);
     // ---- head: dL/dlogit for rows 0..2 of lane group 0
     f4 dlog = zero;
     if (g == 0 && si.has) {
@@ -684,7 +720,7 @@ __global__ __launch_bounds__(kTexThreads) void texture_backward_kernel(
       for (int e = 0; e < 8; ++e) bd[e] = e < 4 ? f2bf(dlog[e]) : (short)0;
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
-        f4 a = mfma_bf16_k32(Operand<true>::get(lds, LY::oA3T + mt, lane), bd, zero);
+        f4 a = mfma_bf16_k32(Operand<true>::get(W, LY::oA3T + mt, lane), bd, zero);
 #pragma unroll
         for (int r = 0; r < 4; ++r) a[r] = h2[mt][r] > 0.f ? a[r] : 0.f;
         dh2[mt] = a;
@@ -696,7 +732,7 @@ __global__ __launch_bounds__(kTexThreads) void texture_backward_kernel(
       for (int mt = 0; mt < MT; ++mt) {
         f4 a = zero;
 #pragma unroll
-        for (int h = 0; h < HT; ++h) a = mfma_bf16_k32(Operand<true>::get(lds, LY::oA2T + mt * HT + h, lane), b2[h], a);
+        for (int h = 0; h < HT; ++h) a = mfma_bf16_k32(Operand<true>::get(W, LY::oA2T + mt * HT + h, lane), b2[h], a);
 #pragma unroll
         for (int r = 0; r < 4; ++r) a[r] = h1[mt][r] > 0.f ? a[r] : 0.f;
         dh1[mt] = a;
@@ -708,7 +744,7 @@ __global__ __launch_bounds__(kTexThreads) void texture_backward_kernel(
       for (int mz = 0; mz < 2; ++mz) {
         f4 a = zero;
 #pragma unroll
-        for (int h = 0; h < HT; ++h) a = mfma_bf16_k32(Operand<true>::get(lds, LY::oA1T + mz * HT + h, lane), b1[h], a);
+        for (int h = 0; h < HT; ++h) a = mfma_bf16_k32(Operand<true>::get(W, LY::oA1T + mz * HT + h, lane), b1[h], a);
         dzt[mz] = a;
       }
     } else {
@@ -716,7 +752,7 @@ __global__ __launch_bounds__(kTexThreads) void texture_backward_kernel(
       for (int mt = 0; mt < MT; ++mt) {
         f4 a = zero;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) a = mfma_f32_k4(Operand<false>::get(lds, LY::oA3T + mt * 4 + r, lane), dlog[r], a);
+        for (int r = 0; r < 4; ++r) a = mfma_f32_k4(Operand<false>::get(W, LY::oA3T + mt * 4 + r, lane), dlog[r], a);
 #pragma unroll
         for (int r = 0; r < 4; ++r) a[r] = h2[mt][r] > 0.f ? a[r] : 0.f;
         dh2[mt] = a;
@@ -728,7 +764,7 @@ __global__ __launch_bounds__(kTexThreads) void texture_backward_kernel(
         for (int mi = 0; mi < MT; ++mi)
 #pragma unroll
           for (int r = 0; r < 4; ++r)
-            a = mfma_f32_k4(Operand<false>::get(lds, LY::oA2T + (mt * MT + mi) * 4 + r, lane), dh2[mi][r], a);
+            a = mfma_f32_k4(Operand<false>::get(W, LY::oA2T + (mt * MT + mi) * 4 + r, lane), dh2[mi][r], a);
 #pragma unroll
         for (int r = 0; r < 4; ++r) a[r] = h1[mt][r] > 0.f ? a[r] : 0.f;
         dh1[mt] = a;
@@ -740,7 +776,7 @@ __global__ __launch_bounds__(kTexThreads) void texture_backward_kernel(
         for (int mi = 0; mi < MT; ++mi)
 #pragma unroll
           for (int r = 0; r < 4; ++r)
-            a = mfma_f32_k4(Operand<false>::get(lds, LY::oA1T + (mz * MT + mi) * 4 + r, lane), dh1[mi][r], a);
+            a = mfma_f32_k4(Operand<false>::get(W, LY::oA1T + (mz * MT + mi) * 4 + r, lane), dh1[mi][r], a);
         dzt[mz] = a;
       }
     }
@@ -776,66 +812,35 @@ __global__ __launch_bounds__(kTexThreads) void texture_backward_kernel(
     wave_sync_lds();
     weight_grad_tiles<BF>(tY, tX, MT, 2, dw, kInPad, HID, in_dim, lane);
     wave_sync_lds();
-    // ---- hash-grid backward and depth gradient
-    // When every active sample of a 16-lane row lies in the same cell of a
-    // level, the row's 8 corners x 2 features are summed across the row
-    // first (one transpose-reduce) and the row issues 16 atomics instead of
-    // up to 256.
+    // ---- per-level feature gradients (distributed over the cell corners by
+    // the hash-scatter kernel) and the depth gradient through the sample
+    // position and Delta_l
     float dD = 0.f;
-    const uint64_t has_mask = __ballot(si.has);
-    const uint32_t row_has = (uint32_t)(has_mask >> (16 * g)) & 0xFFFFu;
-    const int leader = 16 * g + (row_has ? __builtin_ctz(row_has) : 0);
+    const int64_t nqK = n_q * K;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int l = lane_level(g, i);
-      const bool lvl_ok = l < gd.levels;
       const bool active = E.act[i];
-      const GridLevel& L = gd.lv[lvl_ok ? l : 0];
-      const LevelGeom lg = level_geom(L, si);
-      const int mcx = active ? lg.cx : 0, mcy = active ? lg.cy : 0, mcz = active ? lg.cz : 0;
-      const int lcx = __shfl(mcx, leader, 64), lcy = __shfl(mcy, leader, 64), lcz = __shfl(mcz, leader, 64);
-      const bool same = !active || (mcx == lcx && mcy == lcy && mcz == lcz);
-      const uint32_t row_same = (uint32_t)(__ballot(same) >> (16 * g)) & 0xFFFFu;
-      const bool uniform = row_same == 0xFFFFu && row_has != 0u && lvl_ok;
       const float gz0 = i < 2 ? dzt[0][2 * i] : dzt[1][2 * (i - 2)];
       const float gz1 = i < 2 ? dzt[0][2 * i + 1] : dzt[1][2 * (i - 2) + 1];
       const float e0 = active ? gz0 * delta[i] : 0.f, e1 = active ? gz1 * delta[i] : 0.f;
-      const uint32_t base = (uint32_t)(lvl_ok ? l : 0) << gd.log2_size;
-      float v[16];
-      float gpx = 0.f, gpy = 0.f, gpz = 0.f;
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
-        const float wx = bx ? lg.frx : 1.f - lg.frx;
-        const float wy = by ? lg.fry : 1.f - lg.fry;
-        const float wz = bz ? lg.frz : 1.f - lg.frz;
-        const float w = wx * wy * wz;
-        v[2 * b] = w * e0;
-        v[2 * b + 1] = w * e1;
-        const float2 th = entry_value<TDT>(E.ent[i][b]);
-        const float qv = th.x * e0 + th.y * e1;
-        gpx += qv * (bx ? 1.f : -1.f) * wy * wz;
-        gpy += qv * (by ? 1.f : -1.f) * wx * wz;
-        gpz += qv * (bz ? 1.f : -1.f) * wx * wy;
-      }
-      if (g_table) {
-        if (uniform) {
-          int which;
-          const float tot = row_transpose_sum16(v, c, &which);
-          const int b = which >> 1, bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
-          const uint32_t h = (map_positive(lcx + bx) ^ (map_positive(lcy + by) * kPrime1) ^
-                              (map_positive(lcz + bz) * kPrime2)) & mask;
-          if (tot != 0.f) unsafeAtomicAdd(&g_table[2 * (base + h) + (which & 1)], tot);
-        } else if (active) {
-#pragma unroll
-          for (int b = 0; b < 8; ++b) {
-            const uint32_t h = corner_hash(lg, b, mask);
-            unsafeAtomicAdd(&g_table[2 * (base + h)], v[2 * b]);
-            unsafeAtomicAdd(&g_table[2 * (base + h) + 1], v[2 * b + 1]);
-          }
-        }
-      }
+      if (feat_grad && si.valid && l < gd.levels) feat_grad[((int64_t)l * nqK + qj) * 16 + c] = make_float2(e0, e1);
       if (active) {
+        const GridLevel& L = gd.lv[l];
+        const LevelGeom lg = level_geom(L, si);
+        float gpx = 0.f, gpy = 0.f, gpz = 0.f;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
+          const float wx = bx ? lg.frx : 1.f - lg.frx;
+          const float wy = by ? lg.fry : 1.f - lg.fry;
+          const float wz = bz ? lg.frz : 1.f - lg.frz;
+          const float2 th = entry_value<TDT>(E.ent[i][b]);
+          const float qv = th.x * e0 + th.y * e1;
+          gpx += qv * (bx ? 1.f : -1.f) * wy * wz;
+          gpy += qv * (by ? 1.f : -1.f) * wx * wz;
+          gpz += qv * (bz ? 1.f : -1.f) * wx * wy;
+        }
         // p = s (o + D d): dp/dD = s d. Delta = 1 - exp(-kappa/D^2): dDelta/dD = -(1-Delta) 2 kappa / D^3.
         const float ddelta = -lg.expo * 2.0f * L.kappa / (si.D * si.D * si.D);
         dD += L.scale * (gpx * si.dx + gpy * si.dy + gpz * si.dz) +
@@ -859,6 +864,136 @@ __global__ __launch_bounds__(kTexThreads) void texture_backward_kernel(
       const int q = i - nW1 - nW2, row = q / HID;
       if (g_w3 && row < 3) unsafeAtomicAdd(&g_w3[q], v);
     }
+  }
+}
+
+// ------------------------------------------------------------------ hash scatter
+// dL/dtheta for a table entry is the sum, over every sample and cell corner
+// that hashes to it, of the corner's trilinear weight times the sample's
+// feature gradient. One task is one level over a block of 4x4-pixel patches
+// (all K slots). Neighbouring samples share cells, so the workgroup first
+// sums its contributions per table entry in an LDS open-addressing map and
+// then adds each distinct entry to global memory once. Tasks run level-major,
+// so the workgroups in flight update one level's slice of the gradient table.
+constexpr int kScatThreads = 256;
+constexpr int kMapLog2 = 12;
+constexpr int kMapSlots = 1 << kMapLog2;
+constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
+constexpr int kMaxProbe = 32;
+constexpr int kScatUnits = 32;  // (patch, slot) units per task
+
+// Slot holding `key` in the map (linear probing), claimed if the key is new;
+// -1 if kMaxProbe consecutive slots hold other keys.
+__device__ __forceinline__ int map_claim(uint32_t* keys, uint32_t key) {
+  uint32_t slot = (key * kPrime1) >> (32 - kMapLog2);
+  for (int p = 0; p < kMaxProbe; ++p) {
+    const uint32_t old = atomicCAS(&keys[slot], kEmptyKey, key);
+    if (old == kEmptyKey || old == key) return (int)slot;
+    slot = (slot + 1) & (kMapSlots - 1);
+  }
+  return -1;
+}
+
+__device__ __forceinline__ void map_add(uint32_t* keys, float* vals, float* g_table, uint32_t key, int f, float v) {
+  const int slot = map_claim(keys, key);
+  if (slot >= 0) {
+    atomicAdd(&vals[2 * slot + f], v);
+  } else {
+    unsafeAtomicAdd(&g_table[2 * (size_t)key + f], v);
+  }
+}
+
+__global__ __launch_bounds__(kScatThreads) void hash_scatter_kernel(GridDev gd, int K, const float* __restrict__ depths,
+                                                                    const float2* __restrict__ feat_grad,
+                                                                    float* __restrict__ g_table, int bw, int bh,
+                                                                    int nbx, int nby) {
+  __shared__ uint32_t keys[kMapSlots];
+  __shared__ float vals[2 * kMapSlots];
+  for (int i = threadIdx.x; i < kMapSlots; i += kScatThreads) {
+    keys[i] = kEmptyKey;
+    vals[2 * i] = 0.f;
+    vals[2 * i + 1] = 0.f;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  const int row = threadIdx.x >> 4;
+  const uint32_t mask = (1u << gd.log2_size) - 1u;
+  const int npx = (gd.width + 3) >> 2, npy = (gd.height + 3) >> 2;
+  const int64_t n_q = (int64_t)npx * npy;
+  const int64_t nqK = n_q * K;
+  const int n_blocks = nbx * nby;
+  const int64_t n_tasks = (int64_t)n_blocks * gd.levels;
+  // Consecutive workgroup ids go to different XCDs; renumber so that each
+  // XCD walks neighbouring blocks (shared corner entries stay in its L2).
+  const int G = gridDim.x;
+  const int wg = (G % 8 == 0) ? (int)(blockIdx.x % 8) * (G / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
+  const int units = bw * bh * K;
+  for (int64_t task = wg; task < n_tasks; task += G) {
+    const int l = (int)(task / n_blocks), blk = (int)(task % n_blocks);
+    const int bx = blk % nbx, by = blk / nbx;
+    const GridLevel& L = gd.lv[l];
+    const uint32_t base = (uint32_t)l << gd.log2_size;
+    for (int u = row; u < units; u += kScatThreads / 16) {
+      const int pb = u / K, j = u % K;
+      const int qx = bx * bw + pb % bw, qy = by * bh + pb / bw;
+      const bool in = qx < npx && qy < npy;
+      const int64_t q = in ? (int64_t)qy * npx + qx : 0;
+      SampleInfo si = sample_ray(gd, K, q, j, c, depths);
+      float2 e = make_float2(0.f, 0.f);
+      if (in && si.valid) e = feat_grad[((int64_t)l * nqK + q * K + j) * 16 + c];
+      const bool act = in && si.valid && (e.x != 0.f || e.y != 0.f);
+      const LevelGeom lg = level_geom(L, si);
+      // If every contributing lane of the 16-lane row lies in one cell, sum
+      // the row's 8 corners x 2 features across the row first.
+      const uint32_t row_act = (uint32_t)(__ballot(act) >> (16 * g)) & 0xFFFFu;
+      const int leader = 16 * g + (row_act ? __builtin_ctz(row_act) : 0);
+      const int mcx = act ? lg.cx : 0, mcy = act ? lg.cy : 0, mcz = act ? lg.cz : 0;
+      const int lcx = __shfl(mcx, leader, 64), lcy = __shfl(mcy, leader, 64), lcz = __shfl(mcz, leader, 64);
+      const bool same = !act || (mcx == lcx && mcy == lcy && mcz == lcz);
+      const uint32_t row_same = (uint32_t)(__ballot(same) >> (16 * g)) & 0xFFFFu;
+      const bool uniform = row_same == 0xFFFFu && row_act != 0u;
+      float v[16];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const float w = corner_weight(lg, b);
+        v[2 * b] = act ? w * e.x : 0.f;
+        v[2 * b + 1] = act ? w * e.y : 0.f;
+      }
+      if (uniform) {
+        int which;
+        const float tot = row_transpose_sum16(v, c, &which);
+        const int b = which >> 1, cbx = b & 1, cby = (b >> 1) & 1, cbz = (b >> 2) & 1;
+        const uint32_t h = (map_positive(lcx + cbx) ^ (map_positive(lcy + cby) * kPrime1) ^
+                            (map_positive(lcz + cbz) * kPrime2)) & mask;
+        if (tot != 0.f) map_add(keys, vals, g_table, base + h, which & 1, tot);
+      } else if (act) {
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          const uint32_t key = base + corner_hash(lg, b, mask);
+          const int slot = map_claim(keys, key);
+          if (slot >= 0) {
+            atomicAdd(&vals[2 * slot], v[2 * b]);
+            atomicAdd(&vals[2 * slot + 1], v[2 * b + 1]);
+          } else {
+            unsafeAtomicAdd(&g_table[2 * (size_t)key], v[2 * b]);
+            unsafeAtomicAdd(&g_table[2 * (size_t)key + 1], v[2 * b + 1]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // Flush: neighbouring lanes carry the two features of one entry.
+    for (int i = threadIdx.x; i < 2 * kMapSlots; i += kScatThreads) {
+      const uint32_t key = keys[i >> 1];
+      if (key != kEmptyKey) {
+        const float val = vals[i];
+        if (val != 0.f) unsafeAtomicAdd(&g_table[2 * (size_t)key + (i & 1)], val);
+        vals[i] = 0.f;
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kMapSlots; i += kScatThreads) keys[i] = kEmptyKey;
+    __syncthreads();
   }
 }
 
@@ -890,15 +1025,20 @@ hipError_t fwd_inst(const GridDev& gd, const void* table, const MlpDev& mlp, int
 template <int TDT, bool BF, int HID>
 hipError_t bwd_inst(const GridDev& gd, const void* table, const MlpDev& mlp, int K, int64_t n_samples,
                     const int32_t* ids, const float* depths, const float* weights, const float* grad_image,
-                    const float* grad_tex, float* g_table, float* g0, float* g1, float* g2, float* grad_depth,
-                    hipStream_t s) {
+                    const float* grad_tex, float2* feat_grad, float* g0, float* g1, float* g2, float* grad_depth,
+                    unsigned char* wop, hipStream_t s) {
+  constexpr bool kWlds = HID <= 64;
   const int64_t n_q = n_patches(gd) * K;
   int64_t grid = (n_q + kWaves - 1) / kWaves;
   if (grid > 1024) grid = 1024;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL((texture_backward_kernel<TDT, BF, HID>), dim3((unsigned)grid), dim3(kTexThreads), 0, s, gd,
-                     table, mlp.w[0], mlp.w[1], mlp.w[2], mlp.in_dim, K, ilog2(K), n_samples, ids, depths, weights,
-                     grad_image, grad_tex, g_table, g0, g1, g2, grad_depth);
+  if constexpr (!kWlds) {
+    hipLaunchKernelGGL((stage_weight_operands_kernel<BF, HID>), dim3(64), dim3(256), 0, s, wop, mlp.w[0], mlp.w[1],
+                       mlp.w[2], mlp.in_dim);
+  }
+  hipLaunchKernelGGL((texture_backward_kernel<TDT, BF, HID, kWlds>), dim3((unsigned)grid), dim3(kTexThreads), 0, s,
+                     gd, table, mlp.w[0], mlp.w[1], mlp.w[2], wop, mlp.in_dim, K, ilog2(K), n_samples, ids, depths,
+                     weights, grad_image, grad_tex, feat_grad, g0, g1, g2, grad_depth);
   return hipGetLastError();
 }
 
@@ -920,18 +1060,32 @@ hipError_t fwd_by_table(int tdt, const GridDev& gd, const void* table, const Mlp
 template <bool BF, int HID>
 hipError_t bwd_by_table(int tdt, const GridDev& gd, const void* table, const MlpDev& mlp, int K, int64_t n,
                         const int32_t* ids, const float* depths, const float* weights, const float* gi,
-                        const float* gt, float* gtab, float* g0, float* g1, float* g2, float* gd_out,
-                        hipStream_t s) {
+                        const float* gt, float2* fg, float* g0, float* g1, float* g2, float* gd_out,
+                        unsigned char* wop, hipStream_t s) {
   switch (tdt) {
     case NX_F32:
-      return bwd_inst<NX_F32, BF, HID>(gd, table, mlp, K, n, ids, depths, weights, gi, gt, gtab, g0, g1, g2, gd_out, s);
+      return bwd_inst<NX_F32, BF, HID>(gd, table, mlp, K, n, ids, depths, weights, gi, gt, fg, g0, g1, g2, gd_out, wop,
+                                       s);
     case NX_F16:
-      return bwd_inst<NX_F16, BF, HID>(gd, table, mlp, K, n, ids, depths, weights, gi, gt, gtab, g0, g1, g2, gd_out, s);
+      return bwd_inst<NX_F16, BF, HID>(gd, table, mlp, K, n, ids, depths, weights, gi, gt, fg, g0, g1, g2, gd_out, wop,
+                                       s);
     case NX_BF16:
-      return bwd_inst<NX_BF16, BF, HID>(gd, table, mlp, K, n, ids, depths, weights, gi, gt, gtab, g0, g1, g2, gd_out,
-                                        s);
+      return bwd_inst<NX_BF16, BF, HID>(gd, table, mlp, K, n, ids, depths, weights, gi, gt, fg, g0, g1, g2, gd_out,
+                                        wop, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+int compute_units() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
 }
 
 }  // namespace
@@ -964,9 +1118,9 @@ hipError_t launch_texture_forward(int K, int feat_dtype, int mlp_dtype, const Gr
 
 hipError_t launch_texture_backward(int K, int feat_dtype, int mlp_dtype, const GridDev& grid, const void* table,
                                    const MlpDev& mlp, const int32_t* ids, const float* depths, const float* weights,
-                                   const float* tex, const float* grad_image, const float* grad_tex, float* g_table,
-                                   float* g_mlp0, float* g_mlp1, float* g_mlp2, float* grad_depth, hipStream_t s) {
-  (void)tex;
+                                   const float* grad_image, const float* grad_tex, float2* feat_grad, float* g_mlp0,
+                                   float* g_mlp1, float* g_mlp2, float* grad_depth, unsigned char* weight_ops,
+                                   hipStream_t s) {
   const int64_t P = (int64_t)grid.width * grid.height;
   if (K == 0) return hipSuccess;
   const int64_t n = P * K;
@@ -974,12 +1128,33 @@ hipError_t launch_texture_backward(int K, int feat_dtype, int mlp_dtype, const G
   const bool bf = mlp_dtype == NX_BF16;
   if (mlp.hidden == 64)
     return bf ? bwd_by_table<true, 64>(feat_dtype, grid, table, mlp, K, n, ids, depths, weights, grad_image, grad_tex,
-                                       g_table, g_mlp0, g_mlp1, g_mlp2, grad_depth, s)
+                                       feat_grad, g_mlp0, g_mlp1, g_mlp2, grad_depth, weight_ops, s)
               : bwd_by_table<false, 64>(feat_dtype, grid, table, mlp, K, n, ids, depths, weights, grad_image, grad_tex,
-                                        g_table, g_mlp0, g_mlp1, g_mlp2, grad_depth, s);
-  // Hidden width 128 would need more LDS than a workgroup has for the
-  // weight-gradient accumulators; the C ABI rejects it before launch.
+                                        feat_grad, g_mlp0, g_mlp1, g_mlp2, grad_depth, weight_ops, s);
+  if (mlp.hidden == 128)
+    return bf ? bwd_by_table<true, 128>(feat_dtype, grid, table, mlp, K, n, ids, depths, weights, grad_image,
+                                        grad_tex, feat_grad, g_mlp0, g_mlp1, g_mlp2, grad_depth, weight_ops, s)
+              : bwd_by_table<false, 128>(feat_dtype, grid, table, mlp, K, n, ids, depths, weights, grad_image,
+                                         grad_tex, feat_grad, g_mlp0, g_mlp1, g_mlp2, grad_depth, weight_ops, s);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_hash_scatter(int K, const GridDev& grid, const float* depths, const float2* feat_grad,
+                               float* g_table, hipStream_t s) {
+  if (K == 0 || grid.width == 0 || grid.height == 0 || grid.levels == 0 || !g_table) return hipSuccess;
+  // Block of bw x bh patches with bw * bh * K = kScatUnits.
+  const int np = K >= kScatUnits ? 1 : kScatUnits / K;
+  int bw = 1;
+  while (bw * bw < np) bw *= 2;
+  const int bh = np / bw > 0 ? np / bw : 1;
+  const int npx = (grid.width + 3) / 4, npy = (grid.height + 3) / 4;
+  const int nbx = (npx + bw - 1) / bw, nby = (npy + bh - 1) / bh;
+  const int64_t n_tasks = (int64_t)nbx * nby * grid.levels;
+  int64_t wgs = (int64_t)compute_units() * 3;
+  if (wgs > n_tasks) wgs = n_tasks;
+  hipLaunchKernelGGL(hash_scatter_kernel, dim3((unsigned)wgs), dim3(kScatThreads), 0, s, grid, K, depths, feat_grad,
+                     g_table, bw, bh, nbx, nby);
+  return hipGetLastError();
 }
 
 }  // namespace nx

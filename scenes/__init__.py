@@ -34,6 +34,8 @@ __all__ = [
     "Workload",
     "look_at",
     "make_workload",
+    "TrainWorkload",
+    "make_train_workload",
     "CONFIG_NAMES",
 ]
 
@@ -193,16 +195,16 @@ def _plane_quats(rng, normals):
     return _rot_to_quat_fast(rot)
 
 
-def _scales(rng, n, log_sd, clip=None):
-    s = np.exp(rng.normal(math.log(0.03), log_sd, (n, 2)))
+def _scales(rng, n, log_sd, clip=None, mean=0.03):
+    s = np.exp(rng.normal(math.log(mean), log_sd, (n, 2)))
     if clip is not None:
         s = np.clip(s, clip[0], clip[1])
     return s
 
 
-def _grid(rng, levels, log2_size, feat, dtype):
-    table = rng.uniform(-1e-2, 1e-2, (levels, 1 << log2_size, feat)).astype(np.float32)
-    scales = (16.0 * 1.5 ** np.arange(levels)).astype(np.float32)
+def _grid(rng, levels, log2_size, feat, dtype, amp=1e-2, base=16.0):
+    table = rng.uniform(-amp, amp, (levels, 1 << log2_size, feat)).astype(np.float32)
+    scales = (base * 1.5 ** np.arange(levels)).astype(np.float32)
     return HashGrid(torch.from_numpy(table).to(dtype), torch.from_numpy(scales))
 
 
@@ -231,7 +233,7 @@ def _uniform_scene(rng, n):
     return _pack_scene(means, quats, scales, opac, gammas, colors)
 
 
-def _planes_scene(rng, n_planar, n_clutter, n_planes=20, half=2.0):
+def _planes_scene(rng, n_planar, n_clutter, n_planes=20, half=2.0, scale_mean=0.03):
     """Surfels on random planes through the box [-half, half]^3 plus clutter."""
     normals = rng.standard_normal((n_planes, 3))
     normals /= np.linalg.norm(normals, axis=1, keepdims=True)
@@ -266,7 +268,7 @@ def _planes_scene(rng, n_planar, n_clutter, n_planes=20, half=2.0):
     means = np.concatenate([planar_means, clutter_means])
     quats = np.concatenate([planar_quats, clutter_quats])
     n = means.shape[0]
-    scales = _scales(rng, n, 0.5)
+    scales = _scales(rng, n, 0.5, mean=scale_mean)
     opac = rng.uniform(0.1, 0.99, n)
     colors = rng.uniform(0.0, 1.0, (n, 3))
     gammas = np.ones((n, 2))
@@ -404,3 +406,45 @@ def make_workload(config: int, seed: int = 0, *, n_surfels=None, width=None, hei
         target = _target_images(rng, cams)
         return Workload(CONFIG_NAMES[config], scene, cams, grid, mlp, kk, target)
     raise ValueError(f"unknown config {config}")
+
+
+@dataclasses.dataclass
+class TrainWorkload:
+    scene: Scene          # geometry and the colours the targets were made with
+    cameras: list         # training views first, the held-out view last
+    teacher_grid: HashGrid
+    teacher_mlp: MLP
+    init_colors: torch.Tensor
+    init_grid: HashGrid
+    init_mlp: MLP
+    K: int
+
+
+def make_train_workload(seed: int = 0, n_surfels: int = 3000, n_views: int = 7, width: int = 64,
+                        height: int = 64, K: int = 4) -> TrainWorkload:
+    """A small textured scene for the training check.
+
+    Surfels on 6 planes through [-2,2]^3 (no clutter) with scales around 0.15;
+    a teacher grid (8 levels x 2^14 x 2, entries U(-1,1), level scales
+    2 * 1.5^l so that the coarse levels stay above the pixel footprint at this
+    resolution) and a teacher MLP 16-64-64-3 give the targets a texture that
+    per-surfel colours cannot express (its output layer is scaled by 8 so the
+    texture varies by about 0.06 within a surfel). Cameras sit on an arc of radius 6 at
+    heights U(0.5, 1.5) looking at the origin; the held-out view lies between
+    two training views. The student starts from fresh colours U[0,1], a grid
+    U(-1e-2, 1e-2) with the same level scales, and a fresh MLP.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    scene = _planes_scene(rng, n_surfels, 0, n_planes=6, half=2.0, scale_mean=0.15)
+    angles = list(np.linspace(-0.7, 0.7, n_views - 1)) + [0.7 / (n_views - 2)]
+    cams = []
+    for a in angles:
+        eye = np.array([6.0 * math.sin(a), rng.uniform(0.5, 1.5), -6.0 * math.cos(a)])
+        cams.append(look_at(eye, (0.0, 0.0, 0.0), (0.0, -1.0, 0.0), width, height))
+    teacher_grid = _grid(rng, 8, 14, 2, torch.float32, amp=1.0, base=2.0)
+    teacher_mlp = _mlp(rng, [16, 64, 64, 3], torch.float32)
+    teacher_mlp.weights[2] = teacher_mlp.weights[2] * 8.0  # contrast: texture std ~0.1 within a surfel
+    init_colors = torch.from_numpy(rng.uniform(0.0, 1.0, (scene.n, 3)).astype(np.float32))
+    init_grid = _grid(rng, 8, 14, 2, torch.float32, amp=1e-2, base=2.0)
+    init_mlp = _mlp(rng, [16, 64, 64, 3], torch.float32)
+    return TrainWorkload(scene, cams, teacher_grid, teacher_mlp, init_colors, init_grid, init_mlp, K)
