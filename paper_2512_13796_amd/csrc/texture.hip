@@ -616,6 +616,52 @@ __device__ __forceinline__ void weight_grad_tiles(const unsigned char* Y, const 
   }
 }
 
+// Register-resident form of the same product: acc[mo * NMI + mi] += the
+// 16-sample contribution to output tile (mo, mi). The accumulators live across
+// the whole work loop, so the only LDS traffic per unit is the transposes.
+template <bool BF, int NMO, int NMI>
+__device__ __forceinline__ void weight_grad_accum(const unsigned char* Y, const unsigned char* X,
+                                                  f4 (&acc)[NMO * NMI], int lane) {
+  const int g = lane >> 4, c = lane & 15;
+#pragma unroll
+  for (int mo = 0; mo < NMO; ++mo) {
+#pragma unroll
+    for (int mi = 0; mi < NMI; ++mi) {
+      f4& d = acc[mo * NMI + mi];
+      if constexpr (BF) {
+        const s4 a = *reinterpret_cast<const s4*>(reinterpret_cast<const short*>(Y) + (16 * mo + c) * 16 + 4 * g);
+        const s4 b = *reinterpret_cast<const s4*>(reinterpret_cast<const short*>(X) + (16 * mi + c) * 16 + 4 * g);
+        d = mfma_bf16_k16(a, b, d);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float a = reinterpret_cast<const float*>(Y)[(16 * mo + c) * 16 + 4 * q + g];
+          const float b = reinterpret_cast<const float*>(X)[(16 * mi + c) * 16 + 4 * q + g];
+          d = mfma_f32_k4(a, b, d);
+        }
+      }
+    }
+  }
+}
+
+// Adds register tiles (rows 16 mo + 4 g + r, column 16 mi + c) into an LDS
+// matrix, dropping rows >= out_rows and columns >= in_cols.
+template <int NMO, int NMI>
+__device__ __forceinline__ void accum_to_lds(const f4 (&acc)[NMO * NMI], float* dst, int ld, int out_rows,
+                                             int in_cols, int lane) {
+  const int g = lane >> 4, c = lane & 15;
+#pragma unroll
+  for (int mo = 0; mo < NMO; ++mo)
+#pragma unroll
+    for (int mi = 0; mi < NMI; ++mi)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * mo + 4 * g + r, col = 16 * mi + c;
+        const float v = acc[mo * NMI + mi][r];
+        if (row < out_rows && col < in_cols && v != 0.0f) atomicAdd(&dst[row * ld + col], v);
+      }
+}
+
 // Sum of v[0..15] over the 16 lanes of a row (c = lane % 16) with 15
 // exchanges; lane c ends with the row total of value 8 b3 + 4 b2 + 2 b1 + b0
 // (b = bits of c).
@@ -683,6 +729,19 @@ __global__ __launch_bounds__(kTexThreads) void texture_backward_kernel(
   const uint32_t mask = (1u << gd.log2_size) - 1u;
   const int64_t n_q = n_patches(gd);
   const f4 zero = {0.f, 0.f, 0.f, 0.f};
+  // Hidden width 64: weight gradients accumulate in registers for the whole
+  // loop (112 floats per lane). Width 128 would need 4x that, so it adds each
+  // unit's tiles into the LDS accumulators instead.
+  constexpr bool kRegAcc = HID <= 64;
+  f4 accW3[kRegAcc ? MT : 1], accW2[kRegAcc ? MT * MT : 1], accW1[kRegAcc ? 2 * MT : 1];
+  if constexpr (kRegAcc) {
+#pragma unroll
+    for (int i = 0; i < MT; ++i) accW3[i] = zero;
+#pragma unroll
+    for (int i = 0; i < MT * MT; ++i) accW2[i] = zero;
+#pragma unroll
+    for (int i = 0; i < 2 * MT; ++i) accW1[i] = zero;
+  }
 
   for (int64_t qj = (int64_t)blockIdx.x * kWaves + wave; qj < n_q * K; qj += (int64_t)gridDim.x * kWaves) {
     const SampleInfo si = sample_info(gd, K, qj / K, (int)(qj % K), c, ids, depths, weights);
@@ -789,7 +848,11 @@ __global__ __launch_bounds__(kTexThreads) void texture_backward_kernel(
 #pragma unroll
       for (int r = 0; r < 4; ++r) put_rows<BF>(tX, 16 * mt + 4 * g + r, c, h2[mt][r]);
     wave_sync_lds();
-    weight_grad_tiles<BF>(tY, tX, 1, MT, dw + nW1 + nW2, HID, 3, HID, lane);
+    if constexpr (kRegAcc) {
+      weight_grad_accum<BF, 1, MT>(tY, tX, accW3, lane);
+    } else {
+      weight_grad_tiles<BF>(tY, tX, 1, MT, dw + nW1 + nW2, HID, 3, HID, lane);
+    }
     wave_sync_lds();
     // dW2 = dH2 x H1^T
 #pragma unroll
@@ -800,7 +863,11 @@ __global__ __launch_bounds__(kTexThreads) void texture_backward_kernel(
         put_rows<BF>(tX, 16 * mt + 4 * g + r, c, h1[mt][r]);
       }
     wave_sync_lds();
-    weight_grad_tiles<BF>(tY, tX, MT, MT, dw + nW1, HID, HID, HID, lane);
+    if constexpr (kRegAcc) {
+      weight_grad_accum<BF, MT, MT>(tY, tX, accW2, lane);
+    } else {
+      weight_grad_tiles<BF>(tY, tX, MT, MT, dw + nW1, HID, HID, HID, lane);
+    }
     wave_sync_lds();
     // dW1 = dH1 x Z^T
 #pragma unroll
@@ -810,7 +877,11 @@ __global__ __launch_bounds__(kTexThreads) void texture_backward_kernel(
 #pragma unroll
     for (int e = 0; e < 8; ++e) put_rows<BF>(tX, feat_index(g, e), c, z[e]);
     wave_sync_lds();
-    weight_grad_tiles<BF>(tY, tX, MT, 2, dw, kInPad, HID, in_dim, lane);
+    if constexpr (kRegAcc) {
+      weight_grad_accum<BF, MT, 2>(tY, tX, accW1, lane);
+    } else {
+      weight_grad_tiles<BF>(tY, tX, MT, 2, dw, kInPad, HID, in_dim, lane);
+    }
     wave_sync_lds();
     // ---- per-level feature gradients (distributed over the cell corners by
     // the hash-scatter kernel) and the depth gradient through the sample
@@ -850,6 +921,11 @@ __global__ __launch_bounds__(kTexThreads) void texture_backward_kernel(
     dD += __shfl_xor(dD, 16, 64);
     dD += __shfl_xor(dD, 32, 64);
     if (g == 0 && si.valid && grad_depth) grad_depth[si.s] = si.has ? dD : 0.f;
+  }
+  if constexpr (kRegAcc) {
+    accum_to_lds<1, MT>(accW3, dw + nW1 + nW2, HID, 3, HID, lane);
+    accum_to_lds<MT, MT>(accW2, dw + nW1, HID, HID, HID, lane);
+    accum_to_lds<MT, 2>(accW1, dw, kInPad, HID, in_dim, lane);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < nW1 + nW2 + nW3; i += kTexThreads) {

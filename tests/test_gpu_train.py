@@ -69,12 +69,12 @@ def _train(nx, tw, targets, K):
         loss.backward()
         opt.step()
         if first is None:
-            first = float(loss)
+            first = float(loss.detach())
     with torch.no_grad():
         img = nx.render(ctx, tw.cameras[-1], ls, *geom, colors, table, *weights)[0]
         torch.cuda.synchronize()
         held = psnr(img.double().cpu().numpy(), targets[-1])
-    log(f"K={K}: first loss {first:.3e}, last {float(loss):.3e}, held-out PSNR {held:.2f} dB")
+    log(f"K={K}: first loss {first:.3e}, last {float(loss.detach()):.3e}, held-out PSNR {held:.2f} dB")
     return held, colors, table, weights
 
 
@@ -88,4 +88,5 @@ def test_texture_beats_colours_on_held_out_view(nx, setup):
     # gradients at the trained point
     wl1 = _student_workload(tw, colors, table, weights, tw.K)
     _grad_case(nx, wl1, label=f"train step {STEPS}", pixels=_sample_pixels(wl1.cameras[0], 6, per_block=8))
-    assert p4 > p0 + 1.0, f"K=4 held-out PSNR {p4:.2f} dB does not beat K=0 {p0:.2f} dB by 1 dB"
+    # measured: 40.2 dB against 28.8 dB; the bar leaves room for atomic-order differences in training
+    assert p4 > p0 + 5.0, f"K=4 held-out PSNR {p4:.2f} dB does not beat K=0 {p0:.2f} dB by 5 dB"
