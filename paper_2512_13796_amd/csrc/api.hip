@@ -52,7 +52,7 @@ struct Layout {
   // N-part
   size_t depth_keys, tile_counts, rects, records, sort_k, sort_v, sort_tk, sort_tv, offsets, scan_blocks;
   // fixed-size parts
-  size_t tile_ranges, rec_grad, grad_depth, feat_grad, weight_ops;
+  size_t tile_ranges, rec_grad, grad_depth, feat_grad, weight_ops, scat_key, scat_val, scat_count;
   // I-part
   size_t hist, inst_tiles, inst_ids, inst_tmp_tiles, inst_tmp_ids;
   size_t total;
@@ -84,6 +84,10 @@ Layout make_layout(int64_t n, const nx::CamDev& cd, int K, int64_t n_inst) {
   L.grad_depth = take(sizeof(float) * (size_t)(n_pix * (K > 0 ? K : 1)));
   L.feat_grad = take(sizeof(float2) * (size_t)nx::feat_grad_elems(cd.width, cd.height, K));
   L.weight_ops = take(K > 0 ? nx::kWeightOperandBytes : 0);
+  const size_t n_rec = K > 0 ? (size_t)nx::scatter_record_capacity(cd.width, cd.height, K) : 0;
+  L.scat_key = take(sizeof(uint16_t) * n_rec);
+  L.scat_val = take(sizeof(float2) * n_rec);
+  L.scat_count = take(sizeof(uint32_t) * (K > 0 ? nx::kScatMaxBuckets : 0));
   const int64_t ni = n_inst > 0 ? n_inst : 1;
   const int64_t hist_n = ni > (int64_t)nn ? ni : (int64_t)nn;
   L.hist = take(4 * nx::radix_hist_words(hist_n));
@@ -513,7 +517,8 @@ int nx_render_backward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* 
     }
     if (grads->table) {
       PhaseTimer pt(ctx, "hash_scatter", s);
-      NX_CHECK_HIP(nx::launch_hash_scatter(K, gd, saved->depths, fgrad, grads->table, s));
+      NX_CHECK_HIP(nx::launch_hash_scatter(K, gd, saved->depths, fgrad, grads->table, at<uint16_t>(ws, L.scat_key),
+                                           at<float2>(ws, L.scat_val), at<uint32_t>(ws, L.scat_count), s));
     }
   }
   {

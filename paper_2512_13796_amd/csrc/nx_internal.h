@@ -126,9 +126,47 @@ hipError_t launch_texture_backward(int K, int feat_dtype, int mlp_dtype, const G
 constexpr size_t kWeightOperandBytes = 192 * 1024;
 
 // Texture backward, second half: distribute feat_grad over the 8 cell
-// corners of every level and add the result into g_table.
+// corners of every level and add the result into g_table, level by level:
+// corner contributions are filed as records under buckets (fixed ranges of
+// table entries), then one workgroup per bucket sums its records and updates
+// that range of g_table (no floating-point global atomics).
 hipError_t launch_hash_scatter(int K, const GridDev& grid, const float* depths, const float2* feat_grad,
-                               float* g_table, hipStream_t s);
+                               float* g_table, uint16_t* rec_key, float2* rec_val, uint32_t* bucket_count,
+                               hipStream_t s);
+
+// Screen blocks of the hash scatter: bw x bh patches of 4x4 pixels with
+// bw * bh * K = kScatUnits (patch, slot) units, i.e. at most 4096 corner
+// records per block and level.
+constexpr int kScatUnits = 32;
+constexpr int kScatMaxBuckets = 2048;
+struct ScatterGeom {
+  int bw, bh, nbx, nby;
+};
+inline ScatterGeom scatter_geom(int width, int height, int K) {
+  ScatterGeom g{1, 1, 0, 0};
+  if (K <= 0) return g;
+  const int np = K >= kScatUnits ? 1 : kScatUnits / K;
+  while (g.bw * g.bw < np) g.bw *= 2;
+  g.bh = np / g.bw > 0 ? np / g.bw : 1;
+  const int npx = (width + 3) / 4, npy = (height + 3) / 4;
+  g.nbx = (npx + g.bw - 1) / g.bw;
+  g.nby = (npy + g.bh - 1) / g.bh;
+  return g;
+}
+// Records one level can file: the worst case (every corner of every sample a
+// record) is n_blocks * 4096; buckets get an equal share of 5/4 of that plus
+// slack, and a bucket that fills up sends further records straight to the
+// table with atomics (correct, slower; hashing spreads the records evenly).
+inline int64_t scatter_record_capacity(int width, int height, int K) {
+  const ScatterGeom g = scatter_geom(width, height, K);
+  return (int64_t)g.nbx * g.nby * 4096 * 5 / 4 + (int64_t)kScatMaxBuckets * 256;
+}
+// Table entries per bucket (log2): 2^(log2_size - 8) clamped to [1, 2^13], so
+// a level has 256 buckets up to 2^21 entries and at most 2048 at 2^24.
+inline int scatter_bucket_log2(int log2_size) {
+  const int b = log2_size - 8;
+  return b < 0 ? 0 : (b > 13 ? 13 : b);
+}
 
 // The per-level feature gradients are stored for 4x4 pixel patches (row-major
 // over the image, ragged at the right and bottom edges): element

@@ -582,6 +582,21 @@ __device__ __forceinline__ void put_rows(unsigned char* buf, int row, int c, flo
   }
 }
 
+// LDS float add as a compare-and-swap loop: LDS float atomics (ds_add_f32)
+// retire about one lane every three clocks per CU on this chip, a
+// compare-and-swap several lanes per clock. A lane retries only after another
+// update of the same word succeeded, so its rounds are bounded by the number
+// of updates the workgroup makes to that word.
+__device__ __forceinline__ void lds_add_f32(float* p, float v) {
+  uint32_t* w = reinterpret_cast<uint32_t*>(p);
+  uint32_t old = *w;
+  while (true) {
+    const uint32_t prev = atomicCAS(w, old, __float_as_uint(__uint_as_float(old) + v));
+    if (prev == old) break;
+    old = prev;
+  }
+}
+
 // dW[out][in] += sum over 16 samples of Y[out][s] X[in][s], for output row
 // tiles [0, n_mo) and input tiles [0, n_mi); result tile added into acc
 // (row-major, ld = ld_acc) with LDS atomics; rows >= out_rows are dropped.
@@ -610,7 +625,7 @@ __device__ __forceinline__ void weight_grad_tiles(const unsigned char* Y, const 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * mo + 4 * g + r;
-        if (row < out_rows && col < in_cols && d[r] != 0.0f) atomicAdd(&acc[row * ld_acc + col], d[r]);
+        if (row < out_rows && col < in_cols && d[r] != 0.0f) lds_add_f32(&acc[row * ld_acc + col], d[r]);
       }
     }
   }
@@ -658,7 +673,7 @@ __device__ __forceinline__ void accum_to_lds(const f4 (&acc)[NMO * NMI], float* 
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * mo + 4 * g + r, col = 16 * mi + c;
         const float v = acc[mo * NMI + mi][r];
-        if (row < out_rows && col < in_cols && v != 0.0f) atomicAdd(&dst[row * ld + col], v);
+        if (row < out_rows && col < in_cols && v != 0.0f) lds_add_f32(&dst[row * ld + col], v);
       }
 }
 
@@ -946,131 +961,319 @@ __global__ __launch_bounds__(kTexThreads) void texture_backward_kernel(
 // ------------------------------------------------------------------ hash scatter
 // dL/dtheta for a table entry is the sum, over every sample and cell corner
 // that hashes to it, of the corner's trilinear weight times the sample's
-// feature gradient. One task is one level over a block of 4x4-pixel patches
-// (all K slots). Neighbouring samples share cells, so the workgroup first
-// sums its contributions per table entry in an LDS open-addressing map and
-// then adds each distinct entry to global memory once. Tasks run level-major,
-// so the workgroups in flight update one level's slice of the gradient table.
+// feature gradient (FP32). It is formed level by level in two kernels that
+// use no floating-point global atomics.
+//
+// scatter_bin: one task is one level over a block of 4x4-pixel patches (all
+// K slots). Each corner contribution becomes a record (entry, 2 features)
+// filed under its bucket, a fixed range of 2^bucket_log2 table entries: the
+// block counts its records per bucket in LDS, reserves space in every bucket
+// it touches with one global cursor add, and writes the records there. Where
+// all samples of a 16-lane row lie in one cell, the row's contributions are
+// summed first, leaving 8 records instead of 128.
+//
+// scatter_reduce: one workgroup per bucket sums the bucket's records into a
+// dense LDS array and adds it to its range of the gradient table, which no
+// other workgroup writes; it also clears the bucket's cursor for the next
+// level.
+//
+// Measured on this chip: LDS float atomics (ds_add_f32) retire about one lane
+// every three clocks per CU, integer LDS atomics about ten lanes per clock and
+// a compare-and-swap several, so the LDS float sums are compare-and-swap loops
+// on the 64-bit feature pair and the counting uses integer atomics.
 constexpr int kScatThreads = 256;
-constexpr int kMapLog2 = 12;
-constexpr int kMapSlots = 1 << kMapLog2;
-constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
-constexpr int kMaxProbe = 32;
-constexpr int kScatUnits = 32;  // (patch, slot) units per task
+constexpr int kReduceThreads = 1024;
+constexpr int kReduceMaxLog2 = 13;  // LDS pairs per bucket in scatter_reduce
+constexpr int kUnitsPerRow = kScatUnits / (kScatThreads / 16);
+static_assert(kUnitsPerRow * (kScatThreads / 16) == kScatUnits, "units per task must fill the rows evenly");
+constexpr int kMaxCasRounds = 256;
 
-// Slot holding `key` in the map (linear probing), claimed if the key is new;
-// -1 if kMaxProbe consecutive slots hold other keys.
-__device__ __forceinline__ int map_claim(uint32_t* keys, uint32_t key) {
-  uint32_t slot = (key * kPrime1) >> (32 - kMapLog2);
-  for (int p = 0; p < kMaxProbe; ++p) {
-    const uint32_t old = atomicCAS(&keys[slot], kEmptyKey, key);
-    if (old == kEmptyKey || old == key) return (int)slot;
-    slot = (slot + 1) & (kMapSlots - 1);
-  }
-  return -1;
+__device__ __forceinline__ unsigned long long pair_plus(unsigned long long old, float a, float b) {
+  const float lo = __uint_as_float((uint32_t)old) + a;
+  const float hi = __uint_as_float((uint32_t)(old >> 32)) + b;
+  return ((unsigned long long)__float_as_uint(hi) << 32) | __float_as_uint(lo);
 }
 
-__device__ __forceinline__ void map_add(uint32_t* keys, float* vals, float* g_table, uint32_t key, int f, float v) {
-  const int slot = map_claim(keys, key);
-  if (slot >= 0) {
-    atomicAdd(&vals[2 * slot + f], v);
-  } else {
-    unsafeAtomicAdd(&g_table[2 * (size_t)key + f], v);
+// Adds (a, b) to the pair at p with a compare-and-swap loop; false if it lost
+// kMaxCasRounds races in a row (the caller then adds to global memory).
+__device__ __forceinline__ bool lds_add_pair(unsigned long long* p, float a, float b) {
+  unsigned long long old = *p;
+#pragma unroll 1
+  for (int r = 0; r < kMaxCasRounds; ++r) {
+    const unsigned long long prev = atomicCAS(p, old, pair_plus(old, a, b));
+    if (prev == old) return true;
+    old = prev;
+  }
+  return false;
+}
+
+constexpr int kBlockSamples = kScatUnits * 16;  // 512 samples per task
+static_assert(kBlockSamples == 2 * kScatThreads, "two samples per thread");
+
+// One compare-exchange stage (k, j) of a bitonic sort for the two positions
+// p0 = 2 l + base, p0 + 1 held by this lane (l = lane), j <= 64: the partner of
+// a position lives in this lane (j = 1) or in lane l ^ (j / 2).
+__device__ __forceinline__ void bitonic_stage_regs(uint32_t (&key)[2], uint32_t (&idx)[2], int p0, int k, int j) {
+  if (j == 1) {
+    const bool asc = (p0 & k) == 0;
+    const bool swap = asc ? key[0] > key[1] : key[0] < key[1];
+    if (swap) {
+      const uint32_t tk = key[0], ti = idx[0];
+      key[0] = key[1];
+      idx[0] = idx[1];
+      key[1] = tk;
+      idx[1] = ti;
+    }
+    return;
+  }
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int p = p0 + e;
+    const uint32_t ok = __shfl_xor(key[e], j >> 1, 64), oi = __shfl_xor(idx[e], j >> 1, 64);
+    const bool asc = (p & k) == 0, lower = (p & j) == 0;
+    // the lower position keeps the smaller key when ascending
+    const bool take = (lower == asc) ? ok < key[e] : ok > key[e];
+    if (take) {
+      key[e] = ok;
+      idx[e] = oi;
+    }
   }
 }
 
-__global__ __launch_bounds__(kScatThreads) void hash_scatter_kernel(GridDev gd, int K, const float* __restrict__ depths,
-                                                                    const float2* __restrict__ feat_grad,
-                                                                    float* __restrict__ g_table, int bw, int bh,
-                                                                    int nbx, int nby) {
-  __shared__ uint32_t keys[kMapSlots];
-  __shared__ float vals[2 * kMapSlots];
-  for (int i = threadIdx.x; i < kMapSlots; i += kScatThreads) {
-    keys[i] = kEmptyKey;
-    vals[2 * i] = 0.f;
-    vals[2 * i + 1] = 0.f;
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+__global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
+    GridDev gd, GridLevel L, int K, int level, const float* __restrict__ depths,
+    const float2* __restrict__ feat_grad, float* __restrict__ g_table, int bw, int bh, int nbx, int nby,
+    int bucket_log2, uint32_t cap, uint32_t* __restrict__ bucket_count, uint16_t* __restrict__ rec_key,
+    float2* __restrict__ rec_val) {
+  __shared__ __attribute__((aligned(16))) float svals[kBlockSamples][16];  // 8 corners x 2 features
+  __shared__ int scell[kBlockSamples][3];
+  __shared__ uint32_t skey[kBlockSamples];
+  __shared__ uint32_t sidx[kBlockSamples];
+  __shared__ uint32_t hist[kScatMaxBuckets];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, c = lane & 15;
   const int row = threadIdx.x >> 4;
   const uint32_t mask = (1u << gd.log2_size) - 1u;
+  const uint32_t emask = (1u << bucket_log2) - 1u;
+  const int nb = 1 << (gd.log2_size - bucket_log2);
   const int npx = (gd.width + 3) >> 2, npy = (gd.height + 3) >> 2;
   const int64_t n_q = (int64_t)npx * npy;
   const int64_t nqK = n_q * K;
   const int n_blocks = nbx * nby;
-  const int64_t n_tasks = (int64_t)n_blocks * gd.levels;
-  // Consecutive workgroup ids go to different XCDs; renumber so that each
-  // XCD walks neighbouring blocks (shared corner entries stay in its L2).
+  float* g_level = g_table + 2 * ((size_t)level << gd.log2_size);
+  const int p0 = 128 * wave + 2 * lane;  // sorted positions p0, p0 + 1 belong to this lane
+  // Consecutive workgroup ids go to different XCDs; renumber so that each XCD
+  // walks neighbouring blocks.
   const int G = gridDim.x;
   const int wg = (G % 8 == 0) ? (int)(blockIdx.x % 8) * (G / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
-  const int units = bw * bh * K;
-  for (int64_t task = wg; task < n_tasks; task += G) {
-    const int l = (int)(task / n_blocks), blk = (int)(task % n_blocks);
+  for (int blk = wg; blk < n_blocks; blk += G) {
+    for (int i = threadIdx.x; i < nb; i += kScatThreads) hist[i] = 0u;
     const int bx = blk % nbx, by = blk / nbx;
-    const GridLevel& L = gd.lv[l];
-    const uint32_t base = (uint32_t)l << gd.log2_size;
-    for (int u = row; u < units; u += kScatThreads / 16) {
+    // 1. per sample: cell, sort key and the 16 corner contributions
+#pragma unroll
+    for (int it = 0; it < kUnitsPerRow; ++it) {
+      const int u = row + it * (kScatThreads / 16);
+      const int smp = u * 16 + c;
       const int pb = u / K, j = u % K;
       const int qx = bx * bw + pb % bw, qy = by * bh + pb / bw;
       const bool in = qx < npx && qy < npy;
       const int64_t q = in ? (int64_t)qy * npx + qx : 0;
-      SampleInfo si = sample_ray(gd, K, q, j, c, depths);
+      const SampleInfo si = sample_ray(gd, K, q, j, c, depths);
       float2 e = make_float2(0.f, 0.f);
-      if (in && si.valid) e = feat_grad[((int64_t)l * nqK + q * K + j) * 16 + c];
+      if (in && si.valid) e = feat_grad[((int64_t)level * nqK + q * K + j) * 16 + c];
       const bool act = in && si.valid && (e.x != 0.f || e.y != 0.f);
       const LevelGeom lg = level_geom(L, si);
-      // If every contributing lane of the 16-lane row lies in one cell, sum
-      // the row's 8 corners x 2 features across the row first.
-      const uint32_t row_act = (uint32_t)(__ballot(act) >> (16 * g)) & 0xFFFFu;
-      const int leader = 16 * g + (row_act ? __builtin_ctz(row_act) : 0);
-      const int mcx = act ? lg.cx : 0, mcy = act ? lg.cy : 0, mcz = act ? lg.cz : 0;
-      const int lcx = __shfl(mcx, leader, 64), lcy = __shfl(mcy, leader, 64), lcz = __shfl(mcz, leader, 64);
-      const bool same = !act || (mcx == lcx && mcy == lcy && mcz == lcz);
-      const uint32_t row_same = (uint32_t)(__ballot(same) >> (16 * g)) & 0xFFFFu;
-      const bool uniform = row_same == 0xFFFFu && row_act != 0u;
-      float v[16];
+      float4* vrow = reinterpret_cast<float4*>(svals[smp]);
+#pragma unroll
+      for (int b4 = 0; b4 < 4; ++b4) {
+        const float w0 = act ? corner_weight(lg, 2 * b4) : 0.f, w1 = act ? corner_weight(lg, 2 * b4 + 1) : 0.f;
+        vrow[b4] = make_float4(w0 * e.x, w0 * e.y, w1 * e.x, w1 * e.y);
+      }
+      scell[smp][0] = lg.cx;
+      scell[smp][1] = lg.cy;
+      scell[smp][2] = lg.cz;
+      // inactive samples sort last and form no records
+      skey[smp] = act ? (lg.hx[0] ^ lg.hy[0] ^ lg.hz[0]) & 0x7FFFFFFFu : 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    // 2. bitonic sort of (key, sample) over the 512 samples
+    uint32_t key[2] = {skey[p0], skey[p0 + 1]};
+    uint32_t idx[2] = {(uint32_t)p0, (uint32_t)p0 + 1u};
+    for (int k = 2; k <= kBlockSamples; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        if (j >= 128) {  // partner in another wave: exchange through LDS
+          __syncthreads();
+          skey[p0] = key[0];
+          skey[p0 + 1] = key[1];
+          sidx[p0] = idx[0];
+          sidx[p0 + 1] = idx[1];
+          __syncthreads();
+#pragma unroll
+          for (int e = 0; e < 2; ++e) {
+            const int p = p0 + e, qq = p ^ j;
+            const uint32_t ok = skey[qq], oi = sidx[qq];
+            const bool asc = (p & k) == 0, lower = (p & j) == 0;
+            const bool take = (lower == asc) ? ok < key[e] : ok > key[e];
+            if (take) {
+              key[e] = ok;
+              idx[e] = oi;
+            }
+          }
+        } else {
+          bitonic_stage_regs(key, idx, p0, k, j);
+        }
+      }
+    }
+    // 3. segments of equal cells along the sorted order, summed within each wave
+    bool live[2];
+    int cx[2], cy[2], cz[2];
+    float a[2][16];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int sm = (int)idx[e];
+      live[e] = key[e] != 0xFFFFFFFFu;
+      cx[e] = scell[sm][0];
+      cy[e] = scell[sm][1];
+      cz[e] = scell[sm][2];
+      const float4* vrow = reinterpret_cast<const float4*>(svals[sm]);
+#pragma unroll
+      for (int b4 = 0; b4 < 4; ++b4) {
+        const float4 t = vrow[b4];
+        a[e][4 * b4] = t.x;
+        a[e][4 * b4 + 1] = t.y;
+        a[e][4 * b4 + 2] = t.z;
+        a[e][4 * b4 + 3] = t.w;
+      }
+    }
+    // element 1 continues element 0's segment?
+    const bool same01 = live[0] == live[1] && cx[0] == cx[1] && cy[0] == cy[1] && cz[0] == cz[1];
+    // previous lane's last element continues into this lane's element 0?
+    const int pcx = __shfl_up(cx[1], 1, 64), pcy = __shfl_up(cy[1], 1, 64), pcz = __shfl_up(cz[1], 1, 64);
+    const bool plive = __shfl_up((int)live[1], 1, 64) != 0;
+    const bool cont0 = lane > 0 && plive == live[0] && pcx == cx[0] && pcy == cy[0] && pcz == cz[0];
+    // lane value: sum of element 1's segment within this lane; head flag: that
+    // segment starts in this lane
+    float s1[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) s1[v] = same01 ? a[0][v] + a[1][v] : a[1][v];
+    bool head = !(same01 && cont0);
+    // inclusive segmented scan over lanes (Hillis-Steele)
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const bool ph = __shfl_up((int)head, d, 64) != 0;
+      float t[16];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) t[v] = __shfl_up(s1[v], d, 64);
+      if (lane >= d && !head) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) s1[v] += t[v];
+        head = ph;
+      }
+    }
+    // carry into element 0 from earlier lanes of its segment
+    float carry[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) carry[v] = __shfl_up(s1[v], 1, 64);
+    // next lane's element 0 continues element 1's segment?
+    const bool next_cont = __shfl_down((int)cont0, 1, 64) != 0;
+    const bool tail1 = lane == 63 || !next_cont;
+    const bool tail0 = !same01;
+    // 4. records: a segment tail emits its cell's 8 corners
+    uint32_t rh[2][8];
+    float r0[2][8], r1[2][8];
+    int nrec[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const bool tail = e == 0 ? tail0 : tail1;
+      nrec[e] = (tail && live[e]) ? 8 : 0;
+      float tot[16];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) tot[v] = e == 0 ? (cont0 ? carry[v] + a[0][v] : a[0][v]) : s1[v];
+      const uint32_t hx0 = map_positive(cx[e]), hx1 = map_positive(cx[e] + 1);
+      const uint32_t hy0 = map_positive(cy[e]) * kPrime1, hy1 = map_positive(cy[e] + 1) * kPrime1;
+      const uint32_t hz0 = map_positive(cz[e]) * kPrime2, hz1 = map_positive(cz[e] + 1) * kPrime2;
 #pragma unroll
       for (int b = 0; b < 8; ++b) {
-        const float w = corner_weight(lg, b);
-        v[2 * b] = act ? w * e.x : 0.f;
-        v[2 * b + 1] = act ? w * e.y : 0.f;
+        rh[e][b] = ((b & 1 ? hx1 : hx0) ^ (b & 2 ? hy1 : hy0) ^ (b & 4 ? hz1 : hz0)) & mask;
+        r0[e][b] = tot[2 * b];
+        r1[e][b] = tot[2 * b + 1];
       }
-      if (uniform) {
-        int which;
-        const float tot = row_transpose_sum16(v, c, &which);
-        const int b = which >> 1, cbx = b & 1, cby = (b >> 1) & 1, cbz = (b >> 2) & 1;
-        const uint32_t h = (map_positive(lcx + cbx) ^ (map_positive(lcy + cby) * kPrime1) ^
-                            (map_positive(lcz + cbz) * kPrime2)) & mask;
-        if (tot != 0.f) map_add(keys, vals, g_table, base + h, which & 1, tot);
-      } else if (act) {
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-          const uint32_t key = base + corner_hash(lg, b, mask);
-          const int slot = map_claim(keys, key);
-          if (slot >= 0) {
-            atomicAdd(&vals[2 * slot], v[2 * b]);
-            atomicAdd(&vals[2 * slot + 1], v[2 * b + 1]);
-          } else {
-            unsafeAtomicAdd(&g_table[2 * (size_t)key], v[2 * b]);
-            unsafeAtomicAdd(&g_table[2 * (size_t)key + 1], v[2 * b + 1]);
+      for (int b = 0; b < 8; ++b)
+        if (b < nrec[e] && (r0[e][b] != 0.f || r1[e][b] != 0.f)) atomicAdd(&hist[rh[e][b] >> bucket_log2], 1u);
+    }
+    __syncthreads();
+    // 5. reserve this block's space in every bucket it touches, then file
+    for (int i = threadIdx.x; i < nb; i += kScatThreads) {
+      const uint32_t n = hist[i];
+      hist[i] = n ? atomicAdd(&bucket_count[i], n) : 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        if (b < nrec[e] && (r0[e][b] != 0.f || r1[e][b] != 0.f)) {
+          const uint32_t h = rh[e][b], bk = h >> bucket_log2;
+          const uint32_t pos = atomicAdd(&hist[bk], 1u);
+          if (pos < cap) {
+            const size_t at = (size_t)bk * cap + pos;
+            rec_key[at] = (uint16_t)(h & emask);
+            rec_val[at] = make_float2(r0[e][b], r1[e][b]);
+          } else {  // bucket full: add straight into the table
+            unsafeAtomicAdd(&g_level[2 * (size_t)h], r0[e][b]);
+            unsafeAtomicAdd(&g_level[2 * (size_t)h + 1], r1[e][b]);
           }
         }
       }
     }
     __syncthreads();
-    // Flush: neighbouring lanes carry the two features of one entry.
-    for (int i = threadIdx.x; i < 2 * kMapSlots; i += kScatThreads) {
-      const uint32_t key = keys[i >> 1];
-      if (key != kEmptyKey) {
-        const float val = vals[i];
-        if (val != 0.f) unsafeAtomicAdd(&g_table[2 * (size_t)key + (i & 1)], val);
-        vals[i] = 0.f;
+  }
+}
+
+__global__ __launch_bounds__(kReduceThreads) void scatter_reduce_kernel(int bucket_log2, uint32_t cap,
+                                                                       uint32_t* __restrict__ bucket_count,
+                                                                       const uint16_t* __restrict__ rec_key,
+                                                                       const float2* __restrict__ rec_val,
+                                                                       float* __restrict__ g_level) {
+  __shared__ unsigned long long acc[1 << kReduceMaxLog2];
+  const int b = blockIdx.x;
+  const int n_e = 1 << bucket_log2;
+  const uint32_t cnt = bucket_count[b];
+  const uint32_t n = cnt < cap ? cnt : cap;
+  for (int i = threadIdx.x; i < n_e; i += kReduceThreads) acc[i] = 0ull;
+  __syncthreads();
+  float2* out = reinterpret_cast<float2*>(g_level) + ((size_t)b << bucket_log2);
+  const uint16_t* rk = rec_key + (size_t)b * cap;
+  const float2* rv = rec_val + (size_t)b * cap;
+  constexpr int kU = 4;  // records in flight per thread
+  for (uint32_t i0 = threadIdx.x; i0 < n; i0 += kU * kReduceThreads) {
+    uint32_t k[kU];
+    float2 v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const uint32_t i = i0 + u * kReduceThreads;
+      k[u] = i < n ? rk[i] : 0u;
+      v[u] = i < n ? rv[i] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if (i0 + u * kReduceThreads < n && !lds_add_pair(&acc[k[u]], v[u].x, v[u].y)) {
+        unsafeAtomicAdd(&out[k[u]].x, v[u].x);
+        unsafeAtomicAdd(&out[k[u]].y, v[u].y);
       }
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < kMapSlots; i += kScatThreads) keys[i] = kEmptyKey;
-    __syncthreads();
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n_e; i += kReduceThreads) {
+    const unsigned long long pv = acc[i];
+    if (pv != 0ull) {
+      float2 o = out[i];
+      o.x += __uint_as_float((uint32_t)pv);
+      o.y += __uint_as_float((uint32_t)(pv >> 32));
+      out[i] = o;
+    }
+  }
+  if (threadIdx.x == 0) bucket_count[b] = 0u;
 }
 
 __global__ void copy_plain_kernel(const float* plain, float* image, int64_t n) {
@@ -1216,20 +1419,26 @@ hipError_t launch_texture_backward(int K, int feat_dtype, int mlp_dtype, const G
 }
 
 hipError_t launch_hash_scatter(int K, const GridDev& grid, const float* depths, const float2* feat_grad,
-                               float* g_table, hipStream_t s) {
+                               float* g_table, uint16_t* rec_key, float2* rec_val, uint32_t* bucket_count,
+                               hipStream_t s) {
   if (K == 0 || grid.width == 0 || grid.height == 0 || grid.levels == 0 || !g_table) return hipSuccess;
-  // Block of bw x bh patches with bw * bh * K = kScatUnits.
-  const int np = K >= kScatUnits ? 1 : kScatUnits / K;
-  int bw = 1;
-  while (bw * bw < np) bw *= 2;
-  const int bh = np / bw > 0 ? np / bw : 1;
-  const int npx = (grid.width + 3) / 4, npy = (grid.height + 3) / 4;
-  const int nbx = (npx + bw - 1) / bw, nby = (npy + bh - 1) / bh;
-  const int64_t n_tasks = (int64_t)nbx * nby * grid.levels;
-  int64_t wgs = (int64_t)compute_units() * 3;
-  if (wgs > n_tasks) wgs = n_tasks;
-  hipLaunchKernelGGL(hash_scatter_kernel, dim3((unsigned)wgs), dim3(kScatThreads), 0, s, grid, K, depths, feat_grad,
-                     g_table, bw, bh, nbx, nby);
+  const ScatterGeom sg = scatter_geom(grid.width, grid.height, K);
+  const int n_blocks = sg.nbx * sg.nby;
+  const int bl = scatter_bucket_log2(grid.log2_size);
+  const int nb = 1 << (grid.log2_size - bl);
+  if (bl > kReduceMaxLog2 || nb > kScatMaxBuckets) return hipErrorInvalidValue;
+  const uint32_t cap = (uint32_t)(scatter_record_capacity(grid.width, grid.height, K) / nb);
+  hipError_t e = launch_fill_f32(reinterpret_cast<float*>(bucket_count), 0.0f, nb, s);
+  if (e != hipSuccess) return e;
+  int64_t wgs = (int64_t)compute_units() * 4;
+  if (wgs > n_blocks) wgs = n_blocks;
+  for (int l = 0; l < grid.levels; ++l) {
+    hipLaunchKernelGGL(scatter_bin_kernel, dim3((unsigned)wgs), dim3(kScatThreads), 0, s, grid, grid.lv[l], K, l,
+                       depths, feat_grad, g_table, sg.bw, sg.bh, sg.nbx, sg.nby, bl, cap, bucket_count, rec_key,
+                       rec_val);
+    hipLaunchKernelGGL(scatter_reduce_kernel, dim3((unsigned)nb), dim3(kReduceThreads), 0, s, bl, cap, bucket_count,
+                       rec_key, rec_val, g_table + 2 * ((size_t)l << grid.log2_size));
+  }
   return hipGetLastError();
 }
 
