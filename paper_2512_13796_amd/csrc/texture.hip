@@ -1045,10 +1045,9 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
     const float2* __restrict__ feat_grad, float* __restrict__ g_table, int bw, int bh, int nbx, int nby,
     int bucket_log2, uint32_t cap, uint32_t* __restrict__ bucket_count, uint16_t* __restrict__ rec_key,
     float2* __restrict__ rec_val) {
-  __shared__ __attribute__((aligned(16))) float svals[kBlockSamples][16];  // 8 corners x 2 features
+  __shared__ float svals[16][kBlockSamples];  // [corner * 2 + feature][sample]: conflict-free by sample
   __shared__ int scell[kBlockSamples][3];
   __shared__ uint32_t skey[kBlockSamples];
-  __shared__ uint32_t sidx[kBlockSamples];
   __shared__ uint32_t hist[kScatMaxBuckets];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, c = lane & 15;
   const int row = threadIdx.x >> 4;
@@ -1082,11 +1081,11 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
       if (in && si.valid) e = feat_grad[((int64_t)level * nqK + q * K + j) * 16 + c];
       const bool act = in && si.valid && (e.x != 0.f || e.y != 0.f);
       const LevelGeom lg = level_geom(L, si);
-      float4* vrow = reinterpret_cast<float4*>(svals[smp]);
 #pragma unroll
-      for (int b4 = 0; b4 < 4; ++b4) {
-        const float w0 = act ? corner_weight(lg, 2 * b4) : 0.f, w1 = act ? corner_weight(lg, 2 * b4 + 1) : 0.f;
-        vrow[b4] = make_float4(w0 * e.x, w0 * e.y, w1 * e.x, w1 * e.y);
+      for (int b = 0; b < 8; ++b) {
+        const float w = act ? corner_weight(lg, b) : 0.f;
+        svals[2 * b][smp] = w * e.x;
+        svals[2 * b + 1][smp] = w * e.y;
       }
       scell[smp][0] = lg.cx;
       scell[smp][1] = lg.cy;
@@ -1095,33 +1094,15 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
       skey[smp] = act ? (lg.hx[0] ^ lg.hy[0] ^ lg.hz[0]) & 0x7FFFFFFFu : 0xFFFFFFFFu;
     }
     __syncthreads();
-    // 2. bitonic sort of (key, sample) over the 512 samples
+    // 2. bitonic sort of (key, sample) over each wave's 128 samples (the
+    // wave's two patches, all slots); equal cells in different waves stay
+    // separate records, which only costs a few duplicates at coarse levels
     uint32_t key[2] = {skey[p0], skey[p0 + 1]};
     uint32_t idx[2] = {(uint32_t)p0, (uint32_t)p0 + 1u};
-    for (int k = 2; k <= kBlockSamples; k <<= 1) {
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        if (j >= 128) {  // partner in another wave: exchange through LDS
-          __syncthreads();
-          skey[p0] = key[0];
-          skey[p0 + 1] = key[1];
-          sidx[p0] = idx[0];
-          sidx[p0 + 1] = idx[1];
-          __syncthreads();
 #pragma unroll
-          for (int e = 0; e < 2; ++e) {
-            const int p = p0 + e, qq = p ^ j;
-            const uint32_t ok = skey[qq], oi = sidx[qq];
-            const bool asc = (p & k) == 0, lower = (p & j) == 0;
-            const bool take = (lower == asc) ? ok < key[e] : ok > key[e];
-            if (take) {
-              key[e] = ok;
-              idx[e] = oi;
-            }
-          }
-        } else {
-          bitonic_stage_regs(key, idx, p0, k, j);
-        }
-      }
+    for (int k = 2; k <= 128; k <<= 1) {
+#pragma unroll
+      for (int j = k >> 1; j > 0; j >>= 1) bitonic_stage_regs(key, idx, p0, k, j);
     }
     // 3. segments of equal cells along the sorted order, summed within each wave
     bool live[2];
@@ -1134,15 +1115,8 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
       cx[e] = scell[sm][0];
       cy[e] = scell[sm][1];
       cz[e] = scell[sm][2];
-      const float4* vrow = reinterpret_cast<const float4*>(svals[sm]);
 #pragma unroll
-      for (int b4 = 0; b4 < 4; ++b4) {
-        const float4 t = vrow[b4];
-        a[e][4 * b4] = t.x;
-        a[e][4 * b4 + 1] = t.y;
-        a[e][4 * b4 + 2] = t.z;
-        a[e][4 * b4 + 3] = t.w;
-      }
+      for (int v = 0; v < 16; ++v) a[e][v] = svals[v][sm];
     }
     // element 1 continues element 0's segment?
     const bool same01 = live[0] == live[1] && cx[0] == cx[1] && cy[0] == cy[1] && cz[0] == cz[1];
