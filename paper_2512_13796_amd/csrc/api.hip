@@ -516,9 +516,23 @@ int nx_render_backward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* 
                                                at<unsigned char>(ws, L.weight_ops), s));
     }
     if (grads->table) {
-      PhaseTimer pt(ctx, "hash_scatter", s);
-      NX_CHECK_HIP(nx::launch_hash_scatter(K, gd, saved->depths, fgrad, grads->table, at<uint16_t>(ws, L.scat_key),
-                                           at<float2>(ws, L.scat_val), at<uint32_t>(ws, L.scat_count), s));
+      uint16_t* rk = at<uint16_t>(ws, L.scat_key);
+      float2* rv = at<float2>(ws, L.scat_val);
+      uint32_t* cnt = at<uint32_t>(ws, L.scat_count);
+      {
+        PhaseTimer pt(ctx, "scatter_init", s);
+        NX_CHECK_HIP(nx::launch_hash_scatter_init(K, gd, cnt, s));
+      }
+      for (int l = 0; l < gd.levels; ++l) {
+        {
+          PhaseTimer pt(ctx, "scatter_bin", s);
+          NX_CHECK_HIP(nx::launch_hash_scatter_bin(K, gd, l, saved->depths, fgrad, grads->table, rk, rv, cnt, s));
+        }
+        {
+          PhaseTimer pt(ctx, "scatter_reduce", s);
+          NX_CHECK_HIP(nx::launch_hash_scatter_reduce(K, gd, l, grads->table, rk, rv, cnt, s));
+        }
+      }
     }
   }
   {

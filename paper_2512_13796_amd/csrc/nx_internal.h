@@ -130,9 +130,15 @@ constexpr size_t kWeightOperandBytes = 192 * 1024;
 // corner contributions are filed as records under buckets (fixed ranges of
 // table entries), then one workgroup per bucket sums its records and updates
 // that range of g_table (no floating-point global atomics).
-hipError_t launch_hash_scatter(int K, const GridDev& grid, const float* depths, const float2* feat_grad,
-                               float* g_table, uint16_t* rec_key, float2* rec_val, uint32_t* bucket_count,
-                               hipStream_t s);
+// init clears the bucket cursors once per backward; bin and reduce run once
+// per level, in that order.
+hipError_t launch_hash_scatter_init(int K, const GridDev& grid, uint32_t* bucket_count, hipStream_t s);
+hipError_t launch_hash_scatter_bin(int K, const GridDev& grid, int level, const float* depths,
+                                   const float2* feat_grad, float* g_table, uint16_t* rec_key, float2* rec_val,
+                                   uint32_t* bucket_count, hipStream_t s);
+hipError_t launch_hash_scatter_reduce(int K, const GridDev& grid, int level, float* g_table,
+                                      const uint16_t* rec_key, const float2* rec_val, uint32_t* bucket_count,
+                                      hipStream_t s);
 
 // Screen blocks of the hash scatter: bw x bh patches of 4x4 pixels with
 // bw * bh * K = kScatUnits (patch, slot) units, i.e. at most 4096 corner

@@ -318,12 +318,13 @@ struct SampleInfo {
 // lanes of a 16-lane row see the same slot of 16 neighbouring pixels, so at
 // coarse levels they usually share a hash-grid cell. This part needs only the
 // sample's depth: has = valid, W = 0.
-__device__ __forceinline__ SampleInfo sample_ray(const GridDev& gd, int K, int64_t q, int j, int c,
+__device__ __forceinline__ SampleInfo sample_ray(const GridDev& gd, int K, int q, int j, int c,
                                                  const float* depths) {
   SampleInfo si;
   const int npx = (gd.width + 3) >> 2;
-  const int px = 4 * (int)(q % npx) + (c & 3);
-  const int py = 4 * (int)(q / npx) + (c >> 2);
+  const int qy = q / npx;
+  const int px = 4 * (q - qy * npx) + (c & 3);
+  const int py = 4 * qy + (c >> 2);
   si.valid = px < gd.width && py < gd.height;
   si.p = si.valid ? (int64_t)py * gd.width + px : 0;
   si.s = si.p * K + j;
@@ -338,7 +339,7 @@ __device__ __forceinline__ SampleInfo sample_ray(const GridDev& gd, int K, int64
   return si;
 }
 
-__device__ __forceinline__ SampleInfo sample_info(const GridDev& gd, int K, int64_t q, int j, int c,
+__device__ __forceinline__ SampleInfo sample_info(const GridDev& gd, int K, int q, int j, int c,
                                                   const int32_t* ids, const float* depths, const float* weights) {
   SampleInfo si = sample_ray(gd, K, q, j, c, depths);
   const int id = si.valid ? ids[si.s] : -1;
@@ -500,7 +501,7 @@ __global__ __launch_bounds__(kTexThreads) void texture_forward_kernel(GridDev gd
     bool pix_valid = false;
     int64_t pix = 0;
     for (int j = 0; j < K; ++j) {
-      const SampleInfo si = sample_info(gd, K, q, j, c, ids, depths, weights);
+      const SampleInfo si = sample_info(gd, K, (int)q, j, c, ids, depths, weights);
       pix_valid = si.valid;
       pix = si.p;
       float z[8], fraw[8], delta[4];
@@ -759,7 +760,7 @@ __global__ __launch_bounds__(kTexThreads) void texture_backward_kernel(
   }
 
   for (int64_t qj = (int64_t)blockIdx.x * kWaves + wave; qj < n_q * K; qj += (int64_t)gridDim.x * kWaves) {
-    const SampleInfo si = sample_info(gd, K, qj / K, (int)(qj % K), c, ids, depths, weights);
+    const SampleInfo si = sample_info(gd, K, (int)(qj >> log2K), (int)(qj & (K - 1)), c, ids, depths, weights);
     // ---- recompute features (all corner reads in flight together)
     float z[8], fraw[8], delta[4];
     LaneEntries<TDT> E;
@@ -1041,7 +1042,7 @@ __device__ __forceinline__ void bitonic_stage_regs(uint32_t (&key)[2], uint32_t 
 }
 
 __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
-    GridDev gd, GridLevel L, int K, int level, const float* __restrict__ depths,
+    GridDev gd, GridLevel L, int K, int log2K, int level, const float* __restrict__ depths,
     const float2* __restrict__ feat_grad, float* __restrict__ g_table, int bw, int bh, int nbx, int nby,
     int bucket_log2, uint32_t cap, uint32_t* __restrict__ bucket_count, uint16_t* __restrict__ rec_key,
     float2* __restrict__ rec_val) {
@@ -1060,6 +1061,7 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
   const int n_blocks = nbx * nby;
   float* g_level = g_table + 2 * ((size_t)level << gd.log2_size);
   const int p0 = 128 * wave + 2 * lane;  // sorted positions p0, p0 + 1 belong to this lane
+  const int log2bw = __builtin_ctz((unsigned)bw);  // bw is a power of two
   // Consecutive workgroup ids go to different XCDs; renumber so that each XCD
   // walks neighbouring blocks.
   const int G = gridDim.x;
@@ -1072,13 +1074,13 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
     for (int it = 0; it < kUnitsPerRow; ++it) {
       const int u = row + it * (kScatThreads / 16);
       const int smp = u * 16 + c;
-      const int pb = u / K, j = u % K;
-      const int qx = bx * bw + pb % bw, qy = by * bh + pb / bw;
+      const int pb = u >> log2K, j = u & (K - 1);
+      const int qx = bx * bw + (pb & (bw - 1)), qy = by * bh + (pb >> log2bw);
       const bool in = qx < npx && qy < npy;
-      const int64_t q = in ? (int64_t)qy * npx + qx : 0;
+      const int q = in ? qy * npx + qx : 0;
       const SampleInfo si = sample_ray(gd, K, q, j, c, depths);
       float2 e = make_float2(0.f, 0.f);
-      if (in && si.valid) e = feat_grad[((int64_t)level * nqK + q * K + j) * 16 + c];
+      if (in && si.valid) e = feat_grad[((int64_t)level * nqK + (int64_t)q * K + j) * 16 + c];
       const bool act = in && si.valid && (e.x != 0.f || e.y != 0.f);
       const LevelGeom lg = level_geom(L, si);
 #pragma unroll
@@ -1392,27 +1394,51 @@ hipError_t launch_texture_backward(int K, int feat_dtype, int mlp_dtype, const G
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_hash_scatter(int K, const GridDev& grid, const float* depths, const float2* feat_grad,
-                               float* g_table, uint16_t* rec_key, float2* rec_val, uint32_t* bucket_count,
-                               hipStream_t s) {
-  if (K == 0 || grid.width == 0 || grid.height == 0 || grid.levels == 0 || !g_table) return hipSuccess;
-  const ScatterGeom sg = scatter_geom(grid.width, grid.height, K);
-  const int n_blocks = sg.nbx * sg.nby;
-  const int bl = scatter_bucket_log2(grid.log2_size);
-  const int nb = 1 << (grid.log2_size - bl);
-  if (bl > kReduceMaxLog2 || nb > kScatMaxBuckets) return hipErrorInvalidValue;
-  const uint32_t cap = (uint32_t)(scatter_record_capacity(grid.width, grid.height, K) / nb);
-  hipError_t e = launch_fill_f32(reinterpret_cast<float*>(bucket_count), 0.0f, nb, s);
-  if (e != hipSuccess) return e;
+namespace {
+struct ScatterLaunch {
+  ScatterGeom sg;
+  int n_blocks, bl, nb;
+  uint32_t cap;
+};
+bool scatter_launch(int K, const GridDev& grid, ScatterLaunch* o) {
+  o->sg = scatter_geom(grid.width, grid.height, K);
+  o->n_blocks = o->sg.nbx * o->sg.nby;
+  o->bl = scatter_bucket_log2(grid.log2_size);
+  o->nb = 1 << (grid.log2_size - o->bl);
+  o->cap = o->nb > 0 ? (uint32_t)(scatter_record_capacity(grid.width, grid.height, K) / o->nb) : 0u;
+  return o->bl <= kReduceMaxLog2 && o->nb <= kScatMaxBuckets && o->n_blocks > 0;
+}
+}  // namespace
+
+hipError_t launch_hash_scatter_init(int K, const GridDev& grid, uint32_t* bucket_count, hipStream_t s) {
+  if (K == 0 || grid.width == 0 || grid.height == 0 || grid.levels == 0) return hipSuccess;
+  ScatterLaunch sl;
+  if (!scatter_launch(K, grid, &sl)) return hipErrorInvalidValue;
+  return launch_fill_f32(reinterpret_cast<float*>(bucket_count), 0.0f, sl.nb, s);
+}
+
+hipError_t launch_hash_scatter_bin(int K, const GridDev& grid, int level, const float* depths,
+                                   const float2* feat_grad, float* g_table, uint16_t* rec_key, float2* rec_val,
+                                   uint32_t* bucket_count, hipStream_t s) {
+  if (K == 0 || grid.width == 0 || grid.height == 0 || level < 0 || level >= grid.levels) return hipSuccess;
+  ScatterLaunch sl;
+  if (!scatter_launch(K, grid, &sl)) return hipErrorInvalidValue;
   int64_t wgs = (int64_t)compute_units() * 4;
-  if (wgs > n_blocks) wgs = n_blocks;
-  for (int l = 0; l < grid.levels; ++l) {
-    hipLaunchKernelGGL(scatter_bin_kernel, dim3((unsigned)wgs), dim3(kScatThreads), 0, s, grid, grid.lv[l], K, l,
-                       depths, feat_grad, g_table, sg.bw, sg.bh, sg.nbx, sg.nby, bl, cap, bucket_count, rec_key,
-                       rec_val);
-    hipLaunchKernelGGL(scatter_reduce_kernel, dim3((unsigned)nb), dim3(kReduceThreads), 0, s, bl, cap, bucket_count,
-                       rec_key, rec_val, g_table + 2 * ((size_t)l << grid.log2_size));
-  }
+  if (wgs > sl.n_blocks) wgs = sl.n_blocks;
+  hipLaunchKernelGGL(scatter_bin_kernel, dim3((unsigned)wgs), dim3(kScatThreads), 0, s, grid, grid.lv[level], K,
+                     ilog2(K), level, depths, feat_grad, g_table, sl.sg.bw, sl.sg.bh, sl.sg.nbx, sl.sg.nby, sl.bl,
+                     sl.cap, bucket_count, rec_key, rec_val);
+  return hipGetLastError();
+}
+
+hipError_t launch_hash_scatter_reduce(int K, const GridDev& grid, int level, float* g_table,
+                                      const uint16_t* rec_key, const float2* rec_val, uint32_t* bucket_count,
+                                      hipStream_t s) {
+  if (K == 0 || grid.width == 0 || grid.height == 0 || level < 0 || level >= grid.levels) return hipSuccess;
+  ScatterLaunch sl;
+  if (!scatter_launch(K, grid, &sl)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(scatter_reduce_kernel, dim3((unsigned)sl.nb), dim3(kReduceThreads), 0, s, sl.bl, sl.cap,
+                     bucket_count, rec_key, rec_val, g_table + 2 * ((size_t)level << grid.log2_size));
   return hipGetLastError();
 }
 
