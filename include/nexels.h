@@ -47,6 +47,9 @@ typedef enum {
 
 typedef enum { NX_F32 = 0, NX_F16 = 1, NX_BF16 = 2 } nx_dtype;
 
+/* Most cameras one call renders. */
+#define NX_MAX_CAMS 64
+
 /* Surfel parameters, already activated (Representation, Geometry):
  * device pointers, float32.
  *   means     [n,3]  centres mu (world)
@@ -113,8 +116,12 @@ typedef struct {
  *                    masks of the hidden units with a positive pre-activation,
  *                    layer 1 words then layer 2 words, bit i of word w for
  *                    unit 32 w + i (0 for empty slots)
- *   n_instances      host scalar written by nx_render_forward: number of
- *                    (surfel, tile) pairs; read by nx_render_backward. */
+ *   n_instances      HOST array [n_cams] written by nx_render_forward: number
+ *                    of (surfel, tile) pairs per camera; read by
+ *                    nx_render_backward.
+ * With n_cams > 1 every per-pixel array holds the cameras one after another
+ * (camera c starts at pixel sum_{c'<c} width*height); the same holds for the
+ * backward's grad_image / grad_weights / grad_tex. */
 typedef struct {
   float *image, *plain;
   int32_t *ids;
@@ -122,7 +129,7 @@ typedef struct {
   uint32_t *n_iter;
   int32_t *cells;
   uint32_t *relu_masks;
-  int64_t n_instances;
+  int64_t *n_instances;
 } nx_fwd_out;
 
 /* Gradients, device float32, ACCUMULATED (+=) into caller-initialised
@@ -145,24 +152,30 @@ typedef struct nx_ctx nx_ctx;
 int nx_create(nx_ctx **out, int32_t K, int32_t tile, nx_dtype feat_dtype, nx_dtype mlp_dtype);
 int nx_destroy(nx_ctx *ctx);
 
-/* Workspace bytes for n_surfels surfels seen by one camera with at most
- * max_instances (surfel, tile) pairs. The same workspace carries the
- * forward's sorted tile lists and per-surfel records to the backward. */
+/* Workspace bytes for n_surfels surfels seen by n_cams cameras with at most
+ * max_instances (surfel, tile) pairs per camera. The workspace holds one
+ * section per camera, one after another; it carries the forward's sorted
+ * tile lists and per-surfel records to the backward. */
 int nx_workspace_size(nx_ctx *ctx, int64_t n_surfels, const nx_camera *cams, int32_t n_cams,
                       int64_t max_instances, size_t *bytes);
 
-/* Collection pass, then texturing pass (Rendering). cams: host array of
- * n_cams cameras (n_cams == 1 is supported). If the workspace is too small
- * the call returns NX_ERR_WORKSPACE, stores the required size in
+/* Collection pass, then texturing pass (Rendering), for each of the n_cams
+ * cameras in cams (host array, 1 <= n_cams <= NX_MAX_CAMS, at most 2^30
+ * pixels in total), one after another on the stream. If the workspace is too
+ * small the call returns NX_ERR_WORKSPACE, stores a required size in
  * *workspace_required and leaves the outputs undefined; call again with a
- * large enough workspace. */
+ * workspace of at least that size (with several cameras the first estimate
+ * may still be short: repeat until the call succeeds). On success
+ * *workspace_required is the size the call used. */
 int nx_render_forward(nx_ctx *ctx, const nx_surfels *surfels, const nx_camera *cams, int32_t n_cams,
                       const nx_hashgrid *grid, const nx_mlp *mlp, nx_fwd_out *out, void *workspace,
                       size_t workspace_bytes, size_t *workspace_required, void *stream);
 
 /* Gradients of L through both passes given dL/dimage [P,3] (device) and the
- * optional dL/dweights [P,K] and dL/dtex [P,K,3] (device, NULL = zero). saved
- * and workspace must be those of the matching forward call, unmodified.
+ * optional dL/dweights [P,K] and dL/dtex [P,K,3] (device, NULL = zero), all
+ * cameras concatenated as in the forward; the cameras' gradients add up in
+ * grads. saved and workspace must be those of the matching forward call,
+ * unmodified.
  * Discrete choices (stop, top-K, hash cell) are those the forward took.
  * Atomic accumulation makes results deterministic up to float32 summation
  * order. */

@@ -44,7 +44,7 @@ class NxMLP(ctypes.Structure):
 class NxFwdOut(ctypes.Structure):
     _fields_ = [("image", c_void_p), ("plain", c_void_p), ("ids", c_void_p), ("weights", c_void_p),
                 ("depths", c_void_p), ("t_final", c_void_p), ("tex", c_void_p), ("n_iter", c_void_p),
-                ("cells", c_void_p), ("relu_masks", c_void_p), ("n_instances", ctypes.c_int64)]
+                ("cells", c_void_p), ("relu_masks", c_void_p), ("n_instances", ctypes.POINTER(ctypes.c_int64))]
 
 
 class NxGrads(ctypes.Structure):

@@ -108,15 +108,21 @@ int check_ctx(const nx_ctx* ctx) {
 
 int check_camera(const nx_camera* cams, int32_t n_cams) {
   if (!cams) return fail(NX_ERR_INVALID, "cams is NULL");
-  if (n_cams != 1) return fail(n_cams < 1 ? NX_ERR_INVALID : NX_ERR_UNSUPPORTED, "n_cams must be 1");
-  const nx_camera& c = cams[0];
-  if (c.width <= 0 || c.height <= 0) return fail(NX_ERR_INVALID, "camera width/height must be positive");
-  if ((int64_t)c.width * c.height > (int64_t)1 << 28) return fail(NX_ERR_UNSUPPORTED, "image larger than 2^28 px");
-  for (int i = 0; i < 12; ++i)
-    if (!finite_d(c.world_to_cam[i])) return fail(NX_ERR_INVALID, "camera matrix not finite");
-  if (!(c.fx > 0 && c.fy > 0 && finite_d(c.fx) && finite_d(c.fy) && finite_d(c.cx) && finite_d(c.cy)))
-    return fail(NX_ERR_INVALID, "camera intrinsics invalid");
-  if (!(c.near_z > 0 && finite_d(c.near_z))) return fail(NX_ERR_INVALID, "near_z must be positive");
+  if (n_cams < 1) return fail(NX_ERR_INVALID, "n_cams must be at least 1");
+  if (n_cams > NX_MAX_CAMS) return fail(NX_ERR_UNSUPPORTED, "n_cams exceeds NX_MAX_CAMS");
+  int64_t total = 0;
+  for (int32_t k = 0; k < n_cams; ++k) {
+    const nx_camera& c = cams[k];
+    if (c.width <= 0 || c.height <= 0) return fail(NX_ERR_INVALID, "camera width/height must be positive");
+    if ((int64_t)c.width * c.height > (int64_t)1 << 28) return fail(NX_ERR_UNSUPPORTED, "image larger than 2^28 px");
+    total += (int64_t)c.width * c.height;
+    for (int i = 0; i < 12; ++i)
+      if (!finite_d(c.world_to_cam[i])) return fail(NX_ERR_INVALID, "camera matrix not finite");
+    if (!(c.fx > 0 && c.fy > 0 && finite_d(c.fx) && finite_d(c.fy) && finite_d(c.cx) && finite_d(c.cy)))
+      return fail(NX_ERR_INVALID, "camera intrinsics invalid");
+    if (!(c.near_z > 0 && finite_d(c.near_z))) return fail(NX_ERR_INVALID, "near_z must be positive");
+  }
+  if (total > (int64_t)1 << 30) return fail(NX_ERR_UNSUPPORTED, "more than 2^30 pixels in one call");
   return NX_OK;
 }
 
@@ -246,6 +252,184 @@ const T* at(const void* base, size_t off) {
   return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
 }
 
+// The outputs of the camera whose pixels start at pixel offset pix in the
+// concatenated arrays.
+nx_fwd_out camera_slice(const nx_ctx* ctx, const nx_hashgrid* grid, const nx_mlp* mlp, const nx_fwd_out& o,
+                        int64_t pix) {
+  const int64_t K = ctx->K > 0 ? ctx->K : 0;
+  nx_fwd_out c = o;
+  c.image = o.image + 3 * pix;
+  c.plain = o.plain + 3 * pix;
+  c.t_final = o.t_final + pix;
+  c.n_iter = o.n_iter + pix;
+  if (o.ids) c.ids = o.ids + K * pix;
+  if (o.weights) c.weights = o.weights + K * pix;
+  if (o.depths) c.depths = o.depths + K * pix;
+  if (o.tex) c.tex = o.tex + 3 * K * pix;
+  if (o.cells && grid) c.cells = o.cells + (int64_t)3 * grid->levels * K * pix;
+  if (o.relu_masks && mlp) c.relu_masks = o.relu_masks + (int64_t)2 * (mlp->dims[1] / 32) * K * pix;
+  return c;
+}
+
+// One camera of nx_render_forward: out points at this camera's slices of the
+// outputs, workspace at its section. *need receives the section size this
+// camera requires so far (its instance count is known after the scan).
+int forward_one(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera& cam, const nx_hashgrid* grid,
+                const nx_mlp* mlp, const nx_fwd_out* out, void* workspace, size_t workspace_bytes, size_t* need,
+                int64_t* n_inst_out, hipStream_t s) {
+  const int K = ctx->K;
+  const nx::CamDev cd = make_cam(cam);
+  const int n_tiles = cd.ntx * cd.nty;
+  const int64_t n = surfels->n;
+  const int64_t P = (int64_t)cd.width * cd.height;
+  const Layout L0 = make_layout(n, cd, K, 0);
+  *need = L0.total;
+  if (!workspace || workspace_bytes < L0.total) return fail(NX_ERR_WORKSPACE, "workspace too small");
+  void* ws = workspace;
+
+  uint32_t* depth_keys = at<uint32_t>(ws, L0.depth_keys);
+  uint32_t* counts = at<uint32_t>(ws, L0.tile_counts);
+  int4* rects = at<int4>(ws, L0.rects);
+  float4* records = at<float4>(ws, L0.records);
+  {
+  PhaseTimer pt(ctx, "preprocess", s);
+  NX_CHECK_HIP(nx::launch_preprocess(surfels->means, surfels->quats, surfels->scales, surfels->opacities,
+                                     surfels->gammas, surfels->colors, n, cd, depth_keys, counts, rects, records, s));
+  }
+  uint32_t* sk = at<uint32_t>(ws, L0.sort_k);
+  uint32_t* sv = at<uint32_t>(ws, L0.sort_v);
+  uint32_t* offsets = at<uint32_t>(ws, L0.offsets);
+  if (n > 0) {
+    PhaseTimer pt(ctx, "depth_sort", s);
+    NX_CHECK_HIP(hipMemcpyAsync(sk, depth_keys, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    NX_CHECK_HIP(nx::launch_iota(sv, n, s));
+    // The I-part is not laid out yet: the histogram for the depth sort uses the
+    // instance area, which is at least as large as the N-sized histogram.
+    NX_CHECK_HIP(nx::radix_sort_pairs(sk, sv, at<uint32_t>(ws, L0.sort_tk), at<uint32_t>(ws, L0.sort_tv),
+                                      at<uint32_t>(ws, L0.hist), n, 32, s));
+  }
+  {
+    PhaseTimer pt(ctx, "instance_scan", s);
+    NX_CHECK_HIP(nx::launch_gather_scan(counts, sv, offsets, at<uint32_t>(ws, L0.scan_blocks), n, s));
+  }
+  NX_CHECK_HIP(hipMemcpyAsync(ctx->pinned, offsets + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  NX_CHECK_HIP(hipStreamSynchronize(s));
+  const int64_t n_inst = (int64_t)ctx->pinned[0];
+  const Layout L = make_layout(n, cd, K, n_inst);
+  *n_inst_out = n_inst;
+  *need = L.total;
+  if (workspace_bytes < L.total) return fail(NX_ERR_WORKSPACE, "workspace too small for the tile instances");
+
+  uint32_t* it = at<uint32_t>(ws, L.inst_tiles);
+  uint32_t* iid = at<uint32_t>(ws, L.inst_ids);
+  {
+    PhaseTimer pt(ctx, "duplicate", s);
+    NX_CHECK_HIP(nx::launch_duplicate(sv, offsets, rects, n, cd.ntx, it, iid, s));
+  }
+  {
+  PhaseTimer pt(ctx, "tile_sort", s);
+  NX_CHECK_HIP(nx::radix_sort_pairs(it, iid, at<uint32_t>(ws, L.inst_tmp_tiles), at<uint32_t>(ws, L.inst_tmp_ids),
+                                    at<uint32_t>(ws, L.hist), n_inst, tile_bits(n_tiles), s));
+  }
+  uint2* ranges = at<uint2>(ws, L.tile_ranges);
+  {
+    PhaseTimer pt(ctx, "tile_ranges", s);
+    NX_CHECK_HIP(nx::launch_tile_ranges(it, n_inst, ranges, n_tiles, s));
+  }
+  {
+  PhaseTimer pt(ctx, "raster_forward", s);
+  NX_CHECK_HIP(nx::launch_raster_forward(K, records, iid, ranges, cd, out->plain, out->ids, out->weights,
+                                         out->depths, out->t_final, out->n_iter, s));
+  }
+  nx::GridDev gd = make_grid(cam, grid);
+  nx::MlpDev md{};
+  if (K > 0) {
+    md.w[0] = mlp->w[0];
+    md.w[1] = mlp->w[1];
+    md.w[2] = mlp->w[2];
+    md.in_dim = mlp->dims[0];
+    md.hidden = mlp->dims[1];
+  }
+  {
+  PhaseTimer pt(ctx, "texture_forward", s);
+  NX_CHECK_HIP(nx::launch_texture_forward(K, ctx->feat_dtype, ctx->mlp_dtype, gd, K > 0 ? grid->table : nullptr, md,
+                                          out->ids, out->depths, out->weights, out->plain, out->tex, out->image,
+                                          out->cells, out->relu_masks, s));
+  }
+  return NX_OK;
+}
+
+// One camera of nx_render_backward: saved, grad_* point at this camera's
+// slices, workspace at its section (laid out for n_inst instances).
+int backward_one(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera& cam, const nx_hashgrid* grid,
+                 const nx_mlp* mlp, const nx_fwd_out* saved, int64_t n_inst, void* workspace,
+                 const float* grad_image, const float* grad_weights, const float* grad_tex, const nx_grads* grads,
+                 hipStream_t s) {
+  const int K = ctx->K;
+  const nx::CamDev cd = make_cam(cam);
+  const int n_tiles = cd.ntx * cd.nty;
+  const int64_t n = surfels->n;
+  const int64_t P = (int64_t)cd.width * cd.height;
+  const Layout L = make_layout(n, cd, K, n_inst);
+  void* ws = workspace;
+  float* rec_grad = at<float>(ws, L.rec_grad);
+  float* gdepth = at<float>(ws, L.grad_depth);
+  {
+    PhaseTimer pt(ctx, "zero_record_grads", s);
+    NX_CHECK_HIP(nx::launch_fill_f32(rec_grad, 0.0f, (int64_t)nx::kRecGrad * n, s));
+  }
+  if (K > 0) {
+    nx::GridDev gd = make_grid(cam, grid);
+    nx::MlpDev md{};
+    md.w[0] = mlp->w[0];
+    md.w[1] = mlp->w[1];
+    md.w[2] = mlp->w[2];
+    md.in_dim = mlp->dims[0];
+    md.hidden = mlp->dims[1];
+    float2* fgrad = grads->table ? at<float2>(ws, L.feat_grad) : nullptr;
+    {
+      PhaseTimer pt(ctx, "texture_backward", s);
+      NX_CHECK_HIP(nx::launch_texture_backward(K, ctx->feat_dtype, ctx->mlp_dtype, gd, grid->table, md, saved->ids,
+                                               saved->depths, saved->weights, grad_image, grad_tex, fgrad,
+                                               grads->mlp[0], grads->mlp[1], grads->mlp[2], gdepth,
+                                               at<unsigned char>(ws, L.weight_ops), s));
+    }
+    if (grads->table) {
+      uint16_t* rk = at<uint16_t>(ws, L.scat_key);
+      float2* rv = at<float2>(ws, L.scat_val);
+      uint32_t* cnt = at<uint32_t>(ws, L.scat_count);
+      {
+        PhaseTimer pt(ctx, "scatter_init", s);
+        NX_CHECK_HIP(nx::launch_hash_scatter_init(K, gd, cnt, s));
+      }
+      for (int l = 0; l < gd.levels; ++l) {
+        {
+          PhaseTimer pt(ctx, "scatter_bin", s);
+          NX_CHECK_HIP(nx::launch_hash_scatter_bin(K, gd, l, saved->depths, fgrad, grads->table, rk, rv, cnt, s));
+        }
+        {
+          PhaseTimer pt(ctx, "scatter_reduce", s);
+          NX_CHECK_HIP(nx::launch_hash_scatter_reduce(K, gd, l, grads->table, rk, rv, cnt, s));
+        }
+      }
+    }
+  }
+  {
+  PhaseTimer pt(ctx, "raster_backward", s);
+  NX_CHECK_HIP(nx::launch_raster_backward(K, at<float4>(ws, L.records), at<uint32_t>(ws, L.inst_ids),
+                                          at<uint2>(ws, L.tile_ranges), cd, saved->plain, saved->ids, saved->weights,
+                                          saved->tex, saved->n_iter, grad_image, grad_weights,
+                                          K > 0 ? gdepth : nullptr, rec_grad, s));
+  }
+  {
+  PhaseTimer pt(ctx, "preprocess_backward", s);
+  NX_CHECK_HIP(nx::launch_preprocess_backward(surfels->means, surfels->quats, surfels->scales, n, cd,
+                                              at<uint32_t>(ws, L.tile_counts), rec_grad, grads->means, grads->quats,
+                                              grads->scales, grads->opacities, grads->gammas, grads->colors, s));
+  }
+  return NX_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -342,9 +526,9 @@ int nx_workspace_size(nx_ctx* ctx, int64_t n_surfels, const nx_camera* cams, int
   if ((r = check_camera(cams, n_cams)) != NX_OK) return r;
   if (!bytes) return fail(NX_ERR_INVALID, "bytes is NULL");
   if (n_surfels < 0 || max_instances < 0) return fail(NX_ERR_INVALID, "negative size");
-  const nx::CamDev cd = make_cam(cams[0]);
-  const Layout L = make_layout(n_surfels, cd, ctx->K, max_instances);
-  *bytes = L.total;
+  size_t total = 0;
+  for (int32_t c = 0; c < n_cams; ++c) total += make_layout(n_surfels, make_cam(cams[c]), ctx->K, max_instances).total;
+  *bytes = total;
   return NX_OK;
 }
 
@@ -354,6 +538,7 @@ int nx_workspace_layout(nx_ctx* ctx, int64_t n_surfels, const nx_camera* cams, i
   if ((r = check_ctx(ctx)) != NX_OK) return r;
   if ((r = check_camera(cams, n_cams)) != NX_OK) return r;
   if (!layout) return fail(NX_ERR_INVALID, "layout is NULL");
+  if (n_cams != 1) return fail(NX_ERR_UNSUPPORTED, "nx_workspace_layout describes one camera");
   if (n_surfels < 0 || n_instances < 0) return fail(NX_ERR_INVALID, "negative size");
   const nx::CamDev cd = make_cam(cams[0]);
   const Layout L = make_layout(n_surfels, cd, ctx->K, n_instances);
@@ -376,94 +561,38 @@ int nx_render_forward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* c
   if ((r = check_surfels(surfels)) != NX_OK) return r;
   if ((r = check_camera(cams, n_cams)) != NX_OK) return r;
   if ((r = check_grid_mlp(ctx, grid, mlp)) != NX_OK) return r;
-  if (!out || !out->image || !out->plain || !out->t_final || !out->n_iter)
+  if (!out || !out->image || !out->plain || !out->t_final || !out->n_iter || !out->n_instances)
     return fail(NX_ERR_INVALID, "an output pointer is NULL");
   if (ctx->K > 0 && (!out->ids || !out->weights || !out->depths || !out->tex))
     return fail(NX_ERR_INVALID, "an output pointer is NULL");
-  const int K = ctx->K;
-  const nx::CamDev cd = make_cam(cams[0]);
-  const int n_tiles = cd.ntx * cd.nty;
-  const int64_t n = surfels->n;
-  const int64_t P = (int64_t)cd.width * cd.height;
-  const Layout L0 = make_layout(n, cd, K, 0);
-  if (workspace_required) *workspace_required = L0.total;
-  if (!workspace || workspace_bytes < L0.total) {
-    if (!workspace_required) return fail(NX_ERR_INVALID, "workspace too small and workspace_required is NULL");
-    return fail(NX_ERR_WORKSPACE, "workspace too small");
-  }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   NX_CHECK_HIP(hipGetLastError());
-  void* ws = workspace;
-
-  uint32_t* depth_keys = at<uint32_t>(ws, L0.depth_keys);
-  uint32_t* counts = at<uint32_t>(ws, L0.tile_counts);
-  int4* rects = at<int4>(ws, L0.rects);
-  float4* records = at<float4>(ws, L0.records);
-  {
-  PhaseTimer pt(ctx, "preprocess", s);
-  NX_CHECK_HIP(nx::launch_preprocess(surfels->means, surfels->quats, surfels->scales, surfels->opacities,
-                                     surfels->gammas, surfels->colors, n, cd, depth_keys, counts, rects, records, s));
+  size_t off = 0;
+  int64_t pix = 0;
+  for (int32_t c = 0; c < n_cams; ++c) {
+    const nx_fwd_out oc = camera_slice(ctx, grid, mlp, *out, pix);
+    size_t need = 0;
+    int64_t n_inst = -1;
+    const size_t avail = workspace && workspace_bytes > off ? workspace_bytes - off : 0;
+    r = forward_one(ctx, surfels, cams[c], grid, mlp, &oc, workspace ? at<char>(workspace, off) : nullptr, avail,
+                    &need, &n_inst, s);
+    if (r == NX_ERR_WORKSPACE) {
+      // Required size: what is known for cameras <= c, and for the later ones
+      // the layout at this camera's instance count (a guess; a second call
+      // may ask for more).
+      size_t req = off + need;
+      const int64_t guess = n_inst > 0 ? n_inst : 0;
+      for (int32_t d = c + 1; d < n_cams; ++d) req += make_layout(surfels->n, make_cam(cams[d]), ctx->K, guess).total;
+      if (workspace_required) *workspace_required = req;
+      if (!workspace_required) return fail(NX_ERR_INVALID, "workspace too small and workspace_required is NULL");
+      return fail(NX_ERR_WORKSPACE, "workspace too small");
+    }
+    if (r != NX_OK) return r;
+    out->n_instances[c] = n_inst;
+    off += need;
+    pix += (int64_t)cams[c].width * cams[c].height;
   }
-  uint32_t* sk = at<uint32_t>(ws, L0.sort_k);
-  uint32_t* sv = at<uint32_t>(ws, L0.sort_v);
-  uint32_t* offsets = at<uint32_t>(ws, L0.offsets);
-  if (n > 0) {
-    PhaseTimer pt(ctx, "depth_sort", s);
-    NX_CHECK_HIP(hipMemcpyAsync(sk, depth_keys, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
-    NX_CHECK_HIP(nx::launch_iota(sv, n, s));
-    // The I-part is not laid out yet: the histogram for the depth sort uses the
-    // instance area, which is at least as large as the N-sized histogram.
-    NX_CHECK_HIP(nx::radix_sort_pairs(sk, sv, at<uint32_t>(ws, L0.sort_tk), at<uint32_t>(ws, L0.sort_tv),
-                                      at<uint32_t>(ws, L0.hist), n, 32, s));
-  }
-  {
-    PhaseTimer pt(ctx, "instance_scan", s);
-    NX_CHECK_HIP(nx::launch_gather_scan(counts, sv, offsets, at<uint32_t>(ws, L0.scan_blocks), n, s));
-  }
-  NX_CHECK_HIP(hipMemcpyAsync(ctx->pinned, offsets + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  NX_CHECK_HIP(hipStreamSynchronize(s));
-  const int64_t n_inst = (int64_t)ctx->pinned[0];
-  const Layout L = make_layout(n, cd, K, n_inst);
-  out->n_instances = n_inst;
-  if (workspace_required) *workspace_required = L.total;
-  if (workspace_bytes < L.total) return fail(NX_ERR_WORKSPACE, "workspace too small for the tile instances");
-
-  uint32_t* it = at<uint32_t>(ws, L.inst_tiles);
-  uint32_t* iid = at<uint32_t>(ws, L.inst_ids);
-  {
-    PhaseTimer pt(ctx, "duplicate", s);
-    NX_CHECK_HIP(nx::launch_duplicate(sv, offsets, rects, n, cd.ntx, it, iid, s));
-  }
-  {
-  PhaseTimer pt(ctx, "tile_sort", s);
-  NX_CHECK_HIP(nx::radix_sort_pairs(it, iid, at<uint32_t>(ws, L.inst_tmp_tiles), at<uint32_t>(ws, L.inst_tmp_ids),
-                                    at<uint32_t>(ws, L.hist), n_inst, tile_bits(n_tiles), s));
-  }
-  uint2* ranges = at<uint2>(ws, L.tile_ranges);
-  {
-    PhaseTimer pt(ctx, "tile_ranges", s);
-    NX_CHECK_HIP(nx::launch_tile_ranges(it, n_inst, ranges, n_tiles, s));
-  }
-  {
-  PhaseTimer pt(ctx, "raster_forward", s);
-  NX_CHECK_HIP(nx::launch_raster_forward(K, records, iid, ranges, cd, out->plain, out->ids, out->weights,
-                                         out->depths, out->t_final, out->n_iter, s));
-  }
-  nx::GridDev gd = make_grid(cams[0], grid);
-  nx::MlpDev md{};
-  if (K > 0) {
-    md.w[0] = mlp->w[0];
-    md.w[1] = mlp->w[1];
-    md.w[2] = mlp->w[2];
-    md.in_dim = mlp->dims[0];
-    md.hidden = mlp->dims[1];
-  }
-  {
-  PhaseTimer pt(ctx, "texture_forward", s);
-  NX_CHECK_HIP(nx::launch_texture_forward(K, ctx->feat_dtype, ctx->mlp_dtype, gd, K > 0 ? grid->table : nullptr, md,
-                                          out->ids, out->depths, out->weights, out->plain, out->tex, out->image,
-                                          out->cells, out->relu_masks, s));
-  }
+  if (workspace_required) *workspace_required = off;
   g_last_error.clear();
   return NX_OK;
 }
@@ -477,76 +606,32 @@ int nx_render_backward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* 
   if ((r = check_surfels(surfels)) != NX_OK) return r;
   if ((r = check_camera(cams, n_cams)) != NX_OK) return r;
   if ((r = check_grid_mlp(ctx, grid, mlp)) != NX_OK) return r;
-  if (!saved || !saved->plain || !saved->n_iter) return fail(NX_ERR_INVALID, "saved forward outputs are NULL");
+  if (!saved || !saved->plain || !saved->n_iter || !saved->n_instances)
+    return fail(NX_ERR_INVALID, "saved forward outputs are NULL");
   if (ctx->K > 0 && (!saved->ids || !saved->weights || !saved->depths || !saved->tex))
     return fail(NX_ERR_INVALID, "saved forward outputs are NULL");
   if (!grad_image) return fail(NX_ERR_INVALID, "grad_image is NULL");
   if (!grads) return fail(NX_ERR_INVALID, "grads is NULL");
-  const int K = ctx->K;
-  const nx::CamDev cd = make_cam(cams[0]);
-  const int n_tiles = cd.ntx * cd.nty;
-  const int64_t n = surfels->n;
-  const int64_t P = (int64_t)cd.width * cd.height;
-  if (saved->n_instances < 0) return fail(NX_ERR_INVALID, "saved n_instances is negative");
-  const Layout L = make_layout(n, cd, K, saved->n_instances);
-  if (!workspace || workspace_bytes < L.total) return fail(NX_ERR_INVALID, "workspace does not match the forward");
+  size_t total = 0;
+  for (int32_t c = 0; c < n_cams; ++c) {
+    if (saved->n_instances[c] < 0) return fail(NX_ERR_INVALID, "saved n_instances is negative");
+    total += make_layout(surfels->n, make_cam(cams[c]), ctx->K, saved->n_instances[c]).total;
+  }
+  if (!workspace || workspace_bytes < total) return fail(NX_ERR_INVALID, "workspace does not match the forward");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   NX_CHECK_HIP(hipGetLastError());
-  void* ws = const_cast<void*>(workspace);
-  float* rec_grad = at<float>(ws, L.rec_grad);
-  float* gdepth = at<float>(ws, L.grad_depth);
-  {
-    PhaseTimer pt(ctx, "zero_record_grads", s);
-    NX_CHECK_HIP(nx::launch_fill_f32(rec_grad, 0.0f, (int64_t)nx::kRecGrad * n, s));
-  }
-  if (K > 0) {
-    nx::GridDev gd = make_grid(cams[0], grid);
-    nx::MlpDev md{};
-    md.w[0] = mlp->w[0];
-    md.w[1] = mlp->w[1];
-    md.w[2] = mlp->w[2];
-    md.in_dim = mlp->dims[0];
-    md.hidden = mlp->dims[1];
-    float2* fgrad = grads->table ? at<float2>(ws, L.feat_grad) : nullptr;
-    {
-      PhaseTimer pt(ctx, "texture_backward", s);
-      NX_CHECK_HIP(nx::launch_texture_backward(K, ctx->feat_dtype, ctx->mlp_dtype, gd, grid->table, md, saved->ids,
-                                               saved->depths, saved->weights, grad_image, grad_tex, fgrad,
-                                               grads->mlp[0], grads->mlp[1], grads->mlp[2], gdepth,
-                                               at<unsigned char>(ws, L.weight_ops), s));
-    }
-    if (grads->table) {
-      uint16_t* rk = at<uint16_t>(ws, L.scat_key);
-      float2* rv = at<float2>(ws, L.scat_val);
-      uint32_t* cnt = at<uint32_t>(ws, L.scat_count);
-      {
-        PhaseTimer pt(ctx, "scatter_init", s);
-        NX_CHECK_HIP(nx::launch_hash_scatter_init(K, gd, cnt, s));
-      }
-      for (int l = 0; l < gd.levels; ++l) {
-        {
-          PhaseTimer pt(ctx, "scatter_bin", s);
-          NX_CHECK_HIP(nx::launch_hash_scatter_bin(K, gd, l, saved->depths, fgrad, grads->table, rk, rv, cnt, s));
-        }
-        {
-          PhaseTimer pt(ctx, "scatter_reduce", s);
-          NX_CHECK_HIP(nx::launch_hash_scatter_reduce(K, gd, l, grads->table, rk, rv, cnt, s));
-        }
-      }
-    }
-  }
-  {
-  PhaseTimer pt(ctx, "raster_backward", s);
-  NX_CHECK_HIP(nx::launch_raster_backward(K, at<float4>(ws, L.records), at<uint32_t>(ws, L.inst_ids),
-                                          at<uint2>(ws, L.tile_ranges), cd, saved->plain, saved->ids, saved->weights,
-                                          saved->tex, saved->n_iter, grad_image, grad_weights,
-                                          K > 0 ? gdepth : nullptr, rec_grad, s));
-  }
-  {
-  PhaseTimer pt(ctx, "preprocess_backward", s);
-  NX_CHECK_HIP(nx::launch_preprocess_backward(surfels->means, surfels->quats, surfels->scales, n, cd,
-                                              at<uint32_t>(ws, L.tile_counts), rec_grad, grads->means, grads->quats,
-                                              grads->scales, grads->opacities, grads->gammas, grads->colors, s));
+  const int64_t K = ctx->K > 0 ? ctx->K : 0;
+  size_t off = 0;
+  int64_t pix = 0;
+  for (int32_t c = 0; c < n_cams; ++c) {
+    const nx_fwd_out sc = camera_slice(ctx, grid, mlp, *saved, pix);
+    const int64_t n_inst = saved->n_instances[c];
+    r = backward_one(ctx, surfels, cams[c], grid, mlp, &sc, n_inst, at<char>(const_cast<void*>(workspace), off),
+                     grad_image + 3 * pix, grad_weights ? grad_weights + K * pix : nullptr,
+                     grad_tex ? grad_tex + 3 * K * pix : nullptr, grads, s);
+    if (r != NX_OK) return r;
+    off += make_layout(surfels->n, make_cam(cams[c]), ctx->K, n_inst).total;
+    pix += (int64_t)cams[c].width * cams[c].height;
   }
   g_last_error.clear();
   return NX_OK;

@@ -110,9 +110,10 @@ class ForwardResult:
     t_final: torch.Tensor
     tex: torch.Tensor
     n_iter: torch.Tensor
-    n_instances: int
+    n_instances: int  # total over the cameras
     workspace: torch.Tensor
-    camera: object = None
+    camera: object = None  # the camera, or the list of cameras, the call rendered
+    n_instances_cam: list = None
     near: float = 0.2
     cells: torch.Tensor = None
     relu_masks: torch.Tensor = None
@@ -149,17 +150,24 @@ def _structs(ctx, surfels, table, level_scales, weights, device):
     return s, g, m, keep
 
 
+def _cameras(cam):
+    return list(cam) if isinstance(cam, (list, tuple)) else [cam]
+
+
 def render_forward(ctx: Context, surfels, cam, table=None, level_scales=None, weights=None, near=0.2,
                    workspace=None, want_cells=False) -> ForwardResult:
-    """Collection and texturing passes for one camera (nx_render_forward).
+    """Collection and texturing passes (nx_render_forward) for one camera or a
+    list of cameras; with several cameras every per-pixel output holds the
+    cameras one after another.
 
     want_cells=True also returns the hash-grid lattice cells the texturing
     pass used ([P, K, levels, 3] int32) and its ReLU decisions
     ([P, K, 2*hidden/32] int32 bit masks), for decision-level comparisons."""
     device = surfels[0].device
     s, g, m, keep = _structs(ctx, surfels, table, level_scales, weights, device)
-    cs = camera_struct(cam, near)
-    P = cam.width * cam.height
+    cams = _cameras(cam)
+    cs = (L.NxCamera * len(cams))(*[camera_struct(c, near) for c in cams])
+    P = sum(c.width * c.height for c in cams)
     K = ctx.K
     f32 = dict(device=device, dtype=torch.float32)
     res = ForwardResult(
@@ -172,15 +180,17 @@ def render_forward(ctx: Context, surfels, cam, table=None, level_scales=None, we
     if want_cells and K > 0:
         res.cells = torch.zeros(P, K, table.shape[0], 3, device=device, dtype=torch.int32)
         res.relu_masks = torch.zeros(P, K, 2 * weights[0].shape[0] // 32, device=device, dtype=torch.int32)
+    n_inst = (ctypes.c_int64 * len(cams))()
     out = L.NxFwdOut(_ptr(res.image), _ptr(res.plain), _ptr(res.ids), _ptr(res.weights), _ptr(res.depths),
-                     _ptr(res.t_final), _ptr(res.tex), _ptr(res.n_iter), _ptr(res.cells), _ptr(res.relu_masks), 0)
+                     _ptr(res.t_final), _ptr(res.tex), _ptr(res.n_iter), _ptr(res.cells), _ptr(res.relu_masks),
+                     n_inst)
     stream = ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
     need = ctypes.c_size_t(0)
     ws = workspace
-    for _ in range(3):
+    for _ in range(len(cams) + 3):
         if ws is None or ws.numel() < ctx.ws_hint:
             ws = torch.empty(max(ctx.ws_hint, 256), device=device, dtype=torch.uint8)
-        code = ctx.lib.nx_render_forward(ctx.handle, ctypes.byref(s), ctypes.byref(cs), 1, ctypes.byref(g),
+        code = ctx.lib.nx_render_forward(ctx.handle, ctypes.byref(s), cs, len(cams), ctypes.byref(g),
                                          ctypes.byref(m), ctypes.byref(out), _ptr(ws), ws.numel(),
                                          ctypes.byref(need), stream)
         if code == L.NX_ERR_WORKSPACE:
@@ -192,7 +202,8 @@ def render_forward(ctx: Context, surfels, cam, table=None, level_scales=None, we
     else:
         raise L.NexelsError(L.NX_ERR_WORKSPACE, "workspace sizing did not converge")
     ctx.ws_hint = max(ctx.ws_hint, int(need.value))
-    res.n_instances = int(out.n_instances)
+    res.n_instances_cam = [int(v) for v in n_inst]
+    res.n_instances = sum(res.n_instances_cam)
     res.workspace = ws
     del keep
     return res
@@ -203,8 +214,9 @@ def render_backward(ctx: Context, surfels, fwd: ForwardResult, table=None, level
     """Accumulate gradients into ``grads`` (dict of float32 tensors; missing keys are skipped)."""
     device = surfels[0].device
     s, g, m, keep = _structs(ctx, surfels, table, level_scales, weights, device)
-    cs = camera_struct(fwd.camera, fwd.near)
-    P = fwd.camera.width * fwd.camera.height
+    cams = _cameras(fwd.camera)
+    cs = (L.NxCamera * len(cams))(*[camera_struct(c, fwd.near) for c in cams])
+    P = sum(c.width * c.height for c in cams)
     K = ctx.K
     _check_dev("grad_image", grad_image, device, torch.float32, (P, 3))
     if grad_weights is not None:
@@ -221,10 +233,11 @@ def render_backward(ctx: Context, surfels, fwd: ForwardResult, table=None, level
                    _ptr(grads.get("table")))
     for i in range(3):
         gs.mlp[i] = None if gm[i] is None else gm[i].data_ptr()
+    n_inst = (ctypes.c_int64 * len(cams))(*fwd.n_instances_cam)
     out = L.NxFwdOut(_ptr(fwd.image), _ptr(fwd.plain), _ptr(fwd.ids), _ptr(fwd.weights), _ptr(fwd.depths),
-                     _ptr(fwd.t_final), _ptr(fwd.tex), _ptr(fwd.n_iter), None, None, fwd.n_instances)
+                     _ptr(fwd.t_final), _ptr(fwd.tex), _ptr(fwd.n_iter), None, None, n_inst)
     stream = ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
-    L.check(ctx.lib.nx_render_backward(ctx.handle, ctypes.byref(s), ctypes.byref(cs), 1, ctypes.byref(g),
+    L.check(ctx.lib.nx_render_backward(ctx.handle, ctypes.byref(s), cs, len(cams), ctypes.byref(g),
                                        ctypes.byref(m), ctypes.byref(out), _ptr(fwd.workspace), fwd.workspace.numel(),
                                        _ptr(grad_image), _ptr(grad_weights), _ptr(grad_tex), ctypes.byref(gs),
                                        stream))

@@ -1,0 +1,144 @@
+"""Several cameras in one call (n_cams > 1) against one call per camera and
+against the FP64 oracle.
+
+Workload: the 300k-surfel planes scene with 16 orbit cameras of mixed
+resolutions, shrunk to 40k surfels; the first five cameras are rendered
+together (640x480 up to 1920x1080 in one call). Per-camera outputs must equal
+the single-camera calls bit for bit (same kernels, same inputs); the
+gradients of the joint backward must equal the sum of the single-camera
+backwards up to float32 summation order; and on a pixel sample per camera
+the joint call must match the oracle (forward within 1e-5, gradients summed
+over the cameras within the parity bars).
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenes
+from tests.gpu_helpers import SAFETY, compare_forward, device_inputs, grad_errors, log, to_np
+from tests.test_gpu_parity import _sample_pixels
+
+pytestmark = pytest.mark.gpu
+N_CAMS = 5
+
+
+@pytest.fixture(scope="module")
+def nx():
+    import paper_2512_13796_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def setup(nx):
+    wl = scenes.make_workload(4, seed=0, n_surfels=40_000)
+    cams = wl.cameras[:N_CAMS]
+    surf, table, weights = device_inputs(wl)
+    ctx = nx.Context(wl.K, table.dtype, weights[0].dtype)
+    res = nx.render_forward(ctx, surf, cams, table, wl.grid.level_scales, weights, want_cells=True)
+    torch.cuda.synchronize()
+    return wl, cams, surf, table, weights, ctx, res
+
+
+def _offsets(cams):
+    off = [0]
+    for c in cams:
+        off.append(off[-1] + c.width * c.height)
+    return off
+
+
+def _zero_grads(surf, table, weights):
+    z = lambda t: torch.zeros(t.shape, device=t.device, dtype=torch.float32)
+    return {"means": z(surf[0]), "quats": z(surf[1]), "scales": z(surf[2]), "opacities": z(surf[3]),
+            "gammas": z(surf[4]), "colors": z(surf[5]), "table": z(table), "mlp": [z(w) for w in weights]}
+
+
+def test_joint_forward_equals_single_camera_calls(nx, setup):
+    wl, cams, surf, table, weights, ctx, res = setup
+    off = _offsets(cams)
+    log("multi-view resolutions", [(c.width, c.height) for c in cams], "instances", res.n_instances_cam)
+    for i, cam in enumerate(cams):
+        one = nx.render_forward(ctx, surf, cam, table, wl.grid.level_scales, weights)
+        torch.cuda.synchronize()
+        sl = slice(off[i], off[i + 1])
+        assert one.n_instances == res.n_instances_cam[i]
+        for nm in ("image", "plain", "ids", "weights", "depths", "t_final", "tex", "n_iter"):
+            a, b = getattr(res, nm)[sl], getattr(one, nm)
+            assert torch.equal(a, b), f"camera {i}: {nm} differs from the single-camera call"
+
+
+def test_joint_backward_equals_sum_of_single_camera_backwards(nx, setup):
+    wl, cams, surf, table, weights, ctx, res = setup
+    P = res.image.shape[0]
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    gi = torch.randn(P, 3, device="cuda", generator=gen) * 1e-3
+    joint = _zero_grads(surf, table, weights)
+    nx.render_backward(ctx, surf, res, table, wl.grid.level_scales, weights, gi, None, None, joint)
+    single = _zero_grads(surf, table, weights)
+    off = _offsets(cams)
+    for i, cam in enumerate(cams):
+        one = nx.render_forward(ctx, surf, cam, table, wl.grid.level_scales, weights)
+        nx.render_backward(ctx, surf, one, table, wl.grid.level_scales, weights,
+                           gi[off[i]:off[i + 1]].contiguous(), None, None, single)
+    torch.cuda.synchronize()
+    for nm in ("means", "quats", "scales", "opacities", "gammas", "colors", "table"):
+        a, b = joint[nm].double(), single[nm].double()
+        rel = float((a - b).norm() / max(float(b.norm()), 1e-30))
+        assert rel <= 1e-5, f"{nm}: joint vs summed single-camera gradients rel {rel:.2e}"
+    for i in range(3):
+        a, b = joint["mlp"][i].double(), single["mlp"][i].double()
+        rel = float((a - b).norm() / max(float(b.norm()), 1e-30))
+        assert rel <= 1e-5, f"mlp{i}: rel {rel:.2e}"
+
+
+def test_joint_call_against_oracle(nx, setup):
+    wl, cams, surf, table, weights, ctx, res = setup
+    off = _offsets(cams)
+    K = wl.K
+    gpu = to_np(res, K)
+    grid = scenes.HashGrid(table.cpu(), wl.grid.level_scales)
+    mlp = scenes.MLP([w.cpu() for w in weights])
+    P = res.image.shape[0]
+    rng = np.random.default_rng(11)
+    gi = np.zeros((P, 3))
+    per_cam = []
+    for i, cam in enumerate(cams):
+        pix = _sample_pixels(cam, 20 + i, per_block=96, full_tiles=1)
+        glob = pix + off[i]
+        cells = res.cells[torch.from_numpy(glob).cuda()].cpu().numpy()
+        masks = res.relu_masks[torch.from_numpy(glob).cuda()].cpu().numpy().view(np.uint32)
+        orc = oracle.render(wl.scene, cam, grid, mlp, K, pixels=pix, force_cells=cells, force_relu=masks)
+        sub = {k: v[off[i]:off[i + 1]] for k, v in gpu.items()}
+        stats = compare_forward(sub, orc, pix, K, label=f"cam {i}")
+        log(f"multi-view cam {i} ({cam.width}x{cam.height}):", stats)
+        dec = orc.margin > SAFETY
+        gi[glob[dec]] = rng.standard_normal((int(dec.sum()), 3))
+        per_cam.append((cam, pix, cells, masks))
+    grads = _zero_grads(surf, table, weights)
+    nx.render_backward(ctx, surf, res, table, wl.grid.level_scales, weights,
+                       torch.from_numpy(gi).float().cuda(), None, None, grads)
+    torch.cuda.synchronize()
+    total = None
+    for i, (cam, pix, cells, masks) in enumerate(per_cam):
+        og = oracle.render_and_grad(wl.scene, cam, grid, mlp, K, pixels=pix, grad_image=gi[pix + off[i]],
+                                    force_cells=cells, force_relu=masks).grads
+        if total is None:
+            total = {k: (v if k != "mlp" else list(v)) for k, v in og.items()}
+        else:
+            for k, v in og.items():
+                if k == "mlp":
+                    total[k] = [a + b for a, b in zip(total[k], v)]
+                else:
+                    total[k] = total[k] + v
+    report = {}
+    for nm in ("means", "quats", "scales", "opacities", "gammas", "colors", "table"):
+        rel, viol, _ = grad_errors(grads[nm].cpu().numpy(), total[nm])
+        report[nm] = (rel, viol)
+    for i in range(3):
+        rel, viol, _ = grad_errors(grads["mlp"][i].cpu().numpy(), total["mlp"][i])
+        report[f"mlp{i}"] = (rel, viol)
+    log("multi-view grads (relL2, frac over bound):", {k: (f"{a:.2e}", f"{b:.1e}") for k, (a, b) in report.items()})
+    for k, (rel, viol) in report.items():
+        assert rel <= 1e-3 and viol <= 5e-3, f"{k}: rel {rel:.2e} viol {viol:.2e}"
