@@ -52,7 +52,7 @@ struct Layout {
   // N-part
   size_t depth_keys, tile_counts, rects, records, sort_k, sort_v, sort_tk, sort_tv, offsets, scan_blocks;
   // fixed-size parts
-  size_t tile_ranges, rec_grad, grad_depth, feat_grad, weight_ops, scat_key, scat_val, scat_count;
+  size_t tile_ranges, rec_grad, grad_depth, feat_grad, weight_ops;
   // I-part
   size_t hist, inst_tiles, inst_ids, inst_tmp_tiles, inst_tmp_ids;
   size_t total;
@@ -84,10 +84,6 @@ Layout make_layout(int64_t n, const nx::CamDev& cd, int K, int64_t n_inst) {
   L.grad_depth = take(sizeof(float) * (size_t)(n_pix * (K > 0 ? K : 1)));
   L.feat_grad = take(sizeof(float2) * (size_t)nx::feat_grad_elems(cd.width, cd.height, K));
   L.weight_ops = take(K > 0 ? nx::kWeightOperandBytes : 0);
-  const size_t n_rec = K > 0 ? (size_t)nx::scatter_record_capacity(cd.width, cd.height, K) : 0;
-  L.scat_key = take(sizeof(uint16_t) * n_rec);
-  L.scat_val = take(sizeof(float2) * n_rec);
-  L.scat_count = take(sizeof(uint32_t) * (K > 0 ? nx::kScatMaxBuckets : 0));
   const int64_t ni = n_inst > 0 ? n_inst : 1;
   const int64_t hist_n = ni > (int64_t)nn ? ni : (int64_t)nn;
   L.hist = take(4 * nx::radix_hist_words(hist_n));
@@ -97,6 +93,30 @@ Layout make_layout(int64_t n, const nx::CamDev& cd, int K, int64_t n_inst) {
   L.inst_tmp_ids = take(4 * (size_t)ni);
   L.total = o;
   return L;
+}
+
+// The hash-grid scatter's record arena is shared by the cameras of a call
+// (every level is reduced once for all of them); it sits at the start of the
+// workspace, before the per-camera sections.
+struct SharedLayout {
+  size_t rec_key, rec_val, bucket_count, total;
+  int64_t capacity;  // records
+};
+
+SharedLayout make_shared_layout(const nx_camera* cams, int32_t n_cams, int K) {
+  SharedLayout S{};
+  for (int32_t c = 0; c < n_cams && K > 0; ++c) S.capacity += nx::scatter_record_capacity(cams[c].width, cams[c].height, K);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  S.rec_key = take(sizeof(uint16_t) * (size_t)S.capacity);
+  S.rec_val = take(sizeof(float2) * (size_t)S.capacity);
+  S.bucket_count = take(sizeof(uint32_t) * (K > 0 ? nx::kScatMaxBuckets : 0));
+  S.total = o;
+  return S;
 }
 
 bool finite_d(double x) { return isfinite(x); }
@@ -394,25 +414,6 @@ int backward_one(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera& cam, c
                                                grads->mlp[0], grads->mlp[1], grads->mlp[2], gdepth,
                                                at<unsigned char>(ws, L.weight_ops), s));
     }
-    if (grads->table) {
-      uint16_t* rk = at<uint16_t>(ws, L.scat_key);
-      float2* rv = at<float2>(ws, L.scat_val);
-      uint32_t* cnt = at<uint32_t>(ws, L.scat_count);
-      {
-        PhaseTimer pt(ctx, "scatter_init", s);
-        NX_CHECK_HIP(nx::launch_hash_scatter_init(K, gd, cnt, s));
-      }
-      for (int l = 0; l < gd.levels; ++l) {
-        {
-          PhaseTimer pt(ctx, "scatter_bin", s);
-          NX_CHECK_HIP(nx::launch_hash_scatter_bin(K, gd, l, saved->depths, fgrad, grads->table, rk, rv, cnt, s));
-        }
-        {
-          PhaseTimer pt(ctx, "scatter_reduce", s);
-          NX_CHECK_HIP(nx::launch_hash_scatter_reduce(K, gd, l, grads->table, rk, rv, cnt, s));
-        }
-      }
-    }
   }
   {
   PhaseTimer pt(ctx, "raster_backward", s);
@@ -526,7 +527,7 @@ int nx_workspace_size(nx_ctx* ctx, int64_t n_surfels, const nx_camera* cams, int
   if ((r = check_camera(cams, n_cams)) != NX_OK) return r;
   if (!bytes) return fail(NX_ERR_INVALID, "bytes is NULL");
   if (n_surfels < 0 || max_instances < 0) return fail(NX_ERR_INVALID, "negative size");
-  size_t total = 0;
+  size_t total = make_shared_layout(cams, n_cams, ctx->K).total;
   for (int32_t c = 0; c < n_cams; ++c) total += make_layout(n_surfels, make_cam(cams[c]), ctx->K, max_instances).total;
   *bytes = total;
   return NX_OK;
@@ -542,14 +543,15 @@ int nx_workspace_layout(nx_ctx* ctx, int64_t n_surfels, const nx_camera* cams, i
   if (n_surfels < 0 || n_instances < 0) return fail(NX_ERR_INVALID, "negative size");
   const nx::CamDev cd = make_cam(cams[0]);
   const Layout L = make_layout(n_surfels, cd, ctx->K, n_instances);
-  layout->depth_keys = L.depth_keys;
-  layout->tile_counts = L.tile_counts;
-  layout->rects = L.rects;
-  layout->records = L.records;
-  layout->sorted_tiles = L.inst_tiles;
-  layout->sorted_ids = L.inst_ids;
-  layout->tile_ranges = L.tile_ranges;
-  layout->total = L.total;
+  const size_t base = make_shared_layout(cams, n_cams, ctx->K).total;
+  layout->depth_keys = base + L.depth_keys;
+  layout->tile_counts = base + L.tile_counts;
+  layout->rects = base + L.rects;
+  layout->records = base + L.records;
+  layout->sorted_tiles = base + L.inst_tiles;
+  layout->sorted_ids = base + L.inst_ids;
+  layout->tile_ranges = base + L.tile_ranges;
+  layout->total = base + L.total;
   return NX_OK;
 }
 
@@ -567,7 +569,7 @@ int nx_render_forward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* c
     return fail(NX_ERR_INVALID, "an output pointer is NULL");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   NX_CHECK_HIP(hipGetLastError());
-  size_t off = 0;
+  size_t off = make_shared_layout(cams, n_cams, ctx->K).total;
   int64_t pix = 0;
   for (int32_t c = 0; c < n_cams; ++c) {
     const nx_fwd_out oc = camera_slice(ctx, grid, mlp, *out, pix);
@@ -612,7 +614,8 @@ int nx_render_backward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* 
     return fail(NX_ERR_INVALID, "saved forward outputs are NULL");
   if (!grad_image) return fail(NX_ERR_INVALID, "grad_image is NULL");
   if (!grads) return fail(NX_ERR_INVALID, "grads is NULL");
-  size_t total = 0;
+  const SharedLayout SH = make_shared_layout(cams, n_cams, ctx->K);
+  size_t total = SH.total;
   for (int32_t c = 0; c < n_cams; ++c) {
     if (saved->n_instances[c] < 0) return fail(NX_ERR_INVALID, "saved n_instances is negative");
     total += make_layout(surfels->n, make_cam(cams[c]), ctx->K, saved->n_instances[c]).total;
@@ -620,18 +623,50 @@ int nx_render_backward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* 
   if (!workspace || workspace_bytes < total) return fail(NX_ERR_INVALID, "workspace does not match the forward");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   NX_CHECK_HIP(hipGetLastError());
+  void* ws = const_cast<void*>(workspace);
   const int64_t K = ctx->K > 0 ? ctx->K : 0;
-  size_t off = 0;
+  // 1. per camera: texture backward (writes its per-level feature
+  //    gradients), collection-pass backward, preprocess backward
+  size_t off = SH.total;
   int64_t pix = 0;
   for (int32_t c = 0; c < n_cams; ++c) {
     const nx_fwd_out sc = camera_slice(ctx, grid, mlp, *saved, pix);
     const int64_t n_inst = saved->n_instances[c];
-    r = backward_one(ctx, surfels, cams[c], grid, mlp, &sc, n_inst, at<char>(const_cast<void*>(workspace), off),
-                     grad_image + 3 * pix, grad_weights ? grad_weights + K * pix : nullptr,
-                     grad_tex ? grad_tex + 3 * K * pix : nullptr, grads, s);
+    r = backward_one(ctx, surfels, cams[c], grid, mlp, &sc, n_inst, at<char>(ws, off), grad_image + 3 * pix,
+                     grad_weights ? grad_weights + K * pix : nullptr, grad_tex ? grad_tex + 3 * K * pix : nullptr,
+                     grads, s);
     if (r != NX_OK) return r;
     off += make_layout(surfels->n, make_cam(cams[c]), ctx->K, n_inst).total;
     pix += (int64_t)cams[c].width * cams[c].height;
+  }
+  // 2. hash-grid gradient, level by level: every camera files its records,
+  //    then one reduction per level for all of them
+  if (K > 0 && grads->table) {
+    uint16_t* rk = at<uint16_t>(ws, SH.rec_key);
+    float2* rv = at<float2>(ws, SH.rec_val);
+    uint32_t* cnt = at<uint32_t>(ws, SH.bucket_count);
+    const nx::GridDev gd0 = make_grid(cams[0], grid);
+    {
+      PhaseTimer pt(ctx, "scatter_init", s);
+      NX_CHECK_HIP(nx::launch_hash_scatter_init(gd0, SH.capacity, cnt, s));
+    }
+    for (int l = 0; l < gd0.levels; ++l) {
+      size_t coff = SH.total;
+      int64_t cpix = 0;
+      for (int32_t c = 0; c < n_cams; ++c) {
+        const nx::CamDev cd = make_cam(cams[c]);
+        const Layout L = make_layout(surfels->n, cd, ctx->K, saved->n_instances[c]);
+        const nx::GridDev gd = make_grid(cams[c], grid);
+        PhaseTimer pt(ctx, "scatter_bin", s);
+        NX_CHECK_HIP(nx::launch_hash_scatter_bin(ctx->K, gd, l, saved->depths + K * cpix,
+                                                 at<float2>(ws, coff + L.feat_grad), grads->table, SH.capacity, rk,
+                                                 rv, cnt, s));
+        coff += L.total;
+        cpix += (int64_t)cams[c].width * cams[c].height;
+      }
+      PhaseTimer pt(ctx, "scatter_reduce", s);
+      NX_CHECK_HIP(nx::launch_hash_scatter_reduce(gd0, l, grads->table, SH.capacity, rk, rv, cnt, s));
+    }
   }
   g_last_error.clear();
   return NX_OK;

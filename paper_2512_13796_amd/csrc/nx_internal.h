@@ -132,11 +132,14 @@ constexpr size_t kWeightOperandBytes = 192 * 1024;
 // that range of g_table (no floating-point global atomics).
 // init clears the bucket cursors once per backward; bin and reduce run once
 // per level, in that order.
-hipError_t launch_hash_scatter_init(int K, const GridDev& grid, uint32_t* bucket_count, hipStream_t s);
+// The record arena (rec_key, rec_val: `capacity` records) and the bucket
+// cursors are shared by all cameras of a call; init once, then per level one
+// bin per camera (appending) and one reduce.
+hipError_t launch_hash_scatter_init(const GridDev& grid, int64_t capacity, uint32_t* bucket_count, hipStream_t s);
 hipError_t launch_hash_scatter_bin(int K, const GridDev& grid, int level, const float* depths,
-                                   const float2* feat_grad, float* g_table, uint16_t* rec_key, float2* rec_val,
-                                   uint32_t* bucket_count, hipStream_t s);
-hipError_t launch_hash_scatter_reduce(int K, const GridDev& grid, int level, float* g_table,
+                                   const float2* feat_grad, float* g_table, int64_t capacity, uint16_t* rec_key,
+                                   float2* rec_val, uint32_t* bucket_count, hipStream_t s);
+hipError_t launch_hash_scatter_reduce(const GridDev& grid, int level, float* g_table, int64_t capacity,
                                       const uint16_t* rec_key, const float2* rec_val, uint32_t* bucket_count,
                                       hipStream_t s);
 

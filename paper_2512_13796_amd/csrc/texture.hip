@@ -1396,47 +1396,48 @@ hipError_t launch_texture_backward(int K, int feat_dtype, int mlp_dtype, const G
 
 namespace {
 struct ScatterLaunch {
-  ScatterGeom sg;
-  int n_blocks, bl, nb;
-  uint32_t cap;
+  int bl, nb;
+  uint32_t cap;  // records per bucket
 };
-bool scatter_launch(int K, const GridDev& grid, ScatterLaunch* o) {
-  o->sg = scatter_geom(grid.width, grid.height, K);
-  o->n_blocks = o->sg.nbx * o->sg.nby;
+bool scatter_launch(const GridDev& grid, int64_t capacity, ScatterLaunch* o) {
   o->bl = scatter_bucket_log2(grid.log2_size);
   o->nb = 1 << (grid.log2_size - o->bl);
-  o->cap = o->nb > 0 ? (uint32_t)(scatter_record_capacity(grid.width, grid.height, K) / o->nb) : 0u;
-  return o->bl <= kReduceMaxLog2 && o->nb <= kScatMaxBuckets && o->n_blocks > 0;
+  const int64_t cap = capacity / o->nb;
+  o->cap = (uint32_t)(cap < 0xFFFFFFFFll ? cap : 0xFFFFFFFFll);
+  return o->bl <= kReduceMaxLog2 && o->nb <= kScatMaxBuckets;
 }
 }  // namespace
 
-hipError_t launch_hash_scatter_init(int K, const GridDev& grid, uint32_t* bucket_count, hipStream_t s) {
-  if (K == 0 || grid.width == 0 || grid.height == 0 || grid.levels == 0) return hipSuccess;
+hipError_t launch_hash_scatter_init(const GridDev& grid, int64_t capacity, uint32_t* bucket_count, hipStream_t s) {
+  if (grid.levels == 0) return hipSuccess;
   ScatterLaunch sl;
-  if (!scatter_launch(K, grid, &sl)) return hipErrorInvalidValue;
+  if (!scatter_launch(grid, capacity, &sl)) return hipErrorInvalidValue;
   return launch_fill_f32(reinterpret_cast<float*>(bucket_count), 0.0f, sl.nb, s);
 }
 
 hipError_t launch_hash_scatter_bin(int K, const GridDev& grid, int level, const float* depths,
-                                   const float2* feat_grad, float* g_table, uint16_t* rec_key, float2* rec_val,
-                                   uint32_t* bucket_count, hipStream_t s) {
+                                   const float2* feat_grad, float* g_table, int64_t capacity, uint16_t* rec_key,
+                                   float2* rec_val, uint32_t* bucket_count, hipStream_t s) {
   if (K == 0 || grid.width == 0 || grid.height == 0 || level < 0 || level >= grid.levels) return hipSuccess;
   ScatterLaunch sl;
-  if (!scatter_launch(K, grid, &sl)) return hipErrorInvalidValue;
+  if (!scatter_launch(grid, capacity, &sl)) return hipErrorInvalidValue;
+  const ScatterGeom sg = scatter_geom(grid.width, grid.height, K);
+  const int n_blocks = sg.nbx * sg.nby;
+  if (n_blocks <= 0) return hipSuccess;
   int64_t wgs = (int64_t)compute_units() * 4;
-  if (wgs > sl.n_blocks) wgs = sl.n_blocks;
+  if (wgs > n_blocks) wgs = n_blocks;
   hipLaunchKernelGGL(scatter_bin_kernel, dim3((unsigned)wgs), dim3(kScatThreads), 0, s, grid, grid.lv[level], K,
-                     ilog2(K), level, depths, feat_grad, g_table, sl.sg.bw, sl.sg.bh, sl.sg.nbx, sl.sg.nby, sl.bl,
-                     sl.cap, bucket_count, rec_key, rec_val);
+                     ilog2(K), level, depths, feat_grad, g_table, sg.bw, sg.bh, sg.nbx, sg.nby, sl.bl, sl.cap,
+                     bucket_count, rec_key, rec_val);
   return hipGetLastError();
 }
 
-hipError_t launch_hash_scatter_reduce(int K, const GridDev& grid, int level, float* g_table,
+hipError_t launch_hash_scatter_reduce(const GridDev& grid, int level, float* g_table, int64_t capacity,
                                       const uint16_t* rec_key, const float2* rec_val, uint32_t* bucket_count,
                                       hipStream_t s) {
-  if (K == 0 || grid.width == 0 || grid.height == 0 || level < 0 || level >= grid.levels) return hipSuccess;
+  if (level < 0 || level >= grid.levels) return hipSuccess;
   ScatterLaunch sl;
-  if (!scatter_launch(K, grid, &sl)) return hipErrorInvalidValue;
+  if (!scatter_launch(grid, capacity, &sl)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(scatter_reduce_kernel, dim3((unsigned)sl.nb), dim3(kReduceThreads), 0, s, sl.bl, sl.cap,
                      bucket_count, rec_key, rec_val, g_table + 2 * ((size_t)level << grid.log2_size));
   return hipGetLastError();
