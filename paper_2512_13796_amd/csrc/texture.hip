@@ -1011,12 +1011,52 @@ __device__ __forceinline__ bool lds_add_pair(unsigned long long* p, float a, flo
 constexpr int kBlockSamples = kScatUnits * 16;  // 512 samples per task
 static_assert(kBlockSamples == 2 * kScatThreads, "two samples per thread");
 
-// One compare-exchange stage (k, j) of a bitonic sort for the two positions
-// p0 = 2 l + base, p0 + 1 held by this lane (l = lane), j <= 64: the partner of
-// a position lives in this lane (j = 1) or in lane l ^ (j / 2).
-__device__ __forceinline__ void bitonic_stage_regs(uint32_t (&key)[2], uint32_t (&idx)[2], int p0, int k, int j) {
-  if (j == 1) {
-    const bool asc = (p0 & k) == 0;
+// Cross-lane moves without the LDS permute path where the pattern allows:
+// DPP (quad_perm, row_ror, wave and row shifts, row broadcasts) and the
+// swizzle unit. dpp<CTRL, ROW_MASK>(v): lanes whose source is out of range,
+// or whose row is not in ROW_MASK, read 0.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ uint32_t dpp_u(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, false);
+}
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __uint_as_float(dpp_u<CTRL, ROW_MASK>(__float_as_uint(v)));
+}
+constexpr int kDppQuadXor1 = 0xB1;   // quad_perm [1,0,3,2]
+constexpr int kDppQuadXor2 = 0x4E;   // quad_perm [2,3,0,1]
+constexpr int kDppRowRor8 = 0x128;   // rotate by 8 within 16 lanes = xor 8
+constexpr int kDppRowShr1 = 0x111;
+constexpr int kDppWaveShr1 = 0x138;  // lane i reads lane i - 1
+constexpr int kDppWaveShl1 = 0x130;  // lane i reads lane i + 1
+constexpr int kDppRowBcast15 = 0x142;
+constexpr int kDppRowBcast31 = 0x143;
+
+// v of lane (lane ^ X), X a power of two below 64.
+template <int X>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v) {
+  if constexpr (X == 1) {
+    return dpp_u<kDppQuadXor1>(v);
+  } else if constexpr (X == 2) {
+    return dpp_u<kDppQuadXor2>(v);
+  } else if constexpr (X == 4) {
+    return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (4 << 10) | 0x1F);
+  } else if constexpr (X == 8) {
+    return dpp_u<kDppRowRor8>(v);
+  } else if constexpr (X == 16) {
+    return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (16 << 10) | 0x1F);
+  } else {
+    return (uint32_t)__shfl_xor((int)v, X, 64);
+  }
+}
+
+// One compare-exchange stage (K_, J) of a bitonic sort for the two positions
+// p0 = 2 l + base, p0 + 1 held by this lane (l = lane), J <= 64: the partner of
+// a position lives in this lane (J = 1) or in lane l ^ (J / 2).
+template <int KK, int J>
+__device__ __forceinline__ void bitonic_stage_regs(uint32_t (&key)[2], uint32_t (&idx)[2], int p0) {
+  if constexpr (J == 1) {
+    const bool asc = (p0 & KK) == 0;
     const bool swap = asc ? key[0] > key[1] : key[0] < key[1];
     if (swap) {
       const uint32_t tk = key[0], ti = idx[0];
@@ -1025,20 +1065,57 @@ __device__ __forceinline__ void bitonic_stage_regs(uint32_t (&key)[2], uint32_t 
       key[1] = tk;
       idx[1] = ti;
     }
-    return;
-  }
+  } else {
 #pragma unroll
-  for (int e = 0; e < 2; ++e) {
-    const int p = p0 + e;
-    const uint32_t ok = __shfl_xor(key[e], j >> 1, 64), oi = __shfl_xor(idx[e], j >> 1, 64);
-    const bool asc = (p & k) == 0, lower = (p & j) == 0;
-    // the lower position keeps the smaller key when ascending
-    const bool take = (lower == asc) ? ok < key[e] : ok > key[e];
-    if (take) {
-      key[e] = ok;
-      idx[e] = oi;
+    for (int e = 0; e < 2; ++e) {
+      const int p = p0 + e;
+      const uint32_t ok = lane_xor<J / 2>(key[e]), oi = lane_xor<J / 2>(idx[e]);
+      const bool asc = (p & KK) == 0, lower = (p & J) == 0;
+      // the lower position keeps the smaller key when ascending
+      const bool take = (lower == asc) ? ok < key[e] : ok > key[e];
+      if (take) {
+        key[e] = ok;
+        idx[e] = oi;
+      }
     }
   }
+}
+
+template <int KK, int J>
+__device__ __forceinline__ void bitonic_merge_regs(uint32_t (&key)[2], uint32_t (&idx)[2], int p0) {
+  bitonic_stage_regs<KK, J>(key, idx, p0);
+  if constexpr (J > 1) bitonic_merge_regs<KK, J / 2>(key, idx, p0);
+}
+
+template <int KK>
+__device__ __forceinline__ void bitonic_sort_regs(uint32_t (&key)[2], uint32_t (&idx)[2], int p0) {
+  bitonic_merge_regs<KK, KK / 2>(key, idx, p0);
+  if constexpr (KK < 128) bitonic_sort_regs<KK * 2>(key, idx, p0);
+}
+
+// Inclusive segmented scan across the 64 lanes: on return v holds the sum of
+// v over the lanes from the start of this lane's segment (the nearest lane
+// at or before it with head set) to this lane. head becomes "a segment
+// starts at or before this lane".
+__device__ __forceinline__ void segmented_scan16(float (&v)[16], bool& head) {
+  uint32_t h = head ? 1u : 0u;
+#define NX_SEG_STEP(CTRL, MASK)                                  \
+  {                                                              \
+    const uint32_t sh = dpp_u<CTRL, MASK>(h);                    \
+    _Pragma("unroll") for (int q = 0; q < 16; ++q) {             \
+      const float sv = dpp_f<CTRL, MASK>(v[q]);                  \
+      v[q] = h ? v[q] : v[q] + sv;                               \
+    }                                                            \
+    h |= sh;                                                     \
+  }
+  NX_SEG_STEP(kDppRowShr1, 0xF)
+  NX_SEG_STEP(kDppRowShr1 + 1, 0xF)
+  NX_SEG_STEP(kDppRowShr1 + 3, 0xF)
+  NX_SEG_STEP(kDppRowShr1 + 7, 0xF)
+  NX_SEG_STEP(kDppRowBcast15, 0xA)
+  NX_SEG_STEP(kDppRowBcast31, 0xC)
+#undef NX_SEG_STEP
+  head = h != 0u;
 }
 
 __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
@@ -1101,11 +1178,7 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
     // separate records, which only costs a few duplicates at coarse levels
     uint32_t key[2] = {skey[p0], skey[p0 + 1]};
     uint32_t idx[2] = {(uint32_t)p0, (uint32_t)p0 + 1u};
-#pragma unroll
-    for (int k = 2; k <= 128; k <<= 1) {
-#pragma unroll
-      for (int j = k >> 1; j > 0; j >>= 1) bitonic_stage_regs(key, idx, p0, k, j);
-    }
+    bitonic_sort_regs<2>(key, idx, p0);
     // 3. segments of equal cells along the sorted order, summed within each wave
     bool live[2];
     int cx[2], cy[2], cz[2];
@@ -1123,8 +1196,9 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
     // element 1 continues element 0's segment?
     const bool same01 = live[0] == live[1] && cx[0] == cx[1] && cy[0] == cy[1] && cz[0] == cz[1];
     // previous lane's last element continues into this lane's element 0?
-    const int pcx = __shfl_up(cx[1], 1, 64), pcy = __shfl_up(cy[1], 1, 64), pcz = __shfl_up(cz[1], 1, 64);
-    const bool plive = __shfl_up((int)live[1], 1, 64) != 0;
+    const int pcx = (int)dpp_u<kDppWaveShr1>((uint32_t)cx[1]), pcy = (int)dpp_u<kDppWaveShr1>((uint32_t)cy[1]);
+    const int pcz = (int)dpp_u<kDppWaveShr1>((uint32_t)cz[1]);
+    const bool plive = dpp_u<kDppWaveShr1>(live[1] ? 1u : 0u) != 0u;
     const bool cont0 = lane > 0 && plive == live[0] && pcx == cx[0] && pcy == cy[0] && pcz == cz[0];
     // lane value: sum of element 1's segment within this lane; head flag: that
     // segment starts in this lane
@@ -1132,25 +1206,13 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
 #pragma unroll
     for (int v = 0; v < 16; ++v) s1[v] = same01 ? a[0][v] + a[1][v] : a[1][v];
     bool head = !(same01 && cont0);
-    // inclusive segmented scan over lanes (Hillis-Steele)
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const bool ph = __shfl_up((int)head, d, 64) != 0;
-      float t[16];
-#pragma unroll
-      for (int v = 0; v < 16; ++v) t[v] = __shfl_up(s1[v], d, 64);
-      if (lane >= d && !head) {
-#pragma unroll
-        for (int v = 0; v < 16; ++v) s1[v] += t[v];
-        head = ph;
-      }
-    }
+    segmented_scan16(s1, head);
     // carry into element 0 from earlier lanes of its segment
     float carry[16];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) carry[v] = __shfl_up(s1[v], 1, 64);
+    for (int v = 0; v < 16; ++v) carry[v] = dpp_f<kDppWaveShr1>(s1[v]);
     // next lane's element 0 continues element 1's segment?
-    const bool next_cont = __shfl_down((int)cont0, 1, 64) != 0;
+    const bool next_cont = dpp_u<kDppWaveShl1>(cont0 ? 1u : 0u) != 0u;
     const bool tail1 = lane == 63 || !next_cont;
     const bool tail0 = !same01;
     // 4. records: a segment tail emits its cell's 8 corners
