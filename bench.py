@@ -39,34 +39,36 @@ def log(*a):
 
 
 def algorithmic(phase, st):
-    """(HBM bytes, matrix flops) one launch of `phase` must move / compute.
+    """(HBM bytes, matrix flops) the launches of `phase` in one step must move / compute.
 
     Counts each input read once and each output written once at its storage
-    width; the hash table is counted once per launch (its re-reads are cache
-    traffic); atomically updated buffers count a read and a write."""
-    N, P, K, I, T = st["N"], st["P"], st["K"], st["I"], st["n_tiles"]
+    width; the hash table is counted once per camera (its re-reads are cache
+    traffic); atomically updated buffers count a read and a write. Per-surfel
+    kernels run once per camera (C cameras)."""
+    N, C, P, K, I, T = st["N"], st["C"], st["P"], st["K"], st["I"], st["n_tiles"]
     S = P * K
-    table = st["L"] * st["T"] * st["F"] * st["tb"]
-    gtable = st["L"] * st["T"] * st["F"] * 4
+    L = st["L"]
+    table = L * st["T"] * st["F"] * st["tb"]
+    gtable = L * st["T"] * st["F"] * 4
     mlp_flops = 2.0 * S * (st["in"] * st["H"] + st["H"] * st["H"] + 3 * st["H"])
     rec = 80
     b = {
-        "preprocess": N * (60 + 4 + 4 + 16 + rec),
-        "depth_sort": N * (8 + 4 * 16),
-        "instance_scan": N * 12,
-        "duplicate": N * 24 + I * 8,
+        "preprocess": C * N * (60 + 4 + 4 + 16 + rec),
+        "depth_sort": C * N * (8 + 4 * 16),
+        "instance_scan": C * N * 12,
+        "duplicate": C * N * 24 + I * 8,
         "tile_sort": I * 16 * st["tile_passes"],
         "tile_ranges": I * 4 + T * 8,
         "raster_forward": I * (4 + rec) + T * 8 + P * (12 + 12 * K + 8),
-        "texture_forward": S * 24 + P * 24 + table,
-        "zero_record_grads": N * 64,
-        "texture_backward": S * 16 + P * 12 + table + S * st["L"] * 8,
-        # per level: that level's feature gradients and the sample depths in,
-        # then that level's slice of the FP32 gradient table read and written
-        "scatter_bin": S * (8 + 4),
-        "scatter_reduce": 2 * gtable / st["L"],
-        "raster_backward": I * (4 + rec) + T * 8 + P * (28 + 24 * K) + N * 120,
-        "preprocess_backward": N * (36 + 4 + 64 + 2 * 60),
+        "texture_forward": S * 24 + P * 24 + C * table,
+        "zero_record_grads": C * N * 64,
+        "texture_backward": S * 16 + P * 12 + C * table + S * L * 8,
+        # per level and camera: that level's feature gradients and the sample
+        # depths in; then that level's slice of the FP32 gradient table read and written
+        "scatter_bin": S * (8 + 4) * L,
+        "scatter_reduce": C * 2 * gtable,
+        "raster_backward": I * (4 + rec) + T * 8 + P * (28 + 24 * K) + C * N * 120,
+        "preprocess_backward": C * N * (36 + 4 + 64 + 2 * 60),
     }
     f = {"texture_forward": mlp_flops, "texture_backward": 3.0 * mlp_flops}
     return float(b.get(phase, 0)), float(f.get(phase, 0.0))
@@ -96,21 +98,31 @@ def measured_traffic(phase):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def setup(form):
+WORKLOADS = {
+    # name: (config, description)
+    "outdoor": (3, "outdoor 400k surfels 1920x1080 K=4, grid 16x2^19x2 fp16, MLP 32-64-64-3 bf16"),
+    "multiview": (4, "planes 300k surfels, 16 orbit cameras 640x480..1920x1080 in one call, K=4, grid 16x2^19x2 fp32, "
+                     "MLP 32-64-64-3 fp32"),
+    "large": (5, "outdoor 1M surfels 2560x1440 K=8, grid 16x2^21x2 bf16, MLP 32-128-128-3 bf16"),
+}
+
+
+def setup(form, workload="outdoor"):
     import torch
 
     import paper_2512_13796_amd as nx
     import scenes
 
-    if form == "bf16":
-        wl = scenes.make_workload(3)  # FP16 grid, BF16 MLP
+    config = WORKLOADS[workload][0]
+    if form == "fp32":
+        wl = scenes.make_workload(config, feat_dtype=torch.float32, mlp_dtype=torch.float32)
     else:
-        wl = scenes.make_workload(3, feat_dtype=torch.float32, mlp_dtype=torch.float32)
+        wl = scenes.make_workload(config)  # the workload's own storage dtypes
     dev = torch.device("cuda:0")
     surf = tuple(t.to(dev).contiguous() for t in wl.scene.tensors())
     table = wl.grid.table.to(dev).contiguous()
     weights = [w.to(dev).contiguous() for w in wl.mlp.weights]
-    target = wl.target[0].reshape(-1, 3).to(dev).contiguous()
+    target = torch.cat([t.reshape(-1, 3) for t in wl.target]).to(dev).contiguous()
     ctx = nx.Context(wl.K, table.dtype, weights[0].dtype)
     z = lambda t: torch.zeros(t.shape, device=dev, dtype=torch.float32)
     grads = {"means": z(surf[0]), "quats": z(surf[1]), "scales": z(surf[2]), "opacities": z(surf[3]),
@@ -119,13 +131,13 @@ def setup(form):
 
 
 def make_step(nx, wl, ctx, surf, table, weights, target, grads):
-    cam = wl.cameras[0]
-    P = cam.width * cam.height
+    cams = wl.cameras if len(wl.cameras) > 1 else wl.cameras[0]
+    P = sum(c.width * c.height for c in wl.cameras)
     scale = 2.0 / (3.0 * P)
     state = {}
 
     def step():
-        res = nx.render_forward(ctx, surf, cam, table, wl.grid.level_scales, weights)
+        res = nx.render_forward(ctx, surf, cams, table, wl.grid.level_scales, weights)
         g = (res.image - target).mul_(scale)
         for k, t in grads.items():
             if k == "mlp":
@@ -140,10 +152,10 @@ def make_step(nx, wl, ctx, surf, table, weights, target, grads):
     return step, state
 
 
-def time_form(form, steps, warmup):
+def time_form(form, steps, warmup, workload="outdoor"):
     import torch
 
-    nx, wl, ctx, surf, table, weights, target, grads = setup(form)
+    nx, wl, ctx, surf, table, weights, target, grads = setup(form, workload)
     step, state = make_step(nx, wl, ctx, surf, table, weights, target, grads)
     for _ in range(warmup):
         step()
@@ -164,12 +176,13 @@ def time_form(form, steps, warmup):
     ms = e0.elapsed_time(e1) / steps
     phases = ctx.timings()
     ctx.timing(False)
-    cam = wl.cameras[0]
     res = state["res"]
-    st = {"N": wl.scene.n, "P": cam.width * cam.height, "K": wl.K, "I": res.n_instances,
-          "n_tiles": ((cam.width + 15) // 16) * ((cam.height + 15) // 16), "L": wl.grid.levels,
-          "T": 1 << wl.grid.log2_size, "F": wl.grid.feat, "tb": table.element_size(),
-          "in": weights[0].shape[1], "H": weights[0].shape[0], "tile_passes": 2}
+    cams = wl.cameras
+    st = {"N": wl.scene.n, "C": len(cams), "P": sum(c.width * c.height for c in cams), "K": wl.K,
+          "I": res.n_instances, "n_tiles": sum(((c.width + 15) // 16) * ((c.height + 15) // 16) for c in cams),
+          "L": wl.grid.levels, "T": 1 << wl.grid.log2_size, "F": wl.grid.feat, "tb": table.element_size(),
+          "in": weights[0].shape[1], "H": weights[0].shape[0], "tile_passes": 2,
+          "width": cams[0].width, "height": cams[0].height}
     return {"ms": ms, "wall_ms": 1000.0 * wall / steps, "phases": phases, "stats": st, "workload": wl}
 
 
@@ -206,6 +219,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=4096)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="outdoor",
+                    help="outdoor (the headline: 400k surfels, 1080p), multiview (16 cameras in one call) or large "
+                         "(1M surfels, 1440p, K=8, hidden 128); the last two print their own line without the FP32 "
+                         "form and the CPU baseline")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain elementwise copy of MIB MiB (read MIB, write MIB) three times, as the "
                          "reference for scaling hardware byte counters")
@@ -217,8 +234,8 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
-    log("bf16 form ...")
-    bf = time_form("bf16", args.steps, args.warmup)
+    log(f"{args.workload} ...")
+    bf = time_form("native", args.steps, args.warmup, args.workload)
     st = bf["stats"]
     P = st["P"]
     value = P / (bf["ms"] / 1000.0) / 1e6
@@ -226,27 +243,37 @@ def main():
     per_step = {k: v[0] / args.steps for k, v in bf["phases"].items()}
     dom = max(per_step, key=lambda k: per_step[k])
     nbytes, nflops = algorithmic(dom, st)
-    dur_s = per_launch[dom] / 1000.0
+    dur_s = per_step[dom] / 1000.0
     achieved = nbytes / dur_s / 1e9
+    launches = bf["phases"][dom][1] // args.steps
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
-            "avg_ms": round(per_launch[dom], 4), "launches_per_step": bf["phases"][dom][1] // args.steps,
-            "algorithmic_bytes": nbytes}
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(dom) if args.workload == "outdoor" else None,
+            "avg_ms": round(per_launch[dom], 4), "launches_per_step": launches,
+            "algorithmic_bytes": nbytes / max(launches, 1)}
     if nflops:
         roof["mfma_tflops"] = round(nflops / dur_s / 1e12, 2)
         roof["mfma_frac"] = round(nflops / dur_s / 1e12 / BF16_PEAK_TFLOPS, 5)
+    cfg = {"workload": WORKLOADS[args.workload][1], "surfels": st["N"], "cameras": st["C"], "pixels": P,
+           "K": st["K"], "instances": st["I"]}
+    if st["C"] == 1:
+        cfg.update(width=st["width"], height=st["height"])
+    dtype = {"outdoor": "bf16", "multiview": "f32", "large": "bf16"}[args.workload]
     line = {
-        "metric": METRIC, "value": round(value, 2), "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps,
+        "metric": METRIC if args.workload == "outdoor" else "Mpix/s fwd+bwd",
+        "value": round(value, 2), "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(bf["ms"], 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
-        "config": {"workload": "outdoor 400k surfels 1920x1080 K=4, grid 16x2^19x2 fp16, MLP 32-64-64-3 bf16",
-                   "surfels": st["N"], "width": 1920, "height": 1080, "K": st["K"], "instances": st["I"]},
+        "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+        "config": cfg,
         "roofline": roof,
         "phases_ms_per_step": {k: round(v, 4) for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},
     }
+    if args.workload != "outdoor":
+        args.no_fp32 = True
+        args.no_cpu_baseline = True
     if not args.no_fp32:
         log("fp32 form ...")
-        f32 = time_form("fp32", max(3, args.steps // 2), max(1, args.warmup // 2))
+        f32 = time_form("fp32", max(3, args.steps // 2), max(1, args.warmup // 2), args.workload)
         n32 = max(3, args.steps // 2)
         ph32 = {k: v[0] / n32 for k, v in f32["phases"].items()}
         line["fp32_form"] = {"value": round(P / (f32["ms"] / 1000.0) / 1e6, 2), "ms_per_step": round(f32["ms"], 4),
