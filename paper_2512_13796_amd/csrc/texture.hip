@@ -46,11 +46,15 @@ constexpr int kWaves = kTexThreads / 64;
 constexpr int kInPad = 32;
 constexpr float kInv2Pi = 0.15915494309189533577f;
 
-// float -> bfloat16 bits, round to nearest even (finite inputs).
-__device__ __forceinline__ short f2bf(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (short)(u >> 16);
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+
+// float -> bfloat16 bits, round to nearest even (gfx950 converts in hardware,
+// two values per v_cvt_pk_bf16_f32).
+__device__ __forceinline__ short f2bf(float x) { return __builtin_bit_cast(short, (__bf16)x); }
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+  const f2v v = {lo, hi};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf2v));
 }
 __device__ __forceinline__ float bf2f(uint32_t b16) { return __uint_as_float(b16 << 16); }
 
@@ -229,20 +233,14 @@ struct Operand<false> {
   }
 };
 
+typedef uint32_t u4v __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ s8 pack8(const float v[8]) {
-  s8 r;
-#pragma unroll
-  for (int e = 0; e < 8; ++e) r[e] = f2bf(v[e]);
-  return r;
+  const u4v w = {pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]), pack_bf16x2(v[4], v[5]), pack_bf16x2(v[6], v[7])};
+  return __builtin_bit_cast(s8, w);
 }
 __device__ __forceinline__ s8 pack_tiles(f4 a, f4 b) {
-  s8 r;
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    r[e] = f2bf(a[e]);
-    r[4 + e] = f2bf(b[e]);
-  }
-  return r;
+  const u4v w = {pack_bf16x2(a[0], a[1]), pack_bf16x2(a[2], a[3]), pack_bf16x2(b[0], b[1]), pack_bf16x2(b[2], b[3])};
+  return __builtin_bit_cast(s8, w);
 }
 __device__ __forceinline__ f4 relu4(f4 x) {
 #pragma unroll
@@ -1017,7 +1015,12 @@ static_assert(kBlockSamples == 2 * kScatThreads, "two samples per thread");
 // or whose row is not in ROW_MASK, read 0.
 template <int CTRL, int ROW_MASK = 0xF>
 __device__ __forceinline__ uint32_t dpp_u(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, false);
+  if constexpr (ROW_MASK == 0xF) {
+    // every row enabled: out-of-range lanes read 0 (bound_ctrl), no old value
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, true);
+  } else {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, false);
+  }
 }
 template <int CTRL, int ROW_MASK = 0xF>
 __device__ __forceinline__ float dpp_f(float v) {
@@ -1215,14 +1218,13 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
     const bool next_cont = dpp_u<kDppWaveShl1>(cont0 ? 1u : 0u) != 0u;
     const bool tail1 = lane == 63 || !next_cont;
     const bool tail0 = !same01;
-    // 4. records: a segment tail emits its cell's 8 corners
+    // 4. records: a segment tail emits its cell's 8 corners (one branch per
+    // tail; a record whose two values are zero is filed like any other)
+    const bool emit[2] = {tail0 && live[0], tail1 && live[1]};
     uint32_t rh[2][8];
     float r0[2][8], r1[2][8];
-    int nrec[2];
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      const bool tail = e == 0 ? tail0 : tail1;
-      nrec[e] = (tail && live[e]) ? 8 : 0;
       float tot[16];
 #pragma unroll
       for (int v = 0; v < 16; ++v) tot[v] = e == 0 ? (cont0 ? carry[v] + a[0][v] : a[0][v]) : s1[v];
@@ -1235,9 +1237,10 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
         r0[e][b] = tot[2 * b];
         r1[e][b] = tot[2 * b + 1];
       }
+      if (emit[e]) {
 #pragma unroll
-      for (int b = 0; b < 8; ++b)
-        if (b < nrec[e] && (r0[e][b] != 0.f || r1[e][b] != 0.f)) atomicAdd(&hist[rh[e][b] >> bucket_log2], 1u);
+        for (int b = 0; b < 8; ++b) atomicAdd(&hist[rh[e][b] >> bucket_log2], 1u);
+      }
     }
     __syncthreads();
     // 5. reserve this block's space in every bucket it touches, then file
@@ -1248,18 +1251,33 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
+      if (emit[e]) {
+        uint32_t pos[8];
+        bool fits = true;
 #pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        if (b < nrec[e] && (r0[e][b] != 0.f || r1[e][b] != 0.f)) {
-          const uint32_t h = rh[e][b], bk = h >> bucket_log2;
-          const uint32_t pos = atomicAdd(&hist[bk], 1u);
-          if (pos < cap) {
-            const size_t at = (size_t)bk * cap + pos;
-            rec_key[at] = (uint16_t)(h & emask);
+        for (int b = 0; b < 8; ++b) {
+          pos[b] = atomicAdd(&hist[rh[e][b] >> bucket_log2], 1u);
+          fits = fits && pos[b] < cap;
+        }
+        if (fits) {
+#pragma unroll
+          for (int b = 0; b < 8; ++b) {
+            const size_t at = (size_t)(rh[e][b] >> bucket_log2) * cap + pos[b];
+            rec_key[at] = (uint16_t)(rh[e][b] & emask);
             rec_val[at] = make_float2(r0[e][b], r1[e][b]);
-          } else {  // bucket full: add straight into the table
-            unsafeAtomicAdd(&g_level[2 * (size_t)h], r0[e][b]);
-            unsafeAtomicAdd(&g_level[2 * (size_t)h + 1], r1[e][b]);
+          }
+        } else {
+#pragma unroll 1
+          for (int b = 0; b < 8; ++b) {
+            const uint32_t h = rh[e][b];
+            if (pos[b] < cap) {
+              const size_t at = (size_t)(h >> bucket_log2) * cap + pos[b];
+              rec_key[at] = (uint16_t)(h & emask);
+              rec_val[at] = make_float2(r0[e][b], r1[e][b]);
+            } else {  // bucket full: add straight into the table
+              unsafeAtomicAdd(&g_level[2 * (size_t)h], r0[e][b]);
+              unsafeAtomicAdd(&g_level[2 * (size_t)h + 1], r1[e][b]);
+            }
           }
         }
       }
