@@ -912,22 +912,32 @@ __global__ __launch_bounds__(kTexThreads) void texture_backward_kernel(
       if (feat_grad && si.valid && l < gd.levels) feat_grad[((int64_t)l * nqK + qj) * 16 + c] = make_float2(e0, e1);
       if (active) {
         const GridLevel& L = gd.lv[l];
-        const LevelGeom lg = level_geom(L, si);
-        float gpx = 0.f, gpy = 0.f, gpz = 0.f;
+        // fractional position in the cell (the gather computed the same values)
+        const float sD = L.scale * si.D;
+        const float Px = fmaf(sD, si.dx, L.ofrac[0]), Py = fmaf(sD, si.dy, L.ofrac[1]);
+        const float Pz = fmaf(sD, si.dz, L.ofrac[2]);
+        const float fx = Px - floorf(Px), fy = Py - floorf(Py), fz = Pz - floorf(Pz);
+        const float wx[2] = {1.f - fx, fx}, wy[2] = {1.f - fy, fy}, wz[2] = {1.f - fz, fz};
+        // q_b = theta_b . e; the trilinear weight's derivative along an axis is
+        // the product of the other two weights with sign +1 / -1 for the
+        // upper / lower corner, so each axis sums differences of q.
+        float qv[8];
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-          const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
-          const float wx = bx ? lg.frx : 1.f - lg.frx;
-          const float wy = by ? lg.fry : 1.f - lg.fry;
-          const float wz = bz ? lg.frz : 1.f - lg.frz;
           const float2 th = entry_value<TDT>(E.ent[i][b]);
-          const float qv = th.x * e0 + th.y * e1;
-          gpx += qv * (bx ? 1.f : -1.f) * wy * wz;
-          gpy += qv * (by ? 1.f : -1.f) * wx * wz;
-          gpz += qv * (bz ? 1.f : -1.f) * wx * wy;
+          qv[b] = fmaf(th.x, e0, th.y * e1);
         }
+        float gpx = 0.f, gpy = 0.f, gpz = 0.f;
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int v = 0; v < 2; ++v) {
+            gpx = fmaf(wy[u] * wz[v], qv[1 + 2 * u + 4 * v] - qv[2 * u + 4 * v], gpx);
+            gpy = fmaf(wx[u] * wz[v], qv[u + 2 + 4 * v] - qv[u + 4 * v], gpy);
+            gpz = fmaf(wx[u] * wy[v], qv[u + 2 * v + 4] - qv[u + 2 * v], gpz);
+          }
         // p = s (o + D d): dp/dD = s d. Delta = 1 - exp(-kappa/D^2): dDelta/dD = -(1-Delta) 2 kappa / D^3.
-        const float ddelta = -lg.expo * 2.0f * L.kappa / (si.D * si.D * si.D);
+        const float ddelta = -(1.0f - delta[i]) * 2.0f * L.kappa / (si.D * si.D * si.D);
         dD += L.scale * (gpx * si.dx + gpy * si.dy + gpz * si.dz) +
               ddelta * (fraw[2 * i] * gz0 + fraw[2 * i + 1] * gz1);
       }
