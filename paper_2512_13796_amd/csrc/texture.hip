@@ -93,12 +93,13 @@ __device__ __forceinline__ f4 mfma_f32_k4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// Orders this wave's LDS writes before its later LDS reads by other lanes:
-// wait for the wave's outstanding LDS operations only (global memory traffic
-// stays in flight) and stop the compiler moving memory accesses across.
+// Orders this wave's LDS writes before its later LDS reads by other lanes of
+// the same wave. A wave's LDS operations are performed in issue order, so no
+// hardware wait is needed: this only stops the compiler from moving memory
+// accesses across.
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_wave_barrier();
-  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  asm volatile("" ::: "memory");
   __builtin_amdgcn_wave_barrier();
 }
 
