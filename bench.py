@@ -183,7 +183,26 @@ def time_form(form, steps, warmup, workload="outdoor"):
           "L": wl.grid.levels, "T": 1 << wl.grid.log2_size, "F": wl.grid.feat, "tb": table.element_size(),
           "in": weights[0].shape[1], "H": weights[0].shape[0], "tile_passes": 2,
           "width": cams[0].width, "height": cams[0].height}
+    st["workload_stats"] = workload_stats(res, wl, K=wl.K)
     return {"ms": ms, "wall_ms": 1000.0 * wall / steps, "phases": phases, "stats": st, "workload": wl}
+
+
+def workload_stats(res, wl, K):
+    """Per-frame statistics of the rendered workload (outside the timed region)."""
+    import torch
+
+    P = res.image.shape[0]
+    n_iter = res.n_iter.to(torch.int64)
+    out = {"instances": int(res.n_instances),
+           "tiles_per_surfel": round(float(res.n_instances) / max(wl.scene.n * len(wl.cameras), 1), 3),
+           "tested_pairs_per_pixel": round(float(n_iter.sum()) / P, 2)}
+    if K > 0:
+        filled = (res.ids[:, :K] >= 0).sum(dim=1)
+        out["mean_selected_per_pixel"] = round(float(filled.double().mean()), 3)
+        out["frac_pixels_under_K"] = round(float((filled < K).double().mean()), 4)
+        out["mean_selected_weight"] = round(float(res.weights[:, :K].sum(dim=1).double().mean()), 4)
+    out["mean_T_final"] = round(float(res.t_final.double().mean()), 4)
+    return out
 
 
 def cpu_baseline(sample_pixels=4096, seed=0):
@@ -255,7 +274,7 @@ def main():
         roof["mfma_tflops"] = round(nflops / dur_s / 1e12, 2)
         roof["mfma_frac"] = round(nflops / dur_s / 1e12 / BF16_PEAK_TFLOPS, 5)
     cfg = {"workload": WORKLOADS[args.workload][1], "surfels": st["N"], "cameras": st["C"], "pixels": P,
-           "K": st["K"], "instances": st["I"]}
+           "K": st["K"], "instances": st["I"], "stats": st["workload_stats"]}
     if st["C"] == 1:
         cfg.update(width=st["width"], height=st["height"])
     dtype = {"outdoor": "bf16", "multiview": "f32", "large": "bf16"}[args.workload]
