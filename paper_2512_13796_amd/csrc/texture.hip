@@ -28,6 +28,7 @@
 // LDS per workgroup and adds them to global memory once, and scatters the
 // hash-grid gradient with FP32 atomics.
 #include <hip/hip_fp16.h>
+#include <type_traits>
 #include <math.h>
 
 #include "nx_internal.h"
@@ -785,10 +786,41 @@ __global__ __launch_bounds__(kTexThreads) void texture_backward_kernel(
         dlog[r] = dt * t * (1.0f - t);
       }
     }
-    // ---- MLP backward
-    f4 dh2[MT], dh1[MT], dzt[2];
+    // ---- MLP backward, layer by layer: each layer's weight gradient is
+    // formed as soon as its two factors exist, so the activations die early
+    // (h2 after layer 3, dH2 and h1 after layer 2, dH1 after layer 1).
+    // Weight gradients go through per-wave LDS transposes (samples become the
+    // K index of the product).
+    auto wgrad = [&](auto NMO_c, auto NMI_c, float* dw_at, int ld, int out_rows, int in_cols) {
+      constexpr int NMO = decltype(NMO_c)::value, NMI = decltype(NMI_c)::value;
+      wave_sync_lds();
+      if constexpr (kRegAcc) {
+        if constexpr (NMO == 1) {
+          weight_grad_accum<BF, 1, MT>(tY, tX, accW3, lane);
+        } else if constexpr (NMI == 2) {
+          weight_grad_accum<BF, MT, 2>(tY, tX, accW1, lane);
+        } else {
+          weight_grad_accum<BF, MT, MT>(tY, tX, accW2, lane);
+        }
+      } else {
+        weight_grad_tiles<BF>(tY, tX, NMO, NMI, dw_at, ld, out_rows, in_cols, lane);
+      }
+      wave_sync_lds();
+    };
+    using C1 = std::integral_constant<int, 1>;
+    using C2 = std::integral_constant<int, 2>;
+    using CM = std::integral_constant<int, MT>;
+    f4 dzt[2];
+    // layer 3: dW3 = dlogit x H2^T, then dH2 = mask(h2) . (W3^T dlogit)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) put_rows<BF>(tY, 4 * g + r, c, dlog[r]);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) put_rows<BF>(tX, 16 * mt + 4 * g + r, c, h2[mt][r]);
+    wgrad(C1{}, CM{}, dw + nW1 + nW2, HID, 3, HID);
+    f4 dh2[MT];
     if constexpr (BF) {
-      constexpr int HT = LY::HT;
       s8 bd;
 #pragma unroll
       for (int e = 0; e < 8; ++e) bd[e] = e < 4 ? f2bf(dlog[e]) : (short)0;
@@ -799,6 +831,29 @@ __global__ __launch_bounds__(kTexThreads) void texture_backward_kernel(
         for (int r = 0; r < 4; ++r) a[r] = h2[mt][r] > 0.f ? a[r] : 0.f;
         dh2[mt] = a;
       }
+    } else {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        f4 a = zero;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a = mfma_f32_k4(Operand<false>::get(W, LY::oA3T + mt * 4 + r, lane), dlog[r], a);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[r] = h2[mt][r] > 0.f ? a[r] : 0.f;
+        dh2[mt] = a;
+      }
+    }
+    // layer 2: dW2 = dH2 x H1^T, then dH1 = mask(h1) . (W2^T dH2)
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        put_rows<BF>(tY, 16 * mt + 4 * g + r, c, dh2[mt][r]);
+        put_rows<BF>(tX, 16 * mt + 4 * g + r, c, h1[mt][r]);
+      }
+    wgrad(CM{}, CM{}, dw + nW1, HID, HID, HID);
+    f4 dh1[MT];
+    if constexpr (BF) {
+      constexpr int HT = LY::HT;
       s8 b2[HT];
 #pragma unroll
       for (int h = 0; h < HT; ++h) b2[h] = pack_tiles(dh2[2 * h], dh2[2 * h + 1]);
@@ -811,26 +866,7 @@ __global__ __launch_bounds__(kTexThreads) void texture_backward_kernel(
         for (int r = 0; r < 4; ++r) a[r] = h1[mt][r] > 0.f ? a[r] : 0.f;
         dh1[mt] = a;
       }
-      s8 b1[HT];
-#pragma unroll
-      for (int h = 0; h < HT; ++h) b1[h] = pack_tiles(dh1[2 * h], dh1[2 * h + 1]);
-#pragma unroll
-      for (int mz = 0; mz < 2; ++mz) {
-        f4 a = zero;
-#pragma unroll
-        for (int h = 0; h < HT; ++h) a = mfma_bf16_k32(Operand<true>::get(W, LY::oA1T + mz * HT + h, lane), b1[h], a);
-        dzt[mz] = a;
-      }
     } else {
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        f4 a = zero;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) a = mfma_f32_k4(Operand<false>::get(W, LY::oA3T + mt * 4 + r, lane), dlog[r], a);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) a[r] = h2[mt][r] > 0.f ? a[r] : 0.f;
-        dh2[mt] = a;
-      }
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         f4 a = zero;
@@ -843,6 +879,28 @@ __global__ __launch_bounds__(kTexThreads) void texture_backward_kernel(
         for (int r = 0; r < 4; ++r) a[r] = h1[mt][r] > 0.f ? a[r] : 0.f;
         dh1[mt] = a;
       }
+    }
+    // layer 1: dW1 = dH1 x Z^T, then dZ = W1^T dH1
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) put_rows<BF>(tY, 16 * mt + 4 * g + r, c, dh1[mt][r]);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) put_rows<BF>(tX, feat_index(g, e), c, z[e]);
+    wgrad(CM{}, C2{}, dw, kInPad, HID, in_dim);
+    if constexpr (BF) {
+      constexpr int HT = LY::HT;
+      s8 b1[HT];
+#pragma unroll
+      for (int h = 0; h < HT; ++h) b1[h] = pack_tiles(dh1[2 * h], dh1[2 * h + 1]);
+#pragma unroll
+      for (int mz = 0; mz < 2; ++mz) {
+        f4 a = zero;
+#pragma unroll
+        for (int h = 0; h < HT; ++h) a = mfma_bf16_k32(Operand<true>::get(W, LY::oA1T + mz * HT + h, lane), b1[h], a);
+        dzt[mz] = a;
+      }
+    } else {
 #pragma unroll
       for (int mz = 0; mz < 2; ++mz) {
         f4 a = zero;
@@ -854,50 +912,6 @@ __global__ __launch_bounds__(kTexThreads) void texture_backward_kernel(
         dzt[mz] = a;
       }
     }
-    // ---- weight gradients through per-wave LDS transposes
-    // dW3 = dlogit x H2^T
-#pragma unroll
-    for (int r = 0; r < 4; ++r) put_rows<BF>(tY, 4 * g + r, c, dlog[r]);
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) put_rows<BF>(tX, 16 * mt + 4 * g + r, c, h2[mt][r]);
-    wave_sync_lds();
-    if constexpr (kRegAcc) {
-      weight_grad_accum<BF, 1, MT>(tY, tX, accW3, lane);
-    } else {
-      weight_grad_tiles<BF>(tY, tX, 1, MT, dw + nW1 + nW2, HID, 3, HID, lane);
-    }
-    wave_sync_lds();
-    // dW2 = dH2 x H1^T
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        put_rows<BF>(tY, 16 * mt + 4 * g + r, c, dh2[mt][r]);
-        put_rows<BF>(tX, 16 * mt + 4 * g + r, c, h1[mt][r]);
-      }
-    wave_sync_lds();
-    if constexpr (kRegAcc) {
-      weight_grad_accum<BF, MT, MT>(tY, tX, accW2, lane);
-    } else {
-      weight_grad_tiles<BF>(tY, tX, MT, MT, dw + nW1, HID, HID, HID, lane);
-    }
-    wave_sync_lds();
-    // dW1 = dH1 x Z^T
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) put_rows<BF>(tY, 16 * mt + 4 * g + r, c, dh1[mt][r]);
-#pragma unroll
-    for (int e = 0; e < 8; ++e) put_rows<BF>(tX, feat_index(g, e), c, z[e]);
-    wave_sync_lds();
-    if constexpr (kRegAcc) {
-      weight_grad_accum<BF, MT, 2>(tY, tX, accW1, lane);
-    } else {
-      weight_grad_tiles<BF>(tY, tX, MT, 2, dw, kInPad, HID, in_dim, lane);
-    }
-    wave_sync_lds();
     // ---- per-level feature gradients (distributed over the cell corners by
     // the hash-scatter kernel) and the depth gradient through the sample
     // position and Delta_l
