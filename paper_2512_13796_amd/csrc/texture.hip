@@ -564,14 +564,6 @@ __global__ __launch_bounds__(kTexThreads) void texture_forward_kernel(GridDev gd
   }
 }
 
-// Per-wave scratch for the weight-gradient transposes: two [HID][16] tiles.
-template <bool BF, int HID>
-struct TLayout {
-  static constexpr int elem = BF ? 2 : 4;
-  static constexpr int tile_bytes = HID * 16 * elem;
-  static constexpr int wave_bytes = 2 * tile_bytes;
-};
-
 // Write a register tile set (rows 16 mt + 4 g + r, column c) into an LDS
 // [rows][16] matrix.
 template <bool BF>
@@ -583,58 +575,10 @@ __device__ __forceinline__ void put_rows(unsigned char* buf, int row, int c, flo
   }
 }
 
-// LDS float add as a compare-and-swap loop: LDS float atomics (ds_add_f32)
-// retire about one lane every three clocks per CU on this chip, a
-// compare-and-swap several lanes per clock. A lane retries only after another
-// update of the same word succeeded, so its rounds are bounded by the number
-// of updates the workgroup makes to that word.
-__device__ __forceinline__ void lds_add_f32(float* p, float v) {
-  uint32_t* w = reinterpret_cast<uint32_t*>(p);
-  uint32_t old = *w;
-  while (true) {
-    const uint32_t prev = atomicCAS(w, old, __float_as_uint(__uint_as_float(old) + v));
-    if (prev == old) break;
-    old = prev;
-  }
-}
-
-// dW[out][in] += sum over 16 samples of Y[out][s] X[in][s], for output row
-// tiles [0, n_mo) and input tiles [0, n_mi); result tile added into acc
-// (row-major, ld = ld_acc) with LDS atomics; rows >= out_rows are dropped.
-template <bool BF>
-__device__ __forceinline__ void weight_grad_tiles(const unsigned char* Y, const unsigned char* X, int n_mo, int n_mi,
-                                                  float* acc, int ld_acc, int out_rows, int in_cols, int lane) {
-  const int g = lane >> 4, c = lane & 15;
-  const f4 zero = {0.f, 0.f, 0.f, 0.f};
-  for (int mo = 0; mo < n_mo; ++mo) {
-    for (int mi = 0; mi < n_mi; ++mi) {
-      f4 d;
-      if constexpr (BF) {
-        const s4 a = *reinterpret_cast<const s4*>(reinterpret_cast<const short*>(Y) + (16 * mo + c) * 16 + 4 * g);
-        const s4 b = *reinterpret_cast<const s4*>(reinterpret_cast<const short*>(X) + (16 * mi + c) * 16 + 4 * g);
-        d = mfma_bf16_k16(a, b, zero);
-      } else {
-        d = zero;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float a = reinterpret_cast<const float*>(Y)[(16 * mo + c) * 16 + 4 * q + g];
-          const float b = reinterpret_cast<const float*>(X)[(16 * mi + c) * 16 + 4 * q + g];
-          d = mfma_f32_k4(a, b, d);
-        }
-      }
-      const int col = 16 * mi + c;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = 16 * mo + 4 * g + r;
-        if (row < out_rows && col < in_cols && d[r] != 0.0f) lds_add_f32(&acc[row * ld_acc + col], d[r]);
-      }
-    }
-  }
-}
-
-// Register-resident form of the same product: acc[mo * NMI + mi] += the
-// 16-sample contribution to output tile (mo, mi). The accumulators live across
-// the whole work loop, so the only LDS traffic per unit is the transposes.
+// dW[out][in] += sum over 16 samples of Y[out][s] X[in][s] for output row
+// tiles mo < NMO and column tiles mi < NMI: acc[mo * NMI + mi] += the
+// 16-sample contribution (samples are the K index of the product), reading
+// Y and X from LDS [rows][16] tiles.
 template <bool BF, int NMO, int NMI>
 __device__ __forceinline__ void weight_grad_accum(const unsigned char* Y, const unsigned char* X,
                                                   f4 (&acc)[NMO * NMI], int lane) {
@@ -658,24 +602,6 @@ __device__ __forceinline__ void weight_grad_accum(const unsigned char* Y, const 
       }
     }
   }
-}
-
-// Adds register tiles (rows 16 mo + 4 g + r, column 16 mi + c) into an LDS
-// matrix, dropping rows >= out_rows and columns >= in_cols.
-template <int NMO, int NMI>
-__device__ __forceinline__ void accum_to_lds(const f4 (&acc)[NMO * NMI], float* dst, int ld, int out_rows,
-                                             int in_cols, int lane) {
-  const int g = lane >> 4, c = lane & 15;
-#pragma unroll
-  for (int mo = 0; mo < NMO; ++mo)
-#pragma unroll
-    for (int mi = 0; mi < NMI; ++mi)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = 16 * mo + 4 * g + r, col = 16 * mi + c;
-        const float v = acc[mo * NMI + mi][r];
-        if (row < out_rows && col < in_cols && v != 0.0f) lds_add_f32(&dst[row * ld + col], v);
-      }
 }
 
 // Sum of v[0..15] over the 16 lanes of a row (c = lane % 16) with 15
@@ -712,23 +638,43 @@ __device__ __forceinline__ float row_transpose_sum16(const float v[16], int c, i
   return x;
 }
 
+// Per-unit activation tiles for the workgroup-cooperative weight gradients:
+// [rows][16 samples] in the MLP's storage precision. Rows: Y3 = dL/dlogit
+// (16, rows 0..2 used), X3 = h2, Y2 = dL/dh2, X2 = h1, Y1 = dL/dh1 (HID each),
+// X1 = z (32).
+template <bool BF, int HID>
+struct UnitTiles {
+  static constexpr int elem = BF ? 2 : 4;
+  static constexpr int oY3 = 0, oX3 = 16, oY2 = oX3 + HID, oX2 = oY2 + HID, oY1 = oX2 + HID, oX1 = oY1 + HID;
+  static constexpr int rows = oX1 + kInPad;
+  static constexpr int bytes = rows * 16 * elem;
+};
+
 // WLDS: operand slots staged in LDS by every workgroup (hidden width 64), or
 // read from wop in global memory (L2-resident; hidden width 128, whose slots
-// and FP32 weight-gradient accumulators do not fit in LDS together).
+// do not fit in LDS next to the activation tiles).
+//
+// Weight gradients: every round each of the 4 waves handles one unit (16
+// samples at one slot of a 4x4-pixel patch) and writes its activation tiles
+// to LDS; after a barrier every wave multiplies the tiles of all 4 units into
+// its own quarter of dW1, dW2 and dW3 (row tiles split across the waves),
+// which it keeps in MFMA accumulator registers for the whole launch and adds
+// to global memory once at the end.
 template <int TDT, bool BF, int HID, bool WLDS>
-__global__ __launch_bounds__(kTexThreads) void texture_backward_kernel(
+__global__ __launch_bounds__(kTexThreads, (HID <= 64 && BF) ? 2 : 1) void texture_backward_kernel(
     GridDev gd, const void* __restrict__ table, const void* w1, const void* w2, const void* w3,
     const unsigned char* __restrict__ wop, int in_dim, int K,
     int log2K, int64_t n_samples, const int32_t* __restrict__ ids, const float* __restrict__ depths,
     const float* __restrict__ weights, const float* __restrict__ grad_image, const float* __restrict__ grad_tex,
     float2* __restrict__ feat_grad, float* g_w1, float* g_w2, float* g_w3, float* __restrict__ grad_depth) {
   using LY = WLayout<BF, HID>;
-  using TL = TLayout<BF, HID>;
+  using UT = UnitTiles<BF, HID>;
   constexpr int MT = LY::MT;
-  constexpr int nW1 = HID * kInPad, nW2 = HID * HID, nW3 = 16 * HID;
+  constexpr int RT = MT / kWaves;           // row tiles of dW1 / dW2 per wave
+  constexpr int CT3 = MT / kWaves;          // column tiles of dW3 per wave
+  static_assert(RT >= 1 && RT * kWaves == MT, "hidden width must be a multiple of 64");
   __shared__ __attribute__((aligned(16))) unsigned char lds[WLDS ? LY::nAll * LY::slot_bytes : 16];
-  __shared__ __attribute__((aligned(16))) unsigned char tbuf[kWaves * TL::wave_bytes];
-  __shared__ float dw[nW1 + nW2 + nW3];
+  __shared__ __attribute__((aligned(16))) unsigned char tiles[kWaves * UT::bytes];
   const unsigned char* W;
   if constexpr (WLDS) {
     stage_weights<BF, HID>(lds, LY::nAll, w1, w2, w3, in_dim);
@@ -736,249 +682,244 @@ __global__ __launch_bounds__(kTexThreads) void texture_backward_kernel(
   } else {
     W = wop;
   }
-  for (int i = threadIdx.x; i < nW1 + nW2 + nW3; i += kTexThreads) dw[i] = 0.0f;
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, c = lane & 15;
-  unsigned char* tY = tbuf + wave * TL::wave_bytes;
-  unsigned char* tX = tY + TL::tile_bytes;
+  unsigned char* T = tiles + wave * UT::bytes;  // this wave's unit
+  auto row_ptr = [&](const unsigned char* base, int row) { return base + row * 16 * UT::elem; };
   const uint32_t mask = (1u << gd.log2_size) - 1u;
   const int64_t n_q = n_patches(gd);
+  const int64_t n_units = n_q * K;
   const f4 zero = {0.f, 0.f, 0.f, 0.f};
-  // Hidden width 64: weight gradients accumulate in registers for the whole
-  // loop (112 floats per lane). Width 128 would need 4x that, so it adds each
-  // unit's tiles into the LDS accumulators instead.
-  constexpr bool kRegAcc = HID <= 64;
-  f4 accW3[kRegAcc ? MT : 1], accW2[kRegAcc ? MT * MT : 1], accW1[kRegAcc ? 2 * MT : 1];
-  if constexpr (kRegAcc) {
+  f4 accW3[CT3], accW2[RT * MT], accW1[RT * 2];
 #pragma unroll
-    for (int i = 0; i < MT; ++i) accW3[i] = zero;
+  for (int i = 0; i < CT3; ++i) accW3[i] = zero;
 #pragma unroll
-    for (int i = 0; i < MT * MT; ++i) accW2[i] = zero;
+  for (int i = 0; i < RT * MT; ++i) accW2[i] = zero;
 #pragma unroll
-    for (int i = 0; i < 2 * MT; ++i) accW1[i] = zero;
-  }
+  for (int i = 0; i < RT * 2; ++i) accW1[i] = zero;
 
-  for (int64_t qj = (int64_t)blockIdx.x * kWaves + wave; qj < n_q * K; qj += (int64_t)gridDim.x * kWaves) {
-    const SampleInfo si = sample_info(gd, K, (int)(qj >> log2K), (int)(qj & (K - 1)), c, ids, depths, weights);
-    // ---- recompute features (all corner reads in flight together)
-    float z[8], fraw[8], delta[4];
-    LaneEntries<TDT> E;
-    gather_lane<TDT>(gd, table, si, g, mask, E, fraw, delta, nullptr);
+  const int64_t first = (int64_t)blockIdx.x * kWaves;
+  const int64_t stride = (int64_t)gridDim.x * kWaves;
+  const int64_t n_rounds = first < n_units ? (n_units - first + stride - 1) / stride : 0;
+  for (int64_t round = 0; round < n_rounds; ++round) {
+    const int64_t qj = first + round * stride + wave;
+    if (qj < n_units) {
+      const SampleInfo si = sample_info(gd, K, (int)(qj >> log2K), (int)(qj & (K - 1)), c, ids, depths, weights);
+      // ---- recompute features (all corner reads in flight together)
+      float z[8], fraw[8], delta[4];
+      LaneEntries<TDT> E;
+      gather_lane<TDT>(gd, table, si, g, mask, E, fraw, delta, nullptr);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      z[2 * i] = fraw[2 * i] * delta[i];
-      z[2 * i + 1] = fraw[2 * i + 1] * delta[i];
-    }
-    // ---- MLP forward, keeping activations
-    f4 h1[MT], h2[MT];
-    const f4 o = mlp_forward<BF, HID>(W, lane, z, h1, h2);
-    // ---- head: dL/dlogit for rows 0..2 of lane group 0
-    f4 dlog = zero;
-    if (g == 0 && si.has) {
-      const float g0 = grad_image[si.p * 3], g1 = grad_image[si.p * 3 + 1], g2 = grad_image[si.p * 3 + 2];
-      const float gi[3] = {g0, g1, g2};
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        const float t = 1.0f / (1.0f + __expf(-o[r]));
-        float dt = si.W * gi[r];
-        if (grad_tex) dt += grad_tex[si.s * 3 + r];
-        dlog[r] = dt * t * (1.0f - t);
+      for (int i = 0; i < 4; ++i) {
+        z[2 * i] = fraw[2 * i] * delta[i];
+        z[2 * i + 1] = fraw[2 * i + 1] * delta[i];
       }
-    }
-    // ---- MLP backward, layer by layer: each layer's weight gradient is
-    // formed as soon as its two factors exist, so the activations die early
-    // (h2 after layer 3, dH2 and h1 after layer 2, dH1 after layer 1).
-    // Weight gradients go through per-wave LDS transposes (samples become the
-    // K index of the product).
-    auto wgrad = [&](auto NMO_c, auto NMI_c, float* dw_at, int ld, int out_rows, int in_cols) {
-      constexpr int NMO = decltype(NMO_c)::value, NMI = decltype(NMI_c)::value;
-      wave_sync_lds();
-      if constexpr (kRegAcc) {
-        if constexpr (NMO == 1) {
-          weight_grad_accum<BF, 1, MT>(tY, tX, accW3, lane);
-        } else if constexpr (NMI == 2) {
-          weight_grad_accum<BF, MT, 2>(tY, tX, accW1, lane);
-        } else {
-          weight_grad_accum<BF, MT, MT>(tY, tX, accW2, lane);
+      // ---- MLP forward, keeping activations
+      f4 h1[MT], h2[MT];
+      const f4 o = mlp_forward<BF, HID>(W, lane, z, h1, h2);
+      // ---- head: dL/dlogit for rows 0..2 of lane group 0
+      f4 dlog = zero;
+      if (g == 0 && si.has) {
+        const float g0 = grad_image[si.p * 3], g1 = grad_image[si.p * 3 + 1], g2 = grad_image[si.p * 3 + 2];
+        const float gi[3] = {g0, g1, g2};
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          const float t = 1.0f / (1.0f + __expf(-o[r]));
+          float dt = si.W * gi[r];
+          if (grad_tex) dt += grad_tex[si.s * 3 + r];
+          dlog[r] = dt * t * (1.0f - t);
+        }
+      }
+      // ---- MLP backward, layer by layer; each layer's two weight-gradient
+      // factors go to this wave's tiles as soon as they exist, so the
+      // activations die early (h2 after layer 3, dH2 and h1 after layer 2).
+      f4 dzt[2];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) put_rows<BF>(T, UT::oY3 + 4 * g + r, c, dlog[r]);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) put_rows<BF>(T, UT::oX3 + 16 * mt + 4 * g + r, c, h2[mt][r]);
+      f4 dh2[MT];
+      if constexpr (BF) {
+        s8 bd;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bd[e] = e < 4 ? f2bf(dlog[e]) : (short)0;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          f4 a = mfma_bf16_k32(Operand<true>::get(W, LY::oA3T + mt, lane), bd, zero);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) a[r] = h2[mt][r] > 0.f ? a[r] : 0.f;
+          dh2[mt] = a;
         }
       } else {
-        weight_grad_tiles<BF>(tY, tX, NMO, NMI, dw_at, ld, out_rows, in_cols, lane);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          f4 a = zero;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) a = mfma_f32_k4(Operand<false>::get(W, LY::oA3T + mt * 4 + r, lane), dlog[r], a);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) a[r] = h2[mt][r] > 0.f ? a[r] : 0.f;
+          dh2[mt] = a;
+        }
       }
-      wave_sync_lds();
-    };
-    using C1 = std::integral_constant<int, 1>;
-    using C2 = std::integral_constant<int, 2>;
-    using CM = std::integral_constant<int, MT>;
-    f4 dzt[2];
-    // layer 3: dW3 = dlogit x H2^T, then dH2 = mask(h2) . (W3^T dlogit)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) put_rows<BF>(tY, 4 * g + r, c, dlog[r]);
+      for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+        for (int r = 0; r < 4; ++r) {
+          put_rows<BF>(T, UT::oY2 + 16 * mt + 4 * g + r, c, dh2[mt][r]);
+          put_rows<BF>(T, UT::oX2 + 16 * mt + 4 * g + r, c, h1[mt][r]);
+        }
+      f4 dh1[MT];
+      if constexpr (BF) {
+        constexpr int HT = LY::HT;
+        s8 b2[HT];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) put_rows<BF>(tX, 16 * mt + 4 * g + r, c, h2[mt][r]);
-    wgrad(C1{}, CM{}, dw + nW1 + nW2, HID, 3, HID);
-    f4 dh2[MT];
-    if constexpr (BF) {
-      s8 bd;
+        for (int h = 0; h < HT; ++h) b2[h] = pack_tiles(dh2[2 * h], dh2[2 * h + 1]);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) bd[e] = e < 4 ? f2bf(dlog[e]) : (short)0;
+        for (int mt = 0; mt < MT; ++mt) {
+          f4 a = zero;
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        f4 a = mfma_bf16_k32(Operand<true>::get(W, LY::oA3T + mt, lane), bd, zero);
+          for (int h = 0; h < HT; ++h) a = mfma_bf16_k32(Operand<true>::get(W, LY::oA2T + mt * HT + h, lane), b2[h], a);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) a[r] = h2[mt][r] > 0.f ? a[r] : 0.f;
-        dh2[mt] = a;
+          for (int r = 0; r < 4; ++r) a[r] = h1[mt][r] > 0.f ? a[r] : 0.f;
+          dh1[mt] = a;
+        }
+      } else {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          f4 a = zero;
+#pragma unroll
+          for (int mi = 0; mi < MT; ++mi)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              a = mfma_f32_k4(Operand<false>::get(W, LY::oA2T + (mt * MT + mi) * 4 + r, lane), dh2[mi][r], a);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) a[r] = h1[mt][r] > 0.f ? a[r] : 0.f;
+          dh1[mt] = a;
+        }
       }
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) put_rows<BF>(T, UT::oY1 + 16 * mt + 4 * g + r, c, dh1[mt][r]);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) put_rows<BF>(T, UT::oX1 + feat_index(g, e), c, z[e]);
+      if constexpr (BF) {
+        constexpr int HT = LY::HT;
+        s8 b1[HT];
+#pragma unroll
+        for (int h = 0; h < HT; ++h) b1[h] = pack_tiles(dh1[2 * h], dh1[2 * h + 1]);
+#pragma unroll
+        for (int mz = 0; mz < 2; ++mz) {
+          f4 a = zero;
+#pragma unroll
+          for (int h = 0; h < HT; ++h) a = mfma_bf16_k32(Operand<true>::get(W, LY::oA1T + mz * HT + h, lane), b1[h], a);
+          dzt[mz] = a;
+        }
+      } else {
+#pragma unroll
+        for (int mz = 0; mz < 2; ++mz) {
+          f4 a = zero;
+#pragma unroll
+          for (int mi = 0; mi < MT; ++mi)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              a = mfma_f32_k4(Operand<false>::get(W, LY::oA1T + (mz * MT + mi) * 4 + r, lane), dh1[mi][r], a);
+          dzt[mz] = a;
+        }
+      }
+      // ---- per-level feature gradients (distributed over the cell corners by
+      // the hash-scatter kernel) and the depth gradient through the sample
+      // position and Delta_l
+      float dD = 0.f;
+      const int64_t nqK = n_q * K;
+  #pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int l = lane_level(g, i);
+        const bool active = E.act[i];
+        const float gz0 = i < 2 ? dzt[0][2 * i] : dzt[1][2 * (i - 2)];
+        const float gz1 = i < 2 ? dzt[0][2 * i + 1] : dzt[1][2 * (i - 2) + 1];
+        const float e0 = active ? gz0 * delta[i] : 0.f, e1 = active ? gz1 * delta[i] : 0.f;
+        if (feat_grad && si.valid && l < gd.levels) feat_grad[((int64_t)l * nqK + qj) * 16 + c] = make_float2(e0, e1);
+        if (active) {
+          const GridLevel& L = gd.lv[l];
+          // fractional position in the cell (the gather computed the same values)
+          const float sD = L.scale * si.D;
+          const float Px = fmaf(sD, si.dx, L.ofrac[0]), Py = fmaf(sD, si.dy, L.ofrac[1]);
+          const float Pz = fmaf(sD, si.dz, L.ofrac[2]);
+          const float fx = Px - floorf(Px), fy = Py - floorf(Py), fz = Pz - floorf(Pz);
+          const float wx[2] = {1.f - fx, fx}, wy[2] = {1.f - fy, fy}, wz[2] = {1.f - fz, fz};
+          // q_b = theta_b . e; the trilinear weight's derivative along an axis is
+          // the product of the other two weights with sign +1 / -1 for the
+          // upper / lower corner, so each axis sums differences of q.
+          float qv[8];
+  #pragma unroll
+          for (int b = 0; b < 8; ++b) {
+            const float2 th = entry_value<TDT>(E.ent[i][b]);
+            qv[b] = fmaf(th.x, e0, th.y * e1);
+          }
+          float gpx = 0.f, gpy = 0.f, gpz = 0.f;
+  #pragma unroll
+          for (int u = 0; u < 2; ++u)
+  #pragma unroll
+            for (int v = 0; v < 2; ++v) {
+              gpx = fmaf(wy[u] * wz[v], qv[1 + 2 * u + 4 * v] - qv[2 * u + 4 * v], gpx);
+              gpy = fmaf(wx[u] * wz[v], qv[u + 2 + 4 * v] - qv[u + 4 * v], gpy);
+              gpz = fmaf(wx[u] * wy[v], qv[u + 2 * v + 4] - qv[u + 2 * v], gpz);
+            }
+          // p = s (o + D d): dp/dD = s d. Delta = 1 - exp(-kappa/D^2): dDelta/dD = -(1-Delta) 2 kappa / D^3.
+          const float ddelta = -(1.0f - delta[i]) * 2.0f * L.kappa / (si.D * si.D * si.D);
+          dD += L.scale * (gpx * si.dx + gpy * si.dy + gpz * si.dz) +
+                ddelta * (fraw[2 * i] * gz0 + fraw[2 * i + 1] * gz1);
+        }
+      }
+      dD += __shfl_xor(dD, 16, 64);
+      dD += __shfl_xor(dD, 32, 64);
+      if (g == 0 && si.valid && grad_depth) grad_depth[si.s] = si.has ? dD : 0.f;
     } else {
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        f4 a = zero;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) a = mfma_f32_k4(Operand<false>::get(W, LY::oA3T + mt * 4 + r, lane), dlog[r], a);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) a[r] = h2[mt][r] > 0.f ? a[r] : 0.f;
-        dh2[mt] = a;
-      }
+      // no unit for this wave in the last round: zero tiles add nothing
+      for (int i = lane; i < UT::bytes / 4; i += 64) reinterpret_cast<uint32_t*>(T)[i] = 0u;
     }
-    // layer 2: dW2 = dH2 x H1^T, then dH1 = mask(h1) . (W2^T dH2)
+    __syncthreads();
+    // ---- this wave's quarter of the weight gradients over the round's 4 units
+#pragma unroll 1
+    for (int u = 0; u < kWaves; ++u) {
+      const unsigned char* U = tiles + u * UT::bytes;
+      weight_grad_accum<BF, 1, CT3>(row_ptr(U, UT::oY3), row_ptr(U, UT::oX3 + 16 * CT3 * wave), accW3, lane);
+      weight_grad_accum<BF, RT, MT>(row_ptr(U, UT::oY2 + 16 * RT * wave), row_ptr(U, UT::oX2), accW2, lane);
+      weight_grad_accum<BF, RT, 2>(row_ptr(U, UT::oY1 + 16 * RT * wave), row_ptr(U, UT::oX1), accW1, lane);
+    }
+    __syncthreads();
+  }
+  // ---- add this wave's weight-gradient tiles to global memory
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+  for (int mi = 0; mi < CT3; ++mi)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 4 * g + r, col = 16 * (CT3 * wave + mi) + c;
+      const float v = accW3[mi][r];
+      if (g_w3 && row < 3 && v != 0.0f) unsafeAtomicAdd(&g_w3[row * HID + col], v);
+    }
+#pragma unroll
+  for (int mo = 0; mo < RT; ++mo) {
+#pragma unroll
+    for (int mi = 0; mi < MT; ++mi)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        put_rows<BF>(tY, 16 * mt + 4 * g + r, c, dh2[mt][r]);
-        put_rows<BF>(tX, 16 * mt + 4 * g + r, c, h1[mt][r]);
+        const int row = 16 * (RT * wave + mo) + 4 * g + r, col = 16 * mi + c;
+        const float v = accW2[mo * MT + mi][r];
+        if (g_w2 && v != 0.0f) unsafeAtomicAdd(&g_w2[row * HID + col], v);
       }
-    wgrad(CM{}, CM{}, dw + nW1, HID, HID, HID);
-    f4 dh1[MT];
-    if constexpr (BF) {
-      constexpr int HT = LY::HT;
-      s8 b2[HT];
 #pragma unroll
-      for (int h = 0; h < HT; ++h) b2[h] = pack_tiles(dh2[2 * h], dh2[2 * h + 1]);
+    for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        f4 a = zero;
-#pragma unroll
-        for (int h = 0; h < HT; ++h) a = mfma_bf16_k32(Operand<true>::get(W, LY::oA2T + mt * HT + h, lane), b2[h], a);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) a[r] = h1[mt][r] > 0.f ? a[r] : 0.f;
-        dh1[mt] = a;
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * (RT * wave + mo) + 4 * g + r, col = 16 * mi + c;
+        const float v = accW1[mo * 2 + mi][r];
+        if (g_w1 && col < in_dim && v != 0.0f) unsafeAtomicAdd(&g_w1[row * in_dim + col], v);
       }
-    } else {
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        f4 a = zero;
-#pragma unroll
-        for (int mi = 0; mi < MT; ++mi)
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            a = mfma_f32_k4(Operand<false>::get(W, LY::oA2T + (mt * MT + mi) * 4 + r, lane), dh2[mi][r], a);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) a[r] = h1[mt][r] > 0.f ? a[r] : 0.f;
-        dh1[mt] = a;
-      }
-    }
-    // layer 1: dW1 = dH1 x Z^T, then dZ = W1^T dH1
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) put_rows<BF>(tY, 16 * mt + 4 * g + r, c, dh1[mt][r]);
-#pragma unroll
-    for (int e = 0; e < 8; ++e) put_rows<BF>(tX, feat_index(g, e), c, z[e]);
-    wgrad(CM{}, C2{}, dw, kInPad, HID, in_dim);
-    if constexpr (BF) {
-      constexpr int HT = LY::HT;
-      s8 b1[HT];
-#pragma unroll
-      for (int h = 0; h < HT; ++h) b1[h] = pack_tiles(dh1[2 * h], dh1[2 * h + 1]);
-#pragma unroll
-      for (int mz = 0; mz < 2; ++mz) {
-        f4 a = zero;
-#pragma unroll
-        for (int h = 0; h < HT; ++h) a = mfma_bf16_k32(Operand<true>::get(W, LY::oA1T + mz * HT + h, lane), b1[h], a);
-        dzt[mz] = a;
-      }
-    } else {
-#pragma unroll
-      for (int mz = 0; mz < 2; ++mz) {
-        f4 a = zero;
-#pragma unroll
-        for (int mi = 0; mi < MT; ++mi)
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            a = mfma_f32_k4(Operand<false>::get(W, LY::oA1T + (mz * MT + mi) * 4 + r, lane), dh1[mi][r], a);
-        dzt[mz] = a;
-      }
-    }
-    // ---- per-level feature gradients (distributed over the cell corners by
-    // the hash-scatter kernel) and the depth gradient through the sample
-    // position and Delta_l
-    float dD = 0.f;
-    const int64_t nqK = n_q * K;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int l = lane_level(g, i);
-      const bool active = E.act[i];
-      const float gz0 = i < 2 ? dzt[0][2 * i] : dzt[1][2 * (i - 2)];
-      const float gz1 = i < 2 ? dzt[0][2 * i + 1] : dzt[1][2 * (i - 2) + 1];
-      const float e0 = active ? gz0 * delta[i] : 0.f, e1 = active ? gz1 * delta[i] : 0.f;
-      if (feat_grad && si.valid && l < gd.levels) feat_grad[((int64_t)l * nqK + qj) * 16 + c] = make_float2(e0, e1);
-      if (active) {
-        const GridLevel& L = gd.lv[l];
-        // fractional position in the cell (the gather computed the same values)
-        const float sD = L.scale * si.D;
-        const float Px = fmaf(sD, si.dx, L.ofrac[0]), Py = fmaf(sD, si.dy, L.ofrac[1]);
-        const float Pz = fmaf(sD, si.dz, L.ofrac[2]);
-        const float fx = Px - floorf(Px), fy = Py - floorf(Py), fz = Pz - floorf(Pz);
-        const float wx[2] = {1.f - fx, fx}, wy[2] = {1.f - fy, fy}, wz[2] = {1.f - fz, fz};
-        // q_b = theta_b . e; the trilinear weight's derivative along an axis is
-        // the product of the other two weights with sign +1 / -1 for the
-        // upper / lower corner, so each axis sums differences of q.
-        float qv[8];
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-          const float2 th = entry_value<TDT>(E.ent[i][b]);
-          qv[b] = fmaf(th.x, e0, th.y * e1);
-        }
-        float gpx = 0.f, gpy = 0.f, gpz = 0.f;
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-          for (int v = 0; v < 2; ++v) {
-            gpx = fmaf(wy[u] * wz[v], qv[1 + 2 * u + 4 * v] - qv[2 * u + 4 * v], gpx);
-            gpy = fmaf(wx[u] * wz[v], qv[u + 2 + 4 * v] - qv[u + 4 * v], gpy);
-            gpz = fmaf(wx[u] * wy[v], qv[u + 2 * v + 4] - qv[u + 2 * v], gpz);
-          }
-        // p = s (o + D d): dp/dD = s d. Delta = 1 - exp(-kappa/D^2): dDelta/dD = -(1-Delta) 2 kappa / D^3.
-        const float ddelta = -(1.0f - delta[i]) * 2.0f * L.kappa / (si.D * si.D * si.D);
-        dD += L.scale * (gpx * si.dx + gpy * si.dy + gpz * si.dz) +
-              ddelta * (fraw[2 * i] * gz0 + fraw[2 * i + 1] * gz1);
-      }
-    }
-    dD += __shfl_xor(dD, 16, 64);
-    dD += __shfl_xor(dD, 32, 64);
-    if (g == 0 && si.valid && grad_depth) grad_depth[si.s] = si.has ? dD : 0.f;
-  }
-  if constexpr (kRegAcc) {
-    accum_to_lds<1, MT>(accW3, dw + nW1 + nW2, HID, 3, HID, lane);
-    accum_to_lds<MT, MT>(accW2, dw + nW1, HID, HID, HID, lane);
-    accum_to_lds<MT, 2>(accW1, dw, kInPad, HID, in_dim, lane);
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < nW1 + nW2 + nW3; i += kTexThreads) {
-    const float v = dw[i];
-    if (v == 0.0f) continue;
-    if (i < nW1) {
-      const int row = i / kInPad, col = i % kInPad;
-      if (g_w1 && col < in_dim) unsafeAtomicAdd(&g_w1[row * in_dim + col], v);
-    } else if (i < nW1 + nW2) {
-      if (g_w2) unsafeAtomicAdd(&g_w2[i - nW1], v);
-    } else {
-      const int q = i - nW1 - nW2, row = q / HID;
-      if (g_w3 && row < 3) unsafeAtomicAdd(&g_w3[q], v);
-    }
   }
 }
 
