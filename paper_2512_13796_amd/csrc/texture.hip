@@ -436,7 +436,7 @@ struct LaneEntries {
 template <int TDT>
 __device__ __forceinline__ void gather_lane(const GridDev& gd, const void* table, const SampleInfo& si, int g,
                                             uint32_t mask, LaneEntries<TDT>& E, float fraw[8], float delta[4],
-                                            int32_t* cells_out) {
+                                            int32_t* cells_out, float* dcoef = nullptr) {
   LevelGeom lg[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -466,6 +466,43 @@ __device__ __forceinline__ void gather_lane(const GridDev& gd, const void* table
     fraw[2 * i] = E.act[i] ? f0 : 0.f;
     fraw[2 * i + 1] = E.act[i] ? f1 : 0.f;
     delta[i] = E.act[i] ? lg[i].delta : 0.f;
+    if (dcoef) {
+      // Depth derivative of this level's two features, as coefficients of the
+      // feature gradients gz (applied once the MLP backward has produced them):
+      // dL/dD = gz0 dcoef[2i] + gz1 dcoef[2i+1]. The sample point is
+      // p = s (o + D d), so dp/dD = s d; the trilinear weight's derivative
+      // along an axis is the product of the other two weights with sign + / -
+      // for the upper / lower corner; Delta = 1 - exp(-kappa/D^2) gives
+      // dDelta/dD = -(1 - Delta) 2 kappa / D^3.
+      const GridLevel& L = gd.lv[lane_level(g, i) < gd.levels ? lane_level(g, i) : 0];
+      const float wx[2] = {1.f - lg[i].frx, lg[i].frx}, wy[2] = {1.f - lg[i].fry, lg[i].fry};
+      const float wz[2] = {1.f - lg[i].frz, lg[i].frz};
+      float ax0 = 0.f, ax1 = 0.f, ay0 = 0.f, ay1 = 0.f, az0 = 0.f, az1 = 0.f;
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+          const float2 x0 = entry_value<TDT>(E.ent[i][2 * u + 4 * v]), x1 = entry_value<TDT>(E.ent[i][1 + 2 * u + 4 * v]);
+          const float2 y0 = entry_value<TDT>(E.ent[i][u + 4 * v]), y1 = entry_value<TDT>(E.ent[i][u + 2 + 4 * v]);
+          const float2 z0 = entry_value<TDT>(E.ent[i][u + 2 * v]), z1 = entry_value<TDT>(E.ent[i][u + 2 * v + 4]);
+          const float cx = wy[u] * wz[v], cy = wx[u] * wz[v], cz = wx[u] * wy[v];
+          ax0 = fmaf(cx, x1.x - x0.x, ax0);
+          ax1 = fmaf(cx, x1.y - x0.y, ax1);
+          ay0 = fmaf(cy, y1.x - y0.x, ay0);
+          ay1 = fmaf(cy, y1.y - y0.y, ay1);
+          az0 = fmaf(cz, z1.x - z0.x, az0);
+          az1 = fmaf(cz, z1.y - z0.y, az1);
+        }
+      const float ds = lg[i].delta * L.scale;
+      const float ddelta = -lg[i].expo * 2.0f * L.kappa / (si.D * si.D * si.D);
+      const float c0 = ds * (ax0 * si.dx + ay0 * si.dy + az0 * si.dz) + ddelta * f0;
+      const float c1 = ds * (ax1 * si.dx + ay1 * si.dy + az1 * si.dz) + ddelta * f1;
+      dcoef[2 * i] = E.act[i] ? c0 : 0.f;
+      dcoef[2 * i + 1] = E.act[i] ? c1 : 0.f;
+      // keep the coefficients here, so that the entries die now rather than
+      // being carried to the end of the backward pass
+      asm volatile("" : "+v"(dcoef[2 * i]), "+v"(dcoef[2 * i + 1]));
+    }
     if (cells_out && E.act[i]) {
       int32_t* cp = cells_out + lane_level(g, i) * 3;
       cp[0] = lg[i].cx;
@@ -707,9 +744,9 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 && BF) ? 2 : 1) void textur
     if (qj < n_units) {
       const SampleInfo si = sample_info(gd, K, (int)(qj >> log2K), (int)(qj & (K - 1)), c, ids, depths, weights);
       // ---- recompute features (all corner reads in flight together)
-      float z[8], fraw[8], delta[4];
+      float z[8], fraw[8], delta[4], dcoef[8];
       LaneEntries<TDT> E;
-      gather_lane<TDT>(gd, table, si, g, mask, E, fraw, delta, nullptr);
+      gather_lane<TDT>(gd, table, si, g, mask, E, fraw, delta, nullptr, dcoef);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         z[2 * i] = fraw[2 * i] * delta[i];
@@ -835,45 +872,14 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 && BF) ? 2 : 1) void textur
       // position and Delta_l
       float dD = 0.f;
       const int64_t nqK = n_q * K;
-  #pragma unroll
+#pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int l = lane_level(g, i);
-        const bool active = E.act[i];
         const float gz0 = i < 2 ? dzt[0][2 * i] : dzt[1][2 * (i - 2)];
         const float gz1 = i < 2 ? dzt[0][2 * i + 1] : dzt[1][2 * (i - 2) + 1];
-        const float e0 = active ? gz0 * delta[i] : 0.f, e1 = active ? gz1 * delta[i] : 0.f;
-        if (feat_grad && si.valid && l < gd.levels) feat_grad[((int64_t)l * nqK + qj) * 16 + c] = make_float2(e0, e1);
-        if (active) {
-          const GridLevel& L = gd.lv[l];
-          // fractional position in the cell (the gather computed the same values)
-          const float sD = L.scale * si.D;
-          const float Px = fmaf(sD, si.dx, L.ofrac[0]), Py = fmaf(sD, si.dy, L.ofrac[1]);
-          const float Pz = fmaf(sD, si.dz, L.ofrac[2]);
-          const float fx = Px - floorf(Px), fy = Py - floorf(Py), fz = Pz - floorf(Pz);
-          const float wx[2] = {1.f - fx, fx}, wy[2] = {1.f - fy, fy}, wz[2] = {1.f - fz, fz};
-          // q_b = theta_b . e; the trilinear weight's derivative along an axis is
-          // the product of the other two weights with sign +1 / -1 for the
-          // upper / lower corner, so each axis sums differences of q.
-          float qv[8];
-  #pragma unroll
-          for (int b = 0; b < 8; ++b) {
-            const float2 th = entry_value<TDT>(E.ent[i][b]);
-            qv[b] = fmaf(th.x, e0, th.y * e1);
-          }
-          float gpx = 0.f, gpy = 0.f, gpz = 0.f;
-  #pragma unroll
-          for (int u = 0; u < 2; ++u)
-  #pragma unroll
-            for (int v = 0; v < 2; ++v) {
-              gpx = fmaf(wy[u] * wz[v], qv[1 + 2 * u + 4 * v] - qv[2 * u + 4 * v], gpx);
-              gpy = fmaf(wx[u] * wz[v], qv[u + 2 + 4 * v] - qv[u + 4 * v], gpy);
-              gpz = fmaf(wx[u] * wy[v], qv[u + 2 * v + 4] - qv[u + 2 * v], gpz);
-            }
-          // p = s (o + D d): dp/dD = s d. Delta = 1 - exp(-kappa/D^2): dDelta/dD = -(1-Delta) 2 kappa / D^3.
-          const float ddelta = -(1.0f - delta[i]) * 2.0f * L.kappa / (si.D * si.D * si.D);
-          dD += L.scale * (gpx * si.dx + gpy * si.dy + gpz * si.dz) +
-                ddelta * (fraw[2 * i] * gz0 + fraw[2 * i + 1] * gz1);
-        }
+        if (feat_grad && si.valid && l < gd.levels)
+          feat_grad[((int64_t)l * nqK + qj) * 16 + c] = make_float2(gz0 * delta[i], gz1 * delta[i]);
+        dD = fmaf(gz0, dcoef[2 * i], fmaf(gz1, dcoef[2 * i + 1], dD));
       }
       dD += __shfl_xor(dD, 16, 64);
       dD += __shfl_xor(dD, 32, 64);
@@ -974,6 +980,10 @@ __device__ __forceinline__ bool lds_add_pair(unsigned long long* p, float a, flo
 
 constexpr int kBlockSamples = kScatUnits * 16;  // 512 samples per task
 static_assert(kBlockSamples == 2 * kScatThreads, "two samples per thread");
+constexpr int kBlockRecords = 8 * kBlockSamples;  // at most 8 corner records per sample
+constexpr int kScatStageBytes = kBlockRecords * (sizeof(uint32_t) + sizeof(float2));
+static_assert(kScatStageBytes >= sizeof(float) * 20 * kBlockSamples, "sample stage must fit the record stage");
+static_assert(kScatMaxBuckets % kScatThreads == 0, "bucket counts split evenly over the threads");
 
 // Cross-lane moves without the LDS permute path where the pattern allows:
 // DPP (quad_perm, row_ror, wave and row shifts, row broadcasts) and the
@@ -1092,10 +1102,18 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
     const float2* __restrict__ feat_grad, float* __restrict__ g_table, int bw, int bh, int nbx, int nby,
     int bucket_log2, uint32_t cap, uint32_t* __restrict__ bucket_count, uint16_t* __restrict__ rec_key,
     float2* __restrict__ rec_val) {
-  __shared__ float svals[16][kBlockSamples];  // [corner * 2 + feature][sample]: conflict-free by sample
-  __shared__ int scell[kBlockSamples][3];
-  __shared__ uint32_t skey[kBlockSamples];
-  __shared__ uint32_t hist[kScatMaxBuckets];
+  // LDS: the per-sample stage (corner values, cells, sort keys) and, once
+  // those are in registers, the block's records grouped by bucket share one
+  // region; per-bucket counters follow it (dynamic size: 2 nb words).
+  extern __shared__ __attribute__((aligned(16))) unsigned char scat_lds[];
+  auto& svals = *reinterpret_cast<float(*)[16][kBlockSamples]>(scat_lds);  // [corner * 2 + feature][sample]
+  auto& scell = *reinterpret_cast<int(*)[kBlockSamples][3]>(scat_lds + sizeof(float) * 16 * kBlockSamples);
+  uint32_t* skey = reinterpret_cast<uint32_t*>(scat_lds + sizeof(float) * 19 * kBlockSamples);
+  uint32_t* st_h = reinterpret_cast<uint32_t*>(scat_lds);                          // record: entry index
+  float2* st_v = reinterpret_cast<float2*>(scat_lds + sizeof(uint32_t) * kBlockRecords);  // record: 2 values
+  uint32_t* hist = reinterpret_cast<uint32_t*>(scat_lds + kScatStageBytes);  // count, then local cursor
+  uint32_t* gdelta = hist + (1 << (gd.log2_size - bucket_log2));             // global minus local position
+  __shared__ uint32_t wsum[kScatThreads / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, c = lane & 15;
   const int row = threadIdx.x >> 4;
   const uint32_t mask = (1u << gd.log2_size) - 1u;
@@ -1187,7 +1205,7 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
     // 4. records: a segment tail emits its cell's 8 corners (one branch per
     // tail; a record whose two values are zero is filed like any other)
     const bool emit[2] = {tail0 && live[0], tail1 && live[1]};
-    uint32_t rh[2][8];
+    uint32_t rh[2][8], rank[2][8];
     float r0[2][8], r1[2][8];
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
@@ -1203,49 +1221,79 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
         r0[e][b] = tot[2 * b];
         r1[e][b] = tot[2 * b + 1];
       }
-      if (emit[e]) {
+      // the count's old value is the record's rank among the block's records
+      // of its bucket
 #pragma unroll
-        for (int b = 0; b < 8; ++b) atomicAdd(&hist[rh[e][b] >> bucket_log2], 1u);
+      for (int b = 0; b < 8; ++b) rank[e][b] = emit[e] ? atomicAdd(&hist[rh[e][b] >> bucket_log2], 1u) : 0u;
+    }
+    __syncthreads();
+    // 5. local offsets of the buckets (exclusive scan of the counts), this
+    // block's space in every bucket it touches (one global cursor add each)
+    uint32_t n_rec = 0;
+    {
+      const int per = nb > kScatThreads ? nb / kScatThreads : 1;
+      const int b0 = threadIdx.x * per;
+      uint32_t cnt[kScatMaxBuckets / kScatThreads];
+      uint32_t run = 0;
+#pragma unroll
+      for (int i = 0; i < kScatMaxBuckets / kScatThreads; ++i) {
+        cnt[i] = (i < per && b0 + i < nb) ? hist[b0 + i] : 0u;
+        run += cnt[i];
       }
+      uint32_t incl = run;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += y;
+      }
+      if (lane == 63) wsum[wave] = incl;
+      __syncthreads();
+      uint32_t before = 0, total = 0;
+#pragma unroll
+      for (int w = 0; w < kScatThreads / 64; ++w) {
+        const uint32_t t = wsum[w];
+        before += w < wave ? t : 0u;
+        total += t;
+      }
+      uint32_t off = before + incl - run;
+#pragma unroll
+      for (int i = 0; i < kScatMaxBuckets / kScatThreads; ++i) {
+        if (i < per && b0 + i < nb) {
+          const uint32_t gbase = cnt[i] ? atomicAdd(&bucket_count[b0 + i], cnt[i]) : 0u;
+          gdelta[b0 + i] = gbase - off;
+          hist[b0 + i] = off;  // from here on: the bucket's local offset
+          off += cnt[i];
+        }
+      }
+      n_rec = total;
+      __syncthreads();
     }
-    __syncthreads();
-    // 5. reserve this block's space in every bucket it touches, then file
-    for (int i = threadIdx.x; i < nb; i += kScatThreads) {
-      const uint32_t n = hist[i];
-      hist[i] = n ? atomicAdd(&bucket_count[i], n) : 0u;
-    }
-    __syncthreads();
+    // 6. records into LDS, grouped by bucket (local offset + rank)
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       if (emit[e]) {
-        uint32_t pos[8];
-        bool fits = true;
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-          pos[b] = atomicAdd(&hist[rh[e][b] >> bucket_log2], 1u);
-          fits = fits && pos[b] < cap;
+          const uint32_t at = hist[rh[e][b] >> bucket_log2] + rank[e][b];
+          st_h[at] = rh[e][b];
+          st_v[at] = make_float2(r0[e][b], r1[e][b]);
         }
-        if (fits) {
-#pragma unroll
-          for (int b = 0; b < 8; ++b) {
-            const size_t at = (size_t)(rh[e][b] >> bucket_log2) * cap + pos[b];
-            rec_key[at] = (uint16_t)(rh[e][b] & emask);
-            rec_val[at] = make_float2(r0[e][b], r1[e][b]);
-          }
-        } else {
-#pragma unroll 1
-          for (int b = 0; b < 8; ++b) {
-            const uint32_t h = rh[e][b];
-            if (pos[b] < cap) {
-              const size_t at = (size_t)(h >> bucket_log2) * cap + pos[b];
-              rec_key[at] = (uint16_t)(h & emask);
-              rec_val[at] = make_float2(r0[e][b], r1[e][b]);
-            } else {  // bucket full: add straight into the table
-              unsafeAtomicAdd(&g_level[2 * (size_t)h], r0[e][b]);
-              unsafeAtomicAdd(&g_level[2 * (size_t)h + 1], r1[e][b]);
-            }
-          }
-        }
+      }
+    }
+    __syncthreads();
+    // 7. consecutive records of a bucket go to consecutive global slots
+    for (uint32_t i = threadIdx.x; i < n_rec; i += kScatThreads) {
+      const uint32_t h = st_h[i];
+      const float2 v = st_v[i];
+      const uint32_t bk = h >> bucket_log2;
+      const uint32_t pos = i + gdelta[bk];
+      if (pos < cap) {
+        const size_t at = (size_t)bk * cap + pos;
+        rec_key[at] = (uint16_t)(h & emask);
+        rec_val[at] = v;
+      } else {  // bucket full: add straight into the table
+        unsafeAtomicAdd(&g_level[2 * (size_t)h], v.x);
+        unsafeAtomicAdd(&g_level[2 * (size_t)h + 1], v.y);
       }
     }
     __syncthreads();
@@ -1472,7 +1520,8 @@ hipError_t launch_hash_scatter_bin(int K, const GridDev& grid, int level, const 
   if (n_blocks <= 0) return hipSuccess;
   int64_t wgs = (int64_t)compute_units() * 4;
   if (wgs > n_blocks) wgs = n_blocks;
-  hipLaunchKernelGGL(scatter_bin_kernel, dim3((unsigned)wgs), dim3(kScatThreads), 0, s, grid, grid.lv[level], K,
+  const size_t lds = kScatStageBytes + 2 * sizeof(uint32_t) * sl.nb;
+  hipLaunchKernelGGL(scatter_bin_kernel, dim3((unsigned)wgs), dim3(kScatThreads), lds, s, grid, grid.lv[level], K,
                      ilog2(K), level, depths, feat_grad, g_table, sg.bw, sg.bh, sg.nbx, sg.nby, sl.bl, sl.cap,
                      bucket_count, rec_key, rec_val);
   return hipGetLastError();
