@@ -978,6 +978,7 @@ __device__ __forceinline__ bool lds_add_pair(unsigned long long* p, float a, flo
   return false;
 }
 
+constexpr uint32_t kInactiveKey = 0x1FFFFFFu;  // above every 24-bit hash
 constexpr int kBlockSamples = kScatUnits * 16;  // 512 samples per task
 static_assert(kBlockSamples == 2 * kScatThreads, "two samples per thread");
 constexpr int kBlockRecords = 8 * kBlockSamples;  // at most 8 corner records per sample
@@ -1029,57 +1030,54 @@ __device__ __forceinline__ uint32_t lane_xor(uint32_t v) {
   }
 }
 
-// One compare-exchange stage (K_, J) of a bitonic sort for the two positions
-// p0 = 2 l + base, p0 + 1 held by this lane (l = lane), J <= 64: the partner of
-// a position lives in this lane (J = 1) or in lane l ^ (J / 2).
+// One compare-exchange stage (K_, J) of a bitonic sort of distinct keys for
+// the two positions p0 = 2 l + base, p0 + 1 held by this lane (l = lane),
+// J <= 64: the partner of a position lives in this lane (J = 1) or in lane
+// l ^ (J / 2). Ascending runs of length KK alternate with descending ones.
 template <int KK, int J>
-__device__ __forceinline__ void bitonic_stage_regs(uint32_t (&key)[2], uint32_t (&idx)[2], int p0) {
+__device__ __forceinline__ void bitonic_stage_regs(uint32_t (&key)[2], int p0) {
   if constexpr (J == 1) {
     const bool asc = (p0 & KK) == 0;
-    const bool swap = asc ? key[0] > key[1] : key[0] < key[1];
-    if (swap) {
-      const uint32_t tk = key[0], ti = idx[0];
-      key[0] = key[1];
-      idx[0] = idx[1];
-      key[1] = tk;
-      idx[1] = ti;
-    }
+    const uint32_t lo = min(key[0], key[1]), hi = max(key[0], key[1]);
+    key[0] = asc ? lo : hi;
+    key[1] = asc ? hi : lo;
   } else {
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       const int p = p0 + e;
-      const uint32_t ok = lane_xor<J / 2>(key[e]), oi = lane_xor<J / 2>(idx[e]);
-      const bool asc = (p & KK) == 0, lower = (p & J) == 0;
-      // the lower position keeps the smaller key when ascending
-      const bool take = (lower == asc) ? ok < key[e] : ok > key[e];
-      if (take) {
-        key[e] = ok;
-        idx[e] = oi;
-      }
+      const uint32_t ok = lane_xor<J / 2>(key[e]);
+      // the lower position of a pair keeps the smaller key in an ascending run
+      const bool keep_min = ((p & J) == 0) == ((p & KK) == 0);
+      key[e] = keep_min ? min(key[e], ok) : max(key[e], ok);
     }
   }
 }
 
 template <int KK, int J>
-__device__ __forceinline__ void bitonic_merge_regs(uint32_t (&key)[2], uint32_t (&idx)[2], int p0) {
-  bitonic_stage_regs<KK, J>(key, idx, p0);
-  if constexpr (J > 1) bitonic_merge_regs<KK, J / 2>(key, idx, p0);
+__device__ __forceinline__ void bitonic_merge_regs(uint32_t (&key)[2], int p0) {
+  bitonic_stage_regs<KK, J>(key, p0);
+  if constexpr (J > 1) bitonic_merge_regs<KK, J / 2>(key, p0);
 }
 
 template <int KK>
-__device__ __forceinline__ void bitonic_sort_regs(uint32_t (&key)[2], uint32_t (&idx)[2], int p0) {
-  bitonic_merge_regs<KK, KK / 2>(key, idx, p0);
-  if constexpr (KK < 128) bitonic_sort_regs<KK * 2>(key, idx, p0);
+__device__ __forceinline__ void bitonic_sort_regs(uint32_t (&key)[2], int p0) {
+  bitonic_merge_regs<KK, KK / 2>(key, p0);
+  if constexpr (KK < 128) bitonic_sort_regs<KK * 2>(key, p0);
 }
 
 // Inclusive segmented scan across the 64 lanes: on return v holds the sum of
 // v over the lanes from the start of this lane's segment (the nearest lane
-// at or before it with head set) to this lane. head becomes "a segment
-// starts at or before this lane".
-__device__ __forceinline__ void segmented_scan16(float (&v)[16], bool& head) {
+// at or before it with head set; lane 0 must have it) to this lane. A step
+// that reaches further back than any lane's segment start adds nothing and
+// is skipped (at fine levels almost every segment is a single lane).
+__device__ __forceinline__ void segmented_scan16(float (&v)[16], bool head) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long heads = __ballot(head) | 1ull;
+  const unsigned long long upto = heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
+  const int d = lane - (63 - __clzll(upto));  // lanes back to the segment start
   uint32_t h = head ? 1u : 0u;
-#define NX_SEG_STEP(CTRL, MASK)                                  \
-  {                                                              \
+#define NX_SEG_STEP(CTRL, MASK, NEEDED)                          \
+  if (__any(NEEDED)) {                                           \
     const uint32_t sh = dpp_u<CTRL, MASK>(h);                    \
     _Pragma("unroll") for (int q = 0; q < 16; ++q) {             \
       const float sv = dpp_f<CTRL, MASK>(v[q]);                  \
@@ -1087,14 +1085,13 @@ __device__ __forceinline__ void segmented_scan16(float (&v)[16], bool& head) {
     }                                                            \
     h |= sh;                                                     \
   }
-  NX_SEG_STEP(kDppRowShr1, 0xF)
-  NX_SEG_STEP(kDppRowShr1 + 1, 0xF)
-  NX_SEG_STEP(kDppRowShr1 + 3, 0xF)
-  NX_SEG_STEP(kDppRowShr1 + 7, 0xF)
-  NX_SEG_STEP(kDppRowBcast15, 0xA)
-  NX_SEG_STEP(kDppRowBcast31, 0xC)
+  NX_SEG_STEP(kDppRowShr1, 0xF, d >= 1)
+  NX_SEG_STEP(kDppRowShr1 + 1, 0xF, d >= 2)
+  NX_SEG_STEP(kDppRowShr1 + 3, 0xF, d >= 4)
+  NX_SEG_STEP(kDppRowShr1 + 7, 0xF, d >= 8)
+  NX_SEG_STEP(kDppRowBcast15, 0xA, d > (lane & 15))
+  NX_SEG_STEP(kDppRowBcast31, 0xC, d > (lane & 31))
 #undef NX_SEG_STEP
-  head = h != 0u;
 }
 
 __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
@@ -1156,24 +1153,27 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
       scell[smp][0] = lg.cx;
       scell[smp][1] = lg.cy;
       scell[smp][2] = lg.cz;
-      // inactive samples sort last and form no records
-      skey[smp] = act ? (lg.hx[0] ^ lg.hy[0] ^ lg.hz[0]) & 0x7FFFFFFFu : 0xFFFFFFFFu;
+      // sort key: 24 bits of the cell's hash above the sample's index within
+      // its wave's 128; inactive samples get a larger prefix, sort last and
+      // form no records (two cells that share the 24 bits only form two
+      // segments, as the segments compare the cells themselves)
+      const uint32_t hk = act ? (lg.hx[0] ^ lg.hy[0] ^ lg.hz[0]) & 0xFFFFFFu : kInactiveKey;
+      skey[smp] = (hk << 7) | (uint32_t)(smp & 127);
     }
     __syncthreads();
     // 2. bitonic sort of (key, sample) over each wave's 128 samples (the
     // wave's two patches, all slots); equal cells in different waves stay
     // separate records, which only costs a few duplicates at coarse levels
     uint32_t key[2] = {skey[p0], skey[p0 + 1]};
-    uint32_t idx[2] = {(uint32_t)p0, (uint32_t)p0 + 1u};
-    bitonic_sort_regs<2>(key, idx, p0);
+    bitonic_sort_regs<2>(key, p0);
     // 3. segments of equal cells along the sorted order, summed within each wave
     bool live[2];
     int cx[2], cy[2], cz[2];
     float a[2][16];
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      const int sm = (int)idx[e];
-      live[e] = key[e] != 0xFFFFFFFFu;
+      const int sm = 128 * wave + (int)(key[e] & 127u);
+      live[e] = (key[e] >> 7) != kInactiveKey;
       cx[e] = scell[sm][0];
       cy[e] = scell[sm][1];
       cz[e] = scell[sm][2];
@@ -1192,8 +1192,7 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
     float s1[16];
 #pragma unroll
     for (int v = 0; v < 16; ++v) s1[v] = same01 ? a[0][v] + a[1][v] : a[1][v];
-    bool head = !(same01 && cont0);
-    segmented_scan16(s1, head);
+    segmented_scan16(s1, !(same01 && cont0));
     // carry into element 0 from earlier lanes of its segment
     float carry[16];
 #pragma unroll
