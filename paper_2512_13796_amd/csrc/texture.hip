@@ -1187,51 +1187,37 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
     const int pcz = (int)dpp_u<kDppWaveShr1>((uint32_t)cz[1]);
     const bool plive = dpp_u<kDppWaveShr1>(live[1] ? 1u : 0u) != 0u;
     const bool cont0 = lane > 0 && plive == live[0] && pcx == cx[0] && pcy == cy[0] && pcz == cz[0];
-    // lane value: sum of element 1's segment within this lane; head flag: that
-    // segment starts in this lane
-    float s1[16];
-#pragma unroll
-    for (int v = 0; v < 16; ++v) s1[v] = same01 ? a[0][v] + a[1][v] : a[1][v];
-    segmented_scan16(s1, !(same01 && cont0));
-    // carry into element 0 from earlier lanes of its segment
-    float carry[16];
-#pragma unroll
-    for (int v = 0; v < 16; ++v) carry[v] = dpp_f<kDppWaveShr1>(s1[v]);
     // next lane's element 0 continues element 1's segment?
     const bool next_cont = dpp_u<kDppWaveShl1>(cont0 ? 1u : 0u) != 0u;
     const bool tail1 = lane == 63 || !next_cont;
     const bool tail0 = !same01;
-    // 4. records: a segment tail emits its cell's 8 corners (one branch per
-    // tail; a record whose two values are zero is filed like any other)
+    // 4. records: a segment tail emits its cell's 8 corners (a record whose
+    // two values are zero is filed like any other). Which records exist is
+    // known before their values, so they are counted first: the count's old
+    // value is the record's rank among the block's records of its bucket.
     const bool emit[2] = {tail0 && live[0], tail1 && live[1]};
     uint32_t rh[2][8], rank[2][8];
-    float r0[2][8], r1[2][8];
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      float tot[16];
-#pragma unroll
-      for (int v = 0; v < 16; ++v) tot[v] = e == 0 ? (cont0 ? carry[v] + a[0][v] : a[0][v]) : s1[v];
       const uint32_t hx0 = map_positive(cx[e]), hx1 = map_positive(cx[e] + 1);
       const uint32_t hy0 = map_positive(cy[e]) * kPrime1, hy1 = map_positive(cy[e] + 1) * kPrime1;
       const uint32_t hz0 = map_positive(cz[e]) * kPrime2, hz1 = map_positive(cz[e] + 1) * kPrime2;
 #pragma unroll
       for (int b = 0; b < 8; ++b) {
         rh[e][b] = ((b & 1 ? hx1 : hx0) ^ (b & 2 ? hy1 : hy0) ^ (b & 4 ? hz1 : hz0)) & mask;
-        r0[e][b] = tot[2 * b];
-        r1[e][b] = tot[2 * b + 1];
+        rank[e][b] = emit[e] ? atomicAdd(&hist[rh[e][b] >> bucket_log2], 1u) : 0u;
       }
-      // the count's old value is the record's rank among the block's records
-      // of its bucket
-#pragma unroll
-      for (int b = 0; b < 8; ++b) rank[e][b] = emit[e] ? atomicAdd(&hist[rh[e][b] >> bucket_log2], 1u) : 0u;
     }
     __syncthreads();
-    // 5. local offsets of the buckets (exclusive scan of the counts), this
-    // block's space in every bucket it touches (one global cursor add each)
+    // 5. local offsets of the buckets (exclusive scan of the counts) and this
+    // block's space in every bucket it touches (one global cursor add each).
+    // With one bucket per thread the cursor's reply is only needed in step 7,
+    // so it arrives while the values are summed and filed.
     uint32_t n_rec = 0;
+    const int per = nb > kScatThreads ? nb / kScatThreads : 1;
+    const int b0 = threadIdx.x * per;
+    uint32_t gbase_own = 0;
     {
-      const int per = nb > kScatThreads ? nb / kScatThreads : 1;
-      const int b0 = threadIdx.x * per;
       uint32_t cnt[kScatMaxBuckets / kScatThreads];
       uint32_t run = 0;
 #pragma unroll
@@ -1255,30 +1241,50 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
         total += t;
       }
       uint32_t off = before + incl - run;
+      if (per == 1) {
+        if (b0 < nb) {
+          gbase_own = cnt[0] ? atomicAdd(&bucket_count[b0], cnt[0]) : 0u;
+          hist[b0] = off;  // from here on: the bucket's local offset
+        }
+      } else {
 #pragma unroll
-      for (int i = 0; i < kScatMaxBuckets / kScatThreads; ++i) {
-        if (i < per && b0 + i < nb) {
-          const uint32_t gbase = cnt[i] ? atomicAdd(&bucket_count[b0 + i], cnt[i]) : 0u;
-          gdelta[b0 + i] = gbase - off;
-          hist[b0 + i] = off;  // from here on: the bucket's local offset
-          off += cnt[i];
+        for (int i = 0; i < kScatMaxBuckets / kScatThreads; ++i) {
+          if (i < per && b0 + i < nb) {
+            const uint32_t gbase = cnt[i] ? atomicAdd(&bucket_count[b0 + i], cnt[i]) : 0u;
+            gdelta[b0 + i] = gbase - off;
+            hist[b0 + i] = off;
+            off += cnt[i];
+          }
         }
       }
       n_rec = total;
       __syncthreads();
     }
-    // 6. records into LDS, grouped by bucket (local offset + rank)
+    // 6. values: element 1's lane value is the sum of its segment within this
+    // lane (head: that segment starts in this lane), summed across lanes;
+    // element 0 takes the carry from earlier lanes of its segment
+    float s1[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) s1[v] = same01 ? a[0][v] + a[1][v] : a[1][v];
+    segmented_scan16(s1, !(same01 && cont0));
+    float carry[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) carry[v] = dpp_f<kDppWaveShr1>(s1[v]);
+    // records into LDS, grouped by bucket (local offset + rank)
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       if (emit[e]) {
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
+          const float v0 = e == 0 ? (cont0 ? carry[2 * b] + a[0][2 * b] : a[0][2 * b]) : s1[2 * b];
+          const float v1 = e == 0 ? (cont0 ? carry[2 * b + 1] + a[0][2 * b + 1] : a[0][2 * b + 1]) : s1[2 * b + 1];
           const uint32_t at = hist[rh[e][b] >> bucket_log2] + rank[e][b];
           st_h[at] = rh[e][b];
-          st_v[at] = make_float2(r0[e][b], r1[e][b]);
+          st_v[at] = make_float2(v0, v1);
         }
       }
     }
+    if (per == 1 && b0 < nb) gdelta[b0] = gbase_own - hist[b0];
     __syncthreads();
     // 7. consecutive records of a bucket go to consecutive global slots
     for (uint32_t i = threadIdx.x; i < n_rec; i += kScatThreads) {
