@@ -178,7 +178,8 @@ int nx_render_forward(nx_ctx *ctx, const nx_surfels *surfels, const nx_camera *c
  * unmodified.
  * Discrete choices (stop, top-K, hash cell) are those the forward took.
  * Atomic accumulation makes results deterministic up to float32 summation
- * order. */
+ * order. With a hash grid and K > 0 the call takes at most about 4e8 samples
+ * (total pixels x K); beyond that it returns NX_ERR_UNSUPPORTED. */
 int nx_render_backward(nx_ctx *ctx, const nx_surfels *surfels, const nx_camera *cams, int32_t n_cams,
                        const nx_hashgrid *grid, const nx_mlp *mlp, const nx_fwd_out *saved,
                        const void *workspace, size_t workspace_bytes, const float *grad_image,

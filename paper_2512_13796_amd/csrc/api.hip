@@ -95,17 +95,21 @@ Layout make_layout(int64_t n, const nx::CamDev& cd, int K, int64_t n_inst) {
   return L;
 }
 
-// The hash-grid scatter's record arena is shared by the cameras of a call
-// (every level is reduced once for all of them); it sits at the start of the
-// workspace, before the per-camera sections.
+// The hash-grid scatter's record arena and slab table are shared by the
+// cameras of a call (every level is reduced once for all of them); they sit
+// at the start of the workspace, before the per-camera sections.
 struct SharedLayout {
-  size_t rec_key, rec_val, bucket_count, total;
+  size_t rec_key, rec_val, slab_table, total;
   int64_t capacity;  // records
+  int64_t rows;      // slab-table rows (bin workgroups over all cameras)
 };
 
 SharedLayout make_shared_layout(const nx_camera* cams, int32_t n_cams, int K) {
   SharedLayout S{};
-  for (int32_t c = 0; c < n_cams && K > 0; ++c) S.capacity += nx::scatter_record_capacity(cams[c].width, cams[c].height, K);
+  for (int32_t c = 0; c < n_cams && K > 0; ++c) {
+    S.capacity += nx::scatter_record_capacity(cams[c].width, cams[c].height, K);
+    S.rows += nx::scatter_slabs(cams[c].width, cams[c].height, K, 1).wgs;
+  }
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
@@ -114,7 +118,7 @@ SharedLayout make_shared_layout(const nx_camera* cams, int32_t n_cams, int K) {
   };
   S.rec_key = take(sizeof(uint16_t) * (size_t)S.capacity);
   S.rec_val = take(sizeof(float2) * (size_t)S.capacity);
-  S.bucket_count = take(sizeof(uint32_t) * (K > 0 ? nx::kScatMaxBuckets : 0));
+  S.slab_table = take(sizeof(uint2) * (size_t)S.rows * nx::kScatMaxBuckets);
   S.total = o;
   return S;
 }
@@ -615,6 +619,8 @@ int nx_render_backward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* 
   if (!grad_image) return fail(NX_ERR_INVALID, "grad_image is NULL");
   if (!grads) return fail(NX_ERR_INVALID, "grads is NULL");
   const SharedLayout SH = make_shared_layout(cams, n_cams, ctx->K);
+  if (SH.capacity >= (1ll << 32))
+    return fail(NX_ERR_UNSUPPORTED, "too many samples (pixels x K) in one call for the hash-grid backward (limit about 4e8)");
   size_t total = SH.total;
   for (int32_t c = 0; c < n_cams; ++c) {
     if (saved->n_instances[c] < 0) return fail(NX_ERR_INVALID, "saved n_instances is negative");
@@ -644,28 +650,28 @@ int nx_render_backward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* 
   if (K > 0 && grads->table) {
     uint16_t* rk = at<uint16_t>(ws, SH.rec_key);
     float2* rv = at<float2>(ws, SH.rec_val);
-    uint32_t* cnt = at<uint32_t>(ws, SH.bucket_count);
+    uint2* tab = at<uint2>(ws, SH.slab_table);
     const nx::GridDev gd0 = make_grid(cams[0], grid);
-    {
-      PhaseTimer pt(ctx, "scatter_init", s);
-      NX_CHECK_HIP(nx::launch_hash_scatter_init(gd0, SH.capacity, cnt, s));
-    }
+    const int nb = nx::scatter_buckets(gd0.log2_size);
     for (int l = 0; l < gd0.levels; ++l) {
       size_t coff = SH.total;
-      int64_t cpix = 0;
+      int64_t cpix = 0, row0 = 0, slab0 = 0;
       for (int32_t c = 0; c < n_cams; ++c) {
         const nx::CamDev cd = make_cam(cams[c]);
         const Layout L = make_layout(surfels->n, cd, ctx->K, saved->n_instances[c]);
         const nx::GridDev gd = make_grid(cams[c], grid);
         PhaseTimer pt(ctx, "scatter_bin", s);
         NX_CHECK_HIP(nx::launch_hash_scatter_bin(ctx->K, gd, l, saved->depths + K * cpix,
-                                                 at<float2>(ws, coff + L.feat_grad), grads->table, SH.capacity, rk,
-                                                 rv, cnt, s));
+                                                 at<float2>(ws, coff + L.feat_grad), grads->table,
+                                                 (uint32_t)slab0, row0, SH.rows, tab, rk, rv, s));
+        const nx::ScatterSlabs sb = nx::scatter_slabs(cams[c].width, cams[c].height, ctx->K, nb);
+        row0 += sb.wgs;
+        slab0 += sb.wgs * nb * sb.slab;
         coff += L.total;
         cpix += (int64_t)cams[c].width * cams[c].height;
       }
       PhaseTimer pt(ctx, "scatter_reduce", s);
-      NX_CHECK_HIP(nx::launch_hash_scatter_reduce(gd0, l, grads->table, SH.capacity, rk, rv, cnt, s));
+      NX_CHECK_HIP(nx::launch_hash_scatter_reduce(gd0, l, grads->table, SH.rows, tab, rk, rv, s));
     }
   }
   g_last_error.clear();

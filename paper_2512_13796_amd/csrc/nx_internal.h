@@ -130,17 +130,22 @@ constexpr size_t kWeightOperandBytes = 192 * 1024;
 // corner contributions are filed as records under buckets (fixed ranges of
 // table entries), then one workgroup per bucket sums its records and updates
 // that range of g_table (no floating-point global atomics).
-// init clears the bucket cursors once per backward; bin and reduce run once
-// per level, in that order.
-// The record arena (rec_key, rec_val: `capacity` records) and the bucket
-// cursors are shared by all cameras of a call; init once, then per level one
-// bin per camera (appending) and one reduce.
-hipError_t launch_hash_scatter_init(const GridDev& grid, int64_t capacity, uint32_t* bucket_count, hipStream_t s);
+// bin runs once per camera and level, then reduce once per level.
+// Records are filed in slabs: the bin launch for a camera runs `wgs`
+// persistent workgroups, and workgroup w keeps the records of bucket b in
+// its own slab of `slab` records at arena offset slab0 + (w nb + b) slab; it
+// ends by writing (slab start, records in it) to row row0 + w of the bucket's
+// slab-table column (slab_table[b * n_rows + row]). A slab that fills up
+// sends further records straight to the table with atomics (correct,
+// slower). The arena (rec_key, rec_val) and the slab table are shared by all
+// cameras of a call: camera c takes the next wgs rows and the next
+// wgs * nb * slab records.
 hipError_t launch_hash_scatter_bin(int K, const GridDev& grid, int level, const float* depths,
-                                   const float2* feat_grad, float* g_table, int64_t capacity, uint16_t* rec_key,
-                                   float2* rec_val, uint32_t* bucket_count, hipStream_t s);
-hipError_t launch_hash_scatter_reduce(const GridDev& grid, int level, float* g_table, int64_t capacity,
-                                      const uint16_t* rec_key, const float2* rec_val, uint32_t* bucket_count,
+                                   const float2* feat_grad, float* g_table, uint32_t slab0, int64_t row0,
+                                   int64_t n_rows, uint2* slab_table, uint16_t* rec_key, float2* rec_val,
+                                   hipStream_t s);
+hipError_t launch_hash_scatter_reduce(const GridDev& grid, int level, float* g_table, int64_t n_rows,
+                                      const uint2* slab_table, const uint16_t* rec_key, const float2* rec_val,
                                       hipStream_t s);
 
 // Screen blocks of the hash scatter: bw x bh patches of 4x4 pixels with
@@ -162,19 +167,35 @@ inline ScatterGeom scatter_geom(int width, int height, int K) {
   g.nby = (npy + g.bh - 1) / g.bh;
   return g;
 }
-// Records one level can file: the worst case (every corner of every sample a
-// record) is n_blocks * 4096; buckets get an equal share of 5/4 of that plus
-// slack, and a bucket that fills up sends further records straight to the
-// table with atomics (correct, slower; hashing spreads the records evenly).
-inline int64_t scatter_record_capacity(int width, int height, int K) {
-  const ScatterGeom g = scatter_geom(width, height, K);
-  return (int64_t)g.nbx * g.nby * 4096 * 5 / 4 + (int64_t)kScatMaxBuckets * 256;
-}
 // Table entries per bucket (log2): 2^(log2_size - 8) clamped to [1, 2^13], so
 // a level has 256 buckets up to 2^21 entries and at most 2048 at 2^24.
 inline int scatter_bucket_log2(int log2_size) {
   const int b = log2_size - 8;
   return b < 0 ? 0 : (b > 13 ? 13 : b);
+}
+inline int scatter_buckets(int log2_size) { return 1 << (log2_size - scatter_bucket_log2(log2_size)); }
+// Slabs of one camera's bin launch: workgroups and records per (workgroup,
+// bucket) slab, sized for 5/4 of the worst case (every corner of every
+// sample a record) spread evenly over the buckets.
+constexpr int kScatWorkgroups = 1024;
+constexpr int kBlockRecords = 4096;  // at most 8 corner records per sample
+struct ScatterSlabs {
+  int64_t wgs, slab;
+};
+inline ScatterSlabs scatter_slabs(int width, int height, int K, int nb) {
+  ScatterSlabs r{0, 0};
+  const ScatterGeom g = scatter_geom(width, height, K);
+  const int64_t nblk = (int64_t)g.nbx * g.nby;
+  if (K <= 0 || nblk <= 0) return r;
+  r.wgs = nblk < kScatWorkgroups ? nblk : kScatWorkgroups;
+  const int64_t per_wg = (nblk + r.wgs - 1) / r.wgs;
+  r.slab = (per_wg * kBlockRecords * 5 / 4 + nb - 1) / nb;
+  return r;
+}
+// Arena records one camera needs under any bucket count up to kScatMaxBuckets.
+inline int64_t scatter_record_capacity(int width, int height, int K) {
+  const ScatterSlabs r = scatter_slabs(width, height, K, 1);
+  return r.wgs * (r.slab + kScatMaxBuckets);
 }
 
 // The per-level feature gradients are stored for 4x4 pixel patches (row-major

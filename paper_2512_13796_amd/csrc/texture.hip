@@ -981,7 +981,7 @@ __device__ __forceinline__ bool lds_add_pair(unsigned long long* p, float a, flo
 constexpr uint32_t kInactiveKey = 0x1FFFFFFu;  // above every 24-bit hash
 constexpr int kBlockSamples = kScatUnits * 16;  // 512 samples per task
 static_assert(kBlockSamples == 2 * kScatThreads, "two samples per thread");
-constexpr int kBlockRecords = 8 * kBlockSamples;  // at most 8 corner records per sample
+static_assert(kBlockRecords == 8 * kBlockSamples, "8 corner records per sample");
 constexpr int kScatStageBytes = kBlockRecords * (sizeof(uint32_t) + sizeof(float2));
 static_assert(kScatStageBytes >= sizeof(float) * 20 * kBlockSamples, "sample stage must fit the record stage");
 static_assert(kScatMaxBuckets % kScatThreads == 0, "bucket counts split evenly over the threads");
@@ -1097,25 +1097,26 @@ __device__ __forceinline__ void segmented_scan16(float (&v)[16], bool head) {
 __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
     GridDev gd, GridLevel L, int K, int log2K, int level, const float* __restrict__ depths,
     const float2* __restrict__ feat_grad, float* __restrict__ g_table, int bw, int bh, int nbx, int nby,
-    int bucket_log2, uint32_t cap, uint32_t* __restrict__ bucket_count, uint16_t* __restrict__ rec_key,
-    float2* __restrict__ rec_val) {
+    int bucket_log2, uint32_t slab0, uint32_t slab, int64_t row0, int64_t n_rows, uint2* __restrict__ slab_table,
+    uint16_t* __restrict__ rec_key, float2* __restrict__ rec_val) {
   // LDS: the per-sample stage (corner values, cells, sort keys) and, once
   // those are in registers, the block's records grouped by bucket share one
-  // region; per-bucket counters follow it (dynamic size: 2 nb words).
+  // region; per-bucket counters follow it (dynamic size: 3 nb words).
   extern __shared__ __attribute__((aligned(16))) unsigned char scat_lds[];
   auto& svals = *reinterpret_cast<float(*)[16][kBlockSamples]>(scat_lds);  // [corner * 2 + feature][sample]
   auto& scell = *reinterpret_cast<int(*)[kBlockSamples][3]>(scat_lds + sizeof(float) * 16 * kBlockSamples);
   uint32_t* skey = reinterpret_cast<uint32_t*>(scat_lds + sizeof(float) * 19 * kBlockSamples);
   uint32_t* st_h = reinterpret_cast<uint32_t*>(scat_lds);                          // record: entry index
   float2* st_v = reinterpret_cast<float2*>(scat_lds + sizeof(uint32_t) * kBlockRecords);  // record: 2 values
-  uint32_t* hist = reinterpret_cast<uint32_t*>(scat_lds + kScatStageBytes);  // count, then local cursor
-  uint32_t* gdelta = hist + (1 << (gd.log2_size - bucket_log2));             // global minus local position
+  const int nb = 1 << (gd.log2_size - bucket_log2);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(scat_lds + kScatStageBytes);  // count, then local offset
+  uint32_t* gdelta = hist + nb;  // slab slot minus local position
+  uint32_t* wcur = gdelta + nb;  // records this workgroup has filed per bucket
   __shared__ uint32_t wsum[kScatThreads / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, c = lane & 15;
   const int row = threadIdx.x >> 4;
   const uint32_t mask = (1u << gd.log2_size) - 1u;
   const uint32_t emask = (1u << bucket_log2) - 1u;
-  const int nb = 1 << (gd.log2_size - bucket_log2);
   const int npx = (gd.width + 3) >> 2, npy = (gd.height + 3) >> 2;
   const int64_t n_q = (int64_t)npx * npy;
   const int64_t nqK = n_q * K;
@@ -1127,6 +1128,8 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
   // walks neighbouring blocks.
   const int G = gridDim.x;
   const int wg = (G % 8 == 0) ? (int)(blockIdx.x % 8) * (G / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
+  const size_t slab_base = slab0 + (size_t)wg * nb * slab;  // this workgroup's slab of bucket 0
+  for (int i = threadIdx.x; i < nb; i += kScatThreads) wcur[i] = 0u;
   for (int blk = wg; blk < n_blocks; blk += G) {
     for (int i = threadIdx.x; i < nb; i += kScatThreads) hist[i] = 0u;
     const int bx = blk % nbx, by = blk / nbx;
@@ -1209,15 +1212,12 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
       }
     }
     __syncthreads();
-    // 5. local offsets of the buckets (exclusive scan of the counts) and this
-    // block's space in every bucket it touches (one global cursor add each).
-    // With one bucket per thread the cursor's reply is only needed in step 7,
-    // so it arrives while the values are summed and filed.
+    // 5. local offsets of the buckets (exclusive scan of the counts) and the
+    // slots this block takes in the workgroup's slabs
     uint32_t n_rec = 0;
-    const int per = nb > kScatThreads ? nb / kScatThreads : 1;
-    const int b0 = threadIdx.x * per;
-    uint32_t gbase_own = 0;
     {
+      const int per = nb > kScatThreads ? nb / kScatThreads : 1;
+      const int b0 = threadIdx.x * per;
       uint32_t cnt[kScatMaxBuckets / kScatThreads];
       uint32_t run = 0;
 #pragma unroll
@@ -1241,20 +1241,14 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
         total += t;
       }
       uint32_t off = before + incl - run;
-      if (per == 1) {
-        if (b0 < nb) {
-          gbase_own = cnt[0] ? atomicAdd(&bucket_count[b0], cnt[0]) : 0u;
-          hist[b0] = off;  // from here on: the bucket's local offset
-        }
-      } else {
 #pragma unroll
-        for (int i = 0; i < kScatMaxBuckets / kScatThreads; ++i) {
-          if (i < per && b0 + i < nb) {
-            const uint32_t gbase = cnt[i] ? atomicAdd(&bucket_count[b0 + i], cnt[i]) : 0u;
-            gdelta[b0 + i] = gbase - off;
-            hist[b0 + i] = off;
-            off += cnt[i];
-          }
+      for (int i = 0; i < kScatMaxBuckets / kScatThreads; ++i) {
+        if (i < per && b0 + i < nb) {
+          const uint32_t used = wcur[b0 + i];
+          gdelta[b0 + i] = used - off;
+          wcur[b0 + i] = used + cnt[i];
+          hist[b0 + i] = off;  // from here on: the bucket's local offset
+          off += cnt[i];
         }
       }
       n_rec = total;
@@ -1284,7 +1278,6 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
         }
       }
     }
-    if (per == 1 && b0 < nb) gdelta[b0] = gbase_own - hist[b0];
     __syncthreads();
     // 7. consecutive records of a bucket go to consecutive global slots
     for (uint32_t i = threadIdx.x; i < n_rec; i += kScatThreads) {
@@ -1292,49 +1285,61 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
       const float2 v = st_v[i];
       const uint32_t bk = h >> bucket_log2;
       const uint32_t pos = i + gdelta[bk];
-      if (pos < cap) {
-        const size_t at = (size_t)bk * cap + pos;
+      if (pos < slab) {
+        const size_t at = slab_base + (size_t)bk * slab + pos;
         rec_key[at] = (uint16_t)(h & emask);
         rec_val[at] = v;
-      } else {  // bucket full: add straight into the table
+      } else {  // slab full: add straight into the table
         unsafeAtomicAdd(&g_level[2 * (size_t)h], v.x);
         unsafeAtomicAdd(&g_level[2 * (size_t)h + 1], v.y);
       }
     }
     __syncthreads();
   }
+  // 8. the workgroup's slab of every bucket: start and records in it
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb; i += kScatThreads) {
+    const uint32_t n = wcur[i];
+    slab_table[(size_t)i * n_rows + row0 + wg] = make_uint2((uint32_t)(slab_base + (size_t)i * slab), n < slab ? n : slab);
+  }
 }
 
-__global__ __launch_bounds__(kReduceThreads) void scatter_reduce_kernel(int bucket_log2, uint32_t cap,
-                                                                       uint32_t* __restrict__ bucket_count,
+__global__ __launch_bounds__(kReduceThreads) void scatter_reduce_kernel(int bucket_log2, int64_t n_rows,
+                                                                       const uint2* __restrict__ slab_table,
                                                                        const uint16_t* __restrict__ rec_key,
                                                                        const float2* __restrict__ rec_val,
                                                                        float* __restrict__ g_level) {
   __shared__ unsigned long long acc[1 << kReduceMaxLog2];
   const int b = blockIdx.x;
   const int n_e = 1 << bucket_log2;
-  const uint32_t cnt = bucket_count[b];
-  const uint32_t n = cnt < cap ? cnt : cap;
   for (int i = threadIdx.x; i < n_e; i += kReduceThreads) acc[i] = 0ull;
   __syncthreads();
   float2* out = reinterpret_cast<float2*>(g_level) + ((size_t)b << bucket_log2);
-  const uint16_t* rk = rec_key + (size_t)b * cap;
-  const float2* rv = rec_val + (size_t)b * cap;
-  constexpr int kU = 4;  // records in flight per thread
-  for (uint32_t i0 = threadIdx.x; i0 < n; i0 += kU * kReduceThreads) {
-    uint32_t k[kU];
-    float2 v[kU];
+  const uint2* col = slab_table + (size_t)b * n_rows;
+  // 16-lane groups walk the slabs (one row each, 64 rows at a time), four
+  // records in flight per lane
+  const int grp = threadIdx.x >> 4, c = threadIdx.x & 15;
+  constexpr int kGroups = kReduceThreads / 16;
+  constexpr int kU = 4;
+  for (int64_t r = grp; r < n_rows; r += kGroups) {
+    const uint2 sl = col[r];
+    const uint16_t* rk = rec_key + sl.x;
+    const float2* rv = rec_val + sl.x;
+    for (uint32_t i0 = c; i0 < sl.y; i0 += 16 * kU) {
+      uint32_t k[kU];
+      float2 v[kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const uint32_t i = i0 + u * kReduceThreads;
-      k[u] = i < n ? rk[i] : 0u;
-      v[u] = i < n ? rv[i] : make_float2(0.f, 0.f);
-    }
+      for (int u = 0; u < kU; ++u) {
+        const uint32_t i = i0 + 16 * u;
+        k[u] = i < sl.y ? rk[i] : 0u;
+        v[u] = i < sl.y ? rv[i] : make_float2(0.f, 0.f);
+      }
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      if (i0 + u * kReduceThreads < n && !lds_add_pair(&acc[k[u]], v[u].x, v[u].y)) {
-        unsafeAtomicAdd(&out[k[u]].x, v[u].x);
-        unsafeAtomicAdd(&out[k[u]].y, v[u].y);
+      for (int u = 0; u < kU; ++u) {
+        if (i0 + 16 * u < sl.y && !lds_add_pair(&acc[k[u]], v[u].x, v[u].y)) {
+          unsafeAtomicAdd(&out[k[u]].x, v[u].x);
+          unsafeAtomicAdd(&out[k[u]].y, v[u].y);
+        }
       }
     }
   }
@@ -1348,7 +1353,6 @@ __global__ __launch_bounds__(kReduceThreads) void scatter_reduce_kernel(int buck
       out[i] = o;
     }
   }
-  if (threadIdx.x == 0) bucket_count[b] = 0u;
 }
 
 __global__ void copy_plain_kernel(const float* plain, float* image, int64_t n) {
@@ -1495,51 +1499,42 @@ hipError_t launch_texture_backward(int K, int feat_dtype, int mlp_dtype, const G
 
 namespace {
 struct ScatterLaunch {
-  int bl, nb;
-  uint32_t cap;  // records per bucket
+  int bl, nb;  // log2 entries per bucket, buckets
 };
-bool scatter_launch(const GridDev& grid, int64_t capacity, ScatterLaunch* o) {
+bool scatter_launch(const GridDev& grid, ScatterLaunch* o) {
   o->bl = scatter_bucket_log2(grid.log2_size);
-  o->nb = 1 << (grid.log2_size - o->bl);
-  const int64_t cap = capacity / o->nb;
-  o->cap = (uint32_t)(cap < 0xFFFFFFFFll ? cap : 0xFFFFFFFFll);
+  o->nb = scatter_buckets(grid.log2_size);
   return o->bl <= kReduceMaxLog2 && o->nb <= kScatMaxBuckets;
 }
 }  // namespace
 
-hipError_t launch_hash_scatter_init(const GridDev& grid, int64_t capacity, uint32_t* bucket_count, hipStream_t s) {
-  if (grid.levels == 0) return hipSuccess;
-  ScatterLaunch sl;
-  if (!scatter_launch(grid, capacity, &sl)) return hipErrorInvalidValue;
-  return launch_fill_f32(reinterpret_cast<float*>(bucket_count), 0.0f, sl.nb, s);
-}
-
 hipError_t launch_hash_scatter_bin(int K, const GridDev& grid, int level, const float* depths,
-                                   const float2* feat_grad, float* g_table, int64_t capacity, uint16_t* rec_key,
-                                   float2* rec_val, uint32_t* bucket_count, hipStream_t s) {
+                                   const float2* feat_grad, float* g_table, uint32_t slab0, int64_t row0,
+                                   int64_t n_rows, uint2* slab_table, uint16_t* rec_key, float2* rec_val,
+                                   hipStream_t s) {
   if (K == 0 || grid.width == 0 || grid.height == 0 || level < 0 || level >= grid.levels) return hipSuccess;
   ScatterLaunch sl;
-  if (!scatter_launch(grid, capacity, &sl)) return hipErrorInvalidValue;
+  if (!scatter_launch(grid, &sl)) return hipErrorInvalidValue;
   const ScatterGeom sg = scatter_geom(grid.width, grid.height, K);
-  const int n_blocks = sg.nbx * sg.nby;
-  if (n_blocks <= 0) return hipSuccess;
-  int64_t wgs = (int64_t)compute_units() * 4;
-  if (wgs > n_blocks) wgs = n_blocks;
-  const size_t lds = kScatStageBytes + 2 * sizeof(uint32_t) * sl.nb;
-  hipLaunchKernelGGL(scatter_bin_kernel, dim3((unsigned)wgs), dim3(kScatThreads), lds, s, grid, grid.lv[level], K,
-                     ilog2(K), level, depths, feat_grad, g_table, sg.bw, sg.bh, sg.nbx, sg.nby, sl.bl, sl.cap,
-                     bucket_count, rec_key, rec_val);
+  const ScatterSlabs sb = scatter_slabs(grid.width, grid.height, K, sl.nb);
+  if (sb.wgs <= 0) return hipSuccess;
+  if (row0 < 0 || row0 + sb.wgs > n_rows || (int64_t)slab0 + sb.wgs * sl.nb * sb.slab > 0xFFFFFFFFll)
+    return hipErrorInvalidValue;
+  const size_t lds = kScatStageBytes + 3 * sizeof(uint32_t) * sl.nb;
+  hipLaunchKernelGGL(scatter_bin_kernel, dim3((unsigned)sb.wgs), dim3(kScatThreads), lds, s, grid, grid.lv[level], K,
+                     ilog2(K), level, depths, feat_grad, g_table, sg.bw, sg.bh, sg.nbx, sg.nby, sl.bl, slab0,
+                     (uint32_t)sb.slab, row0, n_rows, slab_table, rec_key, rec_val);
   return hipGetLastError();
 }
 
-hipError_t launch_hash_scatter_reduce(const GridDev& grid, int level, float* g_table, int64_t capacity,
-                                      const uint16_t* rec_key, const float2* rec_val, uint32_t* bucket_count,
+hipError_t launch_hash_scatter_reduce(const GridDev& grid, int level, float* g_table, int64_t n_rows,
+                                      const uint2* slab_table, const uint16_t* rec_key, const float2* rec_val,
                                       hipStream_t s) {
-  if (level < 0 || level >= grid.levels) return hipSuccess;
+  if (level < 0 || level >= grid.levels || n_rows <= 0) return hipSuccess;
   ScatterLaunch sl;
-  if (!scatter_launch(grid, capacity, &sl)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(scatter_reduce_kernel, dim3((unsigned)sl.nb), dim3(kReduceThreads), 0, s, sl.bl, sl.cap,
-                     bucket_count, rec_key, rec_val, g_table + 2 * ((size_t)level << grid.log2_size));
+  if (!scatter_launch(grid, &sl)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(scatter_reduce_kernel, dim3((unsigned)sl.nb), dim3(kReduceThreads), 0, s, sl.bl, n_rows,
+                     slab_table, rec_key, rec_val, g_table + 2 * ((size_t)level << grid.log2_size));
   return hipGetLastError();
 }
 
