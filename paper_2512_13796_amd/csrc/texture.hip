@@ -1070,7 +1070,8 @@ __device__ __forceinline__ void bitonic_sort_regs(uint32_t (&key)[2], int p0) {
 // at or before it with head set; lane 0 must have it) to this lane. A step
 // that reaches further back than any lane's segment start adds nothing and
 // is skipped (at fine levels almost every segment is a single lane).
-__device__ __forceinline__ void segmented_scan16(float (&v)[16], bool head) {
+template <int N>
+__device__ __forceinline__ void segmented_scan(float (&v)[N], bool head) {
   const int lane = threadIdx.x & 63;
   const unsigned long long heads = __ballot(head) | 1ull;
   const unsigned long long upto = heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
@@ -1079,7 +1080,7 @@ __device__ __forceinline__ void segmented_scan16(float (&v)[16], bool head) {
 #define NX_SEG_STEP(CTRL, MASK, NEEDED)                          \
   if (__any(NEEDED)) {                                           \
     const uint32_t sh = dpp_u<CTRL, MASK>(h);                    \
-    _Pragma("unroll") for (int q = 0; q < 16; ++q) {             \
+    _Pragma("unroll") for (int q = 0; q < N; ++q) {              \
       const float sv = dpp_f<CTRL, MASK>(v[q]);                  \
       v[q] = h ? v[q] : v[q] + sv;                               \
     }                                                            \
@@ -1260,7 +1261,7 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
     float s1[16];
 #pragma unroll
     for (int v = 0; v < 16; ++v) s1[v] = same01 ? a[0][v] + a[1][v] : a[1][v];
-    segmented_scan16(s1, !(same01 && cont0));
+    segmented_scan<16>(s1, !(same01 && cont0));
     float carry[16];
 #pragma unroll
     for (int v = 0; v < 16; ++v) carry[v] = dpp_f<kDppWaveShr1>(s1[v]);
@@ -1304,7 +1305,32 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
   }
 }
 
-__global__ __launch_bounds__(kReduceThreads) void scatter_reduce_kernel(int bucket_log2, int64_t n_rows,
+// Sorts (key, a, b) across the 64 lanes by key, ascending (keys distinct or
+// not; equal keys end up adjacent).
+__device__ __forceinline__ void wave_sort_by_key(uint32_t& key, float& a, float& b) {
+  const int lane = threadIdx.x & 63;
+#define NX_WS_STAGE(KK, J)                                                          \
+  {                                                                                 \
+    const uint32_t ok = lane_xor<J>(key);                                           \
+    const float oa = __uint_as_float(lane_xor<J>(__float_as_uint(a)));              \
+    const float ob = __uint_as_float(lane_xor<J>(__float_as_uint(b)));              \
+    const bool keep_min = ((lane & J) == 0) == ((lane & KK) == 0);                  \
+    const bool take = keep_min ? ok < key : ok > key;                               \
+    key = take ? ok : key;                                                          \
+    a = take ? oa : a;                                                              \
+    b = take ? ob : b;                                                              \
+  }
+  NX_WS_STAGE(2, 1)
+  NX_WS_STAGE(4, 2) NX_WS_STAGE(4, 1)
+  NX_WS_STAGE(8, 4) NX_WS_STAGE(8, 2) NX_WS_STAGE(8, 1)
+  NX_WS_STAGE(16, 8) NX_WS_STAGE(16, 4) NX_WS_STAGE(16, 2) NX_WS_STAGE(16, 1)
+  NX_WS_STAGE(32, 16) NX_WS_STAGE(32, 8) NX_WS_STAGE(32, 4) NX_WS_STAGE(32, 2) NX_WS_STAGE(32, 1)
+  NX_WS_STAGE(64, 32) NX_WS_STAGE(64, 16) NX_WS_STAGE(64, 8) NX_WS_STAGE(64, 4) NX_WS_STAGE(64, 2)
+  NX_WS_STAGE(64, 1)
+#undef NX_WS_STAGE
+}
+
+__global__ __launch_bounds__(kReduceThreads) void scatter_reduce_kernel(int bucket_log2, int coarse, int64_t n_rows,
                                                                        const uint2* __restrict__ slab_table,
                                                                        const uint16_t* __restrict__ rec_key,
                                                                        const float2* __restrict__ rec_val,
@@ -1316,10 +1342,34 @@ __global__ __launch_bounds__(kReduceThreads) void scatter_reduce_kernel(int buck
   __syncthreads();
   float2* out = reinterpret_cast<float2*>(g_level) + ((size_t)b << bucket_log2);
   const uint2* col = slab_table + (size_t)b * n_rows;
-  // 16-lane groups walk the slabs (one row each, 64 rows at a time), four
-  // records in flight per lane
+  // 16-lane groups walk the slabs (one row each, 64 rows at a time)
   const int grp = threadIdx.x >> 4, c = threadIdx.x & 15;
   constexpr int kGroups = kReduceThreads / 16;
+  if (coarse) {
+    // Coarse level: few entries take many records each, so equal keys meet
+    // in one instruction; each wave first sorts its 64 records by key and
+    // sums runs of equal keys, and only the last record of a run goes to LDS.
+    const int lane = threadIdx.x & 63;
+    for (int64_t r0 = grp - (grp & 3); r0 < n_rows; r0 += kGroups) {  // uniform per wave
+      const int64_t r = r0 + (grp & 3);
+      const uint2 sl = r < n_rows ? col[r] : make_uint2(0u, 0u);
+      for (uint32_t i0 = 0; __any(i0 < sl.y); i0 += 16) {
+        const uint32_t i = i0 + c;
+        const bool ok = i < sl.y;
+        uint32_t key = ok ? (uint32_t)rec_key[sl.x + i] : 0xFFFFFFFFu;
+        float2 v = ok ? rec_val[sl.x + i] : make_float2(0.f, 0.f);
+        wave_sort_by_key(key, v.x, v.y);
+        const uint32_t prev = dpp_u<kDppWaveShr1>(key), next = dpp_u<kDppWaveShl1>(key);
+        float s2[2] = {v.x, v.y};
+        segmented_scan<2>(s2, lane == 0 || prev != key);
+        if (key != 0xFFFFFFFFu && (lane == 63 || next != key) && !lds_add_pair(&acc[key], s2[0], s2[1])) {
+          unsafeAtomicAdd(&out[key].x, s2[0]);
+          unsafeAtomicAdd(&out[key].y, s2[1]);
+        }
+      }
+    }
+  } else {
+  // fine level: four records in flight per lane
   constexpr int kU = 4;
   for (int64_t r = grp; r < n_rows; r += kGroups) {
     const uint2 sl = col[r];
@@ -1342,6 +1392,7 @@ __global__ __launch_bounds__(kReduceThreads) void scatter_reduce_kernel(int buck
         }
       }
     }
+  }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < n_e; i += kReduceThreads) {
@@ -1533,7 +1584,11 @@ hipError_t launch_hash_scatter_reduce(const GridDev& grid, int level, float* g_t
   if (level < 0 || level >= grid.levels || n_rows <= 0) return hipSuccess;
   ScatterLaunch sl;
   if (!scatter_launch(grid, &sl)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(scatter_reduce_kernel, dim3((unsigned)sl.nb), dim3(kReduceThreads), 0, s, sl.bl, n_rows,
+  // a level whose lattice has fewer than 2^16 corners (s_l + 2)^3 spreads its
+  // records over at most that many entries
+  const float corners = (grid.lv[level].scale + 2.0f) * (grid.lv[level].scale + 2.0f) * (grid.lv[level].scale + 2.0f);
+  const int coarse = corners < 65536.0f ? 1 : 0;
+  hipLaunchKernelGGL(scatter_reduce_kernel, dim3((unsigned)sl.nb), dim3(kReduceThreads), 0, s, sl.bl, coarse, n_rows,
                      slab_table, rec_key, rec_val, g_table + 2 * ((size_t)level << grid.log2_size));
   return hipGetLastError();
 }
