@@ -698,7 +698,7 @@ struct UnitTiles {
 // which it keeps in MFMA accumulator registers for the whole launch and adds
 // to global memory once at the end.
 template <int TDT, bool BF, int HID, bool WLDS>
-__global__ __launch_bounds__(kTexThreads, (HID <= 64 && BF) ? 2 : 1) void texture_backward_kernel(
+__global__ __launch_bounds__(kTexThreads, (HID <= 64 || BF) ? 2 : 1) void texture_backward_kernel(
     GridDev gd, const void* __restrict__ table, const void* w1, const void* w2, const void* w3,
     const unsigned char* __restrict__ wop, int in_dim, int K,
     int log2K, int64_t n_samples, const int32_t* __restrict__ ids, const float* __restrict__ depths,
@@ -740,6 +740,11 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 && BF) ? 2 : 1) void textur
   const int64_t stride = (int64_t)gridDim.x * kWaves;
   const int64_t n_rounds = first < n_units ? (n_units - first + stride - 1) / stride : 0;
   for (int64_t round = 0; round < n_rounds; ++round) {
+    if constexpr (!WLDS) {
+      // operand slots come from global memory: keep their loads inside the
+      // loop (hoisted, they would occupy hundreds of registers)
+      asm volatile("" : "+s"(W));
+    }
     const int64_t qj = first + round * stride + wave;
     if (qj < n_units) {
       const SampleInfo si = sample_info(gd, K, (int)(qj >> log2K), (int)(qj & (K - 1)), c, ids, depths, weights);
@@ -1436,7 +1441,7 @@ hipError_t bwd_inst(const GridDev& gd, const void* table, const MlpDev& mlp, int
                     const int32_t* ids, const float* depths, const float* weights, const float* grad_image,
                     const float* grad_tex, float2* feat_grad, float* g0, float* g1, float* g2, float* grad_depth,
                     unsigned char* wop, hipStream_t s) {
-  constexpr bool kWlds = HID <= 64;
+  constexpr bool kWlds = HID <= 64 && BF;
   const int64_t n_q = n_patches(gd) * K;
   int64_t grid = (n_q + kWaves - 1) / kWaves;
   if (grid > 1024) grid = 1024;
