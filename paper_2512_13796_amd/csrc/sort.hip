@@ -207,25 +207,50 @@ __global__ void fill_f32_kernel(float* out, float value, int64_t n) {
   if (i < n) out[i] = value;
 }
 
+// One wave per 64 consecutive surfels (in depth order): their instances
+// form one contiguous range, which the wave writes with consecutive lanes on
+// consecutive instances (coalesced, and long tile lists are shared by all
+// lanes). Instance o of surfel j is tile (x0 + t mod w, y0 + t div w) with
+// t = o - offsets[j], row-major over its rectangle.
 __global__ __launch_bounds__(256) void duplicate_kernel(const uint32_t* __restrict__ order,
                                                         const uint32_t* __restrict__ offsets,
                                                         const int4* __restrict__ rects, int64_t n, int ntx,
                                                         uint32_t* __restrict__ tile_keys,
                                                         uint32_t* __restrict__ ids) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t begin = offsets[i], end = offsets[i + 1];
-  if (begin == end) return;
-  const uint32_t s = order[i];
-  const int4 r = rects[s];
-  const int w = r.z - r.x + 1;
-  uint32_t o = begin;
-  for (int ty = r.y; ty <= r.w; ++ty)
-    for (int tx = r.x; tx < r.x + w; ++tx) {
-      tile_keys[o] = (uint32_t)(ty * ntx + tx);
-      ids[o] = s;
-      ++o;
-    }
+  __shared__ uint32_t soff[4][65];
+  __shared__ uint32_t sid[4][64];
+  __shared__ int4 srect[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t i0 = ((int64_t)blockIdx.x * 4 + wave) * 64;
+  if (i0 >= n) return;  // whole wave
+  const int64_t i = i0 + lane;
+  const bool valid = i < n;
+  const uint32_t s = valid ? order[i] : 0u;
+  soff[wave][lane] = offsets[valid ? i : n];
+  if (lane == 0) soff[wave][64] = offsets[i0 + 64 < n ? i0 + 64 : n];
+  sid[wave][lane] = s;
+  srect[wave][lane] = valid ? rects[s] : make_int4(0, 0, -1, -1);
+  // this wave's LDS rows are written and read by this wave only, and a
+  // wave's LDS operations complete in issue order: only the compiler must
+  // not move the reads above the writes
+  __builtin_amdgcn_wave_barrier();
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_wave_barrier();
+  const uint32_t base = soff[wave][0], total = soff[wave][64] - base;
+  for (uint32_t k = lane; k < total; k += 64) {
+    const uint32_t o = base + k;
+    // last surfel j whose range starts at or before o (non-empty: o < its end)
+    int j = 0;
+#pragma unroll
+    for (int step = 32; step >= 1; step >>= 1)
+      if (soff[wave][j + step] <= o) j += step;
+    const int4 r = srect[wave][j];
+    const uint32_t w = (uint32_t)(r.z - r.x + 1);
+    const uint32_t t = o - soff[wave][j];
+    const uint32_t ty = t / w, tx = t - ty * w;
+    tile_keys[o] = (uint32_t)(((int)ty + r.y) * ntx + (int)tx + r.x);
+    ids[o] = sid[wave][j];
+  }
 }
 
 __global__ __launch_bounds__(256) void tile_ranges_kernel(const uint32_t* __restrict__ keys, int64_t n,
