@@ -513,7 +513,7 @@ __device__ __forceinline__ void gather_lane(const GridDev& gd, const void* table
 }
 
 template <int TDT, bool BF, int HID>
-__global__ __launch_bounds__(kTexThreads) void texture_forward_kernel(GridDev gd, const void* __restrict__ table,
+__global__ __launch_bounds__(kTexThreads, (HID <= 64 && BF && TDT != NX_F32) ? 3 : 1) void texture_forward_kernel(GridDev gd, const void* __restrict__ table,
                                                                       const void* w1, const void* w2, const void* w3,
                                                                       int in_dim, int K, int log2K, int64_t n_samples,
                                                                       const int32_t* __restrict__ ids,
@@ -549,6 +549,9 @@ __global__ __launch_bounds__(kTexThreads) void texture_forward_kernel(GridDev gd
       for (int i = 0; i < 4; ++i) {
         z[2 * i] = fraw[2 * i] * delta[i];
         z[2 * i + 1] = fraw[2 * i + 1] * delta[i];
+        // the features are complete here: keep the table entries from
+        // living on into the MLP
+        asm volatile("" : "+v"(z[2 * i]), "+v"(z[2 * i + 1]));
       }
       f4 h1[MT], h2[MT];
       const f4 o = mlp_forward<BF, HID>(lds, lane, z, h1, h2);
