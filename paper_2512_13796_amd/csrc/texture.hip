@@ -314,16 +314,14 @@ struct SampleInfo {
   float dx, dy, dz;  // world ray direction
 };
 
-// Sample (pixel c of 4x4 patch q, slot j). Patches tile the image row-major;
-// lanes of a 16-lane row see the same slot of 16 neighbouring pixels, so at
+// Sample (pixel c of the 4x4 patch at patch column qx, row qy; slot j).
+// Lanes of a 16-lane row see the same slot of 16 neighbouring pixels, so at
 // coarse levels they usually share a hash-grid cell. This part needs only the
 // sample's depth: has = valid, W = 0.
-__device__ __forceinline__ SampleInfo sample_ray(const GridDev& gd, int K, int q, int j, int c,
-                                                 const float* depths) {
+__device__ __forceinline__ SampleInfo sample_ray_xy(const GridDev& gd, int K, int qx, int qy, int j, int c,
+                                                    const float* depths) {
   SampleInfo si;
-  const int npx = (gd.width + 3) >> 2;
-  const int qy = q / npx;
-  const int px = 4 * (q - qy * npx) + (c & 3);
+  const int px = 4 * qx + (c & 3);
   const int py = 4 * qy + (c >> 2);
   si.valid = px < gd.width && py < gd.height;
   si.p = si.valid ? (int64_t)py * gd.width + px : 0;
@@ -337,6 +335,14 @@ __device__ __forceinline__ SampleInfo sample_ray(const GridDev& gd, int K, int q
   si.dy = gd.rot[3] * cx + gd.rot[4] * cy + gd.rot[5];
   si.dz = gd.rot[6] * cx + gd.rot[7] * cy + gd.rot[8];
   return si;
+}
+
+// The same for patch q (patches tile the image row-major).
+__device__ __forceinline__ SampleInfo sample_ray(const GridDev& gd, int K, int q, int j, int c,
+                                                 const float* depths) {
+  const int npx = (gd.width + 3) >> 2;
+  const int qy = q / npx;
+  return sample_ray_xy(gd, K, q - qy * npx, qy, j, c, depths);
 }
 
 __device__ __forceinline__ SampleInfo sample_info(const GridDev& gd, int K, int q, int j, int c,
@@ -991,7 +997,7 @@ constexpr int kBlockSamples = kScatUnits * 16;  // 512 samples per task
 static_assert(kBlockSamples == 2 * kScatThreads, "two samples per thread");
 static_assert(kBlockRecords == 8 * kBlockSamples, "8 corner records per sample");
 constexpr int kScatStageBytes = kBlockRecords * (sizeof(uint32_t) + sizeof(float2));
-static_assert(kScatStageBytes >= sizeof(float) * 20 * kBlockSamples, "sample stage must fit the record stage");
+static_assert(kScatStageBytes >= sizeof(float) * 9 * kBlockSamples, "sample stage must fit the record stage");
 static_assert(kScatMaxBuckets % kScatThreads == 0, "bucket counts split evenly over the threads");
 
 // Cross-lane moves without the LDS permute path where the pattern allows:
@@ -1112,9 +1118,10 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
   // those are in registers, the block's records grouped by bucket share one
   // region; per-bucket counters follow it (dynamic size: 3 nb words).
   extern __shared__ __attribute__((aligned(16))) unsigned char scat_lds[];
-  auto& svals = *reinterpret_cast<float(*)[16][kBlockSamples]>(scat_lds);  // [corner * 2 + feature][sample]
-  auto& scell = *reinterpret_cast<int(*)[kBlockSamples][3]>(scat_lds + sizeof(float) * 16 * kBlockSamples);
-  uint32_t* skey = reinterpret_cast<uint32_t*>(scat_lds + sizeof(float) * 19 * kBlockSamples);
+  // [e.x, e.y, fx, fy, fz][sample]: feature gradient and position in the cell
+  auto& sfeat = *reinterpret_cast<float(*)[5][kBlockSamples]>(scat_lds);
+  auto& scell = *reinterpret_cast<int(*)[kBlockSamples][3]>(scat_lds + sizeof(float) * 5 * kBlockSamples);
+  uint32_t* skey = reinterpret_cast<uint32_t*>(scat_lds + sizeof(float) * 8 * kBlockSamples);
   uint32_t* st_h = reinterpret_cast<uint32_t*>(scat_lds);                          // record: entry index
   float2* st_v = reinterpret_cast<float2*>(scat_lds + sizeof(uint32_t) * kBlockRecords);  // record: 2 values
   const int nb = 1 << (gd.log2_size - bucket_log2);
@@ -1142,7 +1149,7 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
   for (int blk = wg; blk < n_blocks; blk += G) {
     for (int i = threadIdx.x; i < nb; i += kScatThreads) hist[i] = 0u;
     const int bx = blk % nbx, by = blk / nbx;
-    // 1. per sample: cell, sort key and the 16 corner contributions
+    // 1. per sample: cell, position in it, feature gradient and sort key
 #pragma unroll
     for (int it = 0; it < kUnitsPerRow; ++it) {
       const int u = row + it * (kScatThreads / 16);
@@ -1150,18 +1157,16 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
       const int pb = u >> log2K, j = u & (K - 1);
       const int qx = bx * bw + (pb & (bw - 1)), qy = by * bh + (pb >> log2bw);
       const bool in = qx < npx && qy < npy;
-      const int q = in ? qy * npx + qx : 0;
-      const SampleInfo si = sample_ray(gd, K, q, j, c, depths);
+      const SampleInfo si = sample_ray_xy(gd, K, in ? qx : 0, in ? qy : 0, j, c, depths);
       float2 e = make_float2(0.f, 0.f);
-      if (in && si.valid) e = feat_grad[((int64_t)level * nqK + (int64_t)q * K + j) * 16 + c];
+      if (in && si.valid) e = feat_grad[((int64_t)level * nqK + ((int64_t)qy * npx + qx) * K + j) * 16 + c];
       const bool act = in && si.valid && (e.x != 0.f || e.y != 0.f);
       const LevelGeom lg = level_geom(L, si);
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const float w = act ? corner_weight(lg, b) : 0.f;
-        svals[2 * b][smp] = w * e.x;
-        svals[2 * b + 1][smp] = w * e.y;
-      }
+      sfeat[0][smp] = act ? e.x : 0.f;
+      sfeat[1][smp] = act ? e.y : 0.f;
+      sfeat[2][smp] = lg.frx;
+      sfeat[3][smp] = lg.fry;
+      sfeat[4][smp] = lg.frz;
       scell[smp][0] = lg.cx;
       scell[smp][1] = lg.cy;
       scell[smp][2] = lg.cz;
@@ -1189,8 +1194,18 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
       cx[e] = scell[sm][0];
       cy[e] = scell[sm][1];
       cz[e] = scell[sm][2];
+      // the 16 corner contributions: trilinear weight x feature gradient
+      LevelGeom fr;
+      fr.frx = sfeat[2][sm];
+      fr.fry = sfeat[3][sm];
+      fr.frz = sfeat[4][sm];
+      const float ex = sfeat[0][sm], ey = sfeat[1][sm];
 #pragma unroll
-      for (int v = 0; v < 16; ++v) a[e][v] = svals[v][sm];
+      for (int b = 0; b < 8; ++b) {
+        const float w = corner_weight(fr, b);
+        a[e][2 * b] = w * ex;
+        a[e][2 * b + 1] = w * ey;
+      }
     }
     // element 1 continues element 0's segment?
     const bool same01 = live[0] == live[1] && cx[0] == cx[1] && cy[0] == cy[1] && cz[0] == cz[1];
