@@ -142,3 +142,64 @@ def test_joint_call_against_oracle(nx, setup):
     log("multi-view grads (relL2, frac over bound):", {k: (f"{a:.2e}", f"{b:.1e}") for k, (a, b) in report.items()})
     for k, (rel, viol) in report.items():
         assert rel <= 1e-3 and viol <= 5e-3, f"{k}: rel {rel:.2e} viol {viol:.2e}"
+
+
+def test_full_size_all_cameras_against_oracle(nx):
+    """The multi-view workload at full size, as bench.py times it (300k surfels, all 16 cameras in one call,
+    FP32 grid and MLP): forward within 1e-5 and gradients within the FP32 parity bars on a pixel sample of
+    every camera."""
+    wl = scenes.make_workload(4)
+    cams = wl.cameras
+    surf, table, weights = device_inputs(wl)
+    ctx = nx.Context(wl.K, table.dtype, weights[0].dtype)
+    res = nx.render_forward(ctx, surf, cams, table, wl.grid.level_scales, weights, want_cells=True)
+    torch.cuda.synchronize()
+    off = _offsets(cams)
+    K = wl.K
+    gpu = to_np(res, K)
+    grid = scenes.HashGrid(table.cpu(), wl.grid.level_scales)
+    mlp = scenes.MLP([w.cpu() for w in weights])
+    rng = np.random.default_rng(17)
+    gi = np.zeros((res.image.shape[0], 3))
+    per_cam = []
+    n_nd = 0
+    for i, cam in enumerate(cams):
+        pix = _sample_pixels(cam, 40 + i, per_block=96, full_tiles=0)
+        glob = pix + off[i]
+        cells = res.cells[torch.from_numpy(glob).cuda()].cpu().numpy()
+        masks = res.relu_masks[torch.from_numpy(glob).cuda()].cpu().numpy().view(np.uint32)
+        orc = oracle.render(wl.scene, cam, grid, mlp, K, pixels=pix, force_cells=cells, force_relu=masks)
+        sub = {k: v[off[i]:off[i + 1]] for k, v in gpu.items()}
+        # the fraction of pixels within FP32 error of a decision is checked over all cameras below
+        compare_forward(sub, orc, pix, K, max_nondecisive=1.0, label=f"full-size cam {i}")
+        dec = orc.margin > SAFETY
+        n_nd += int((~dec).sum())
+        gi[glob[dec]] = rng.standard_normal((int(dec.sum()), 3))
+        per_cam.append((cam, pix, cells, masks))
+    n_pix = sum(p[1].shape[0] for p in per_cam)
+    log(f"full-size multi-view: {n_pix} sampled pixels over {len(cams)} cameras, {n_nd} within FP32 error of a decision")
+    assert n_nd <= 1e-2 * n_pix, f"non-decisive pixels {n_nd} of {n_pix}"
+    grads = _zero_grads(surf, table, weights)
+    nx.render_backward(ctx, surf, res, table, wl.grid.level_scales, weights,
+                       torch.from_numpy(gi).float().cuda(), None, None, grads)
+    torch.cuda.synchronize()
+    total = None
+    for i, (cam, pix, cells, masks) in enumerate(per_cam):
+        og = oracle.render_and_grad(wl.scene, cam, grid, mlp, K, pixels=pix, grad_image=gi[pix + off[i]],
+                                    force_cells=cells, force_relu=masks).grads
+        if total is None:
+            total = {k: (v if k != "mlp" else list(v)) for k, v in og.items()}
+        else:
+            for k, v in og.items():
+                total[k] = [a + b for a, b in zip(total[k], v)] if k == "mlp" else total[k] + v
+    report = {}
+    for nm in ("means", "quats", "scales", "opacities", "gammas", "colors", "table"):
+        rel, viol, _ = grad_errors(grads[nm].cpu().numpy(), total[nm])
+        report[nm] = (rel, viol)
+    for i in range(3):
+        rel, viol, _ = grad_errors(grads["mlp"][i].cpu().numpy(), total["mlp"][i])
+        report[f"mlp{i}"] = (rel, viol)
+    log("full-size multi-view grads (relL2, frac over bound):",
+        {k: (f"{a:.2e}", f"{b:.1e}") for k, (a, b) in report.items()})
+    for k, (rel, viol) in report.items():
+        assert rel <= 1e-3 and viol <= 5e-3, f"{k}: rel {rel:.2e} viol {viol:.2e}"

@@ -312,6 +312,18 @@ def test_outdoor_bf16_form_gradients_sampled(nx):
         assert rep[nm][0] <= 1e-3, f"{nm}: {rep[nm][0]:.2e}"
 
 
+def test_large_hidden128_bf16_gradients_sampled(nx):
+    """The large workload at full size, as bench.py times it: 1M surfels, 2560x1440, K = 8, BF16 grid and
+    hidden-128 BF16 MLP. Forward and gradients against the FP64 oracle on a pixel sample, with the BF16 bars
+    of the 1080p test; surfel gradients go through no BF16 rounding and stay near FP32 accuracy."""
+    wl = scenes.make_workload(5)
+    pix = _sample_pixels(wl.cameras[0], 13, per_block=96, full_tiles=1)
+    log(f"c5 sampled pixels: {pix.shape[0]}")
+    rep = _grad_case(nx, wl, label="c5 bf16", pixels=pix, rel_tol=5e-2, viol_tol=1.0, tol_fwd=1e-3, max_nd=1e-2)
+    for nm in ("means", "quats", "scales", "opacities", "gammas", "colors"):
+        assert rep[nm][0] <= 1e-3, f"{nm}: {rep[nm][0]:.2e}"
+
+
 def test_outdoor_bf16_form_psnr(nx):
     """FP16 grid + BF16 MLP: image PSNR against the FP64 oracle >= 45 dB."""
     wl = scenes.make_workload(3)
