@@ -94,6 +94,12 @@ __device__ __forceinline__ f4 mfma_f32_k4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// 1/x from the hardware reciprocal (within 1 ulp): the texture path's
+// divisions (ray setup, Delta_l and its derivative, the sigmoid head) feed
+// FP32 arithmetic whose own rounding is of the same order, and every kernel
+// that recomputes a quantity uses this same form.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // Orders this wave's LDS writes before its later LDS reads by other lanes of
 // the same wave. A wave's LDS operations are performed in issue order, so no
 // hardware wait is needed: this only stops the compiler from moving memory
@@ -329,8 +335,8 @@ __device__ __forceinline__ SampleInfo sample_ray_xy(const GridDev& gd, int K, in
   si.has = si.valid;
   si.D = si.valid ? depths[si.s] : 1.0f;
   si.W = 0.0f;
-  const float cx = ((float)px + 0.5f - gd.cx) / gd.fx;
-  const float cy = ((float)py + 0.5f - gd.cy) / gd.fy;
+  const float cx = ((float)px + 0.5f - gd.cx) * rcp(gd.fx);
+  const float cy = ((float)py + 0.5f - gd.cy) * rcp(gd.fy);
   si.dx = gd.rot[0] * cx + gd.rot[1] * cy + gd.rot[2];
   si.dy = gd.rot[3] * cx + gd.rot[4] * cy + gd.rot[5];
   si.dz = gd.rot[6] * cx + gd.rot[7] * cy + gd.rot[8];
@@ -386,7 +392,7 @@ __device__ __forceinline__ LevelGeom level_geom(const GridLevel& L, const Sample
   g.hy[1] = map_positive(cy + 1) * kPrime1;
   g.hz[0] = map_positive(cz) * kPrime2;
   g.hz[1] = map_positive(cz + 1) * kPrime2;
-  const float y = L.kappa / (si.D * si.D);
+  const float y = L.kappa * rcp(si.D * si.D);
   g.delta = -expm1f(-y);
   g.expo = 1.0f - g.delta;
   return g;
@@ -500,7 +506,7 @@ __device__ __forceinline__ void gather_lane(const GridDev& gd, const void* table
           az1 = fmaf(cz, z1.y - z0.y, az1);
         }
       const float ds = lg[i].delta * L.scale;
-      const float ddelta = -lg[i].expo * 2.0f * L.kappa / (si.D * si.D * si.D);
+      const float ddelta = -lg[i].expo * 2.0f * L.kappa * rcp(si.D * si.D * si.D);
       const float c0 = ds * (ax0 * si.dx + ay0 * si.dy + az0 * si.dz) + ddelta * f0;
       const float c1 = ds * (ax1 * si.dx + ay1 * si.dy + az1 * si.dz) + ddelta * f1;
       dcoef[2 * i] = E.act[i] ? c0 : 0.f;
@@ -597,7 +603,7 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 && BF && TDT != NX_F32) ? 3
       if (g == 0 && si.valid) {
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
-          const float t = si.has ? 1.0f / (1.0f + __expf(-o[r])) : 0.0f;
+          const float t = si.has ? rcp(1.0f + __expf(-o[r])) : 0.0f;
           tex[si.s * 3 + r] = t;
           contrib[r] = fmaf(si.W, t, contrib[r]);
         }
@@ -776,7 +782,7 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 || BF) ? 2 : 1) void textur
         const float gi[3] = {g0, g1, g2};
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
-          const float t = 1.0f / (1.0f + __expf(-o[r]));
+          const float t = rcp(1.0f + __expf(-o[r]));
           float dt = si.W * gi[r];
           if (grad_tex) dt += grad_tex[si.s * 3 + r];
           dlog[r] = dt * t * (1.0f - t);
