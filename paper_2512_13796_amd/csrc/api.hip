@@ -305,7 +305,6 @@ int forward_one(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera& cam, co
   const nx::CamDev cd = make_cam(cam);
   const int n_tiles = cd.ntx * cd.nty;
   const int64_t n = surfels->n;
-  const int64_t P = (int64_t)cd.width * cd.height;
   const Layout L0 = make_layout(n, cd, K, 0);
   *need = L0.total;
   if (!workspace || workspace_bytes < L0.total) return fail(NX_ERR_WORKSPACE, "workspace too small");
@@ -391,9 +390,7 @@ int backward_one(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera& cam, c
                  hipStream_t s) {
   const int K = ctx->K;
   const nx::CamDev cd = make_cam(cam);
-  const int n_tiles = cd.ntx * cd.nty;
   const int64_t n = surfels->n;
-  const int64_t P = (int64_t)cd.width * cd.height;
   const Layout L = make_layout(n, cd, K, n_inst);
   void* ws = workspace;
   float* rec_grad = at<float>(ws, L.rec_grad);

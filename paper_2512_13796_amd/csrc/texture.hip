@@ -45,7 +45,6 @@ typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 constexpr int kTexThreads = 256;
 constexpr int kWaves = kTexThreads / 64;
 constexpr int kInPad = 32;
-constexpr float kInv2Pi = 0.15915494309189533577f;
 
 typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
 typedef float f2v __attribute__((ext_vector_type(2)));
@@ -99,16 +98,6 @@ __device__ __forceinline__ f4 mfma_f32_k4(float a, float b, f4 c) {
 // FP32 arithmetic whose own rounding is of the same order, and every kernel
 // that recomputes a quantity uses this same form.
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-
-// Orders this wave's LDS writes before its later LDS reads by other lanes of
-// the same wave. A wave's LDS operations are performed in issue order, so no
-// hardware wait is needed: this only stops the compiler from moving memory
-// accesses across.
-__device__ __forceinline__ void wave_sync_lds() {
-  __builtin_amdgcn_wave_barrier();
-  asm volatile("" ::: "memory");
-  __builtin_amdgcn_wave_barrier();
-}
 
 template <bool BF>
 __device__ __forceinline__ float load_w(const void* w, int idx) {
@@ -654,40 +643,6 @@ __device__ __forceinline__ void weight_grad_accum(const unsigned char* Y, const 
       }
     }
   }
-}
-
-// Sum of v[0..15] over the 16 lanes of a row (c = lane % 16) with 15
-// exchanges; lane c ends with the row total of value 8 b3 + 4 b2 + 2 b1 + b0
-// (b = bits of c).
-__device__ __forceinline__ float row_transpose_sum16(const float v[16], int c, int* which) {
-  float a8[8];
-  const bool h8 = c & 8;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const float send = h8 ? v[i] : v[i + 8];
-    const float keep = h8 ? v[i + 8] : v[i];
-    a8[i] = keep + __shfl_xor(send, 8, 64);
-  }
-  float a4[4];
-  const bool h4 = c & 4;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const float send = h4 ? a8[i] : a8[i + 4];
-    const float keep = h4 ? a8[i + 4] : a8[i];
-    a4[i] = keep + __shfl_xor(send, 4, 64);
-  }
-  float a2[2];
-  const bool h2 = c & 2;
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const float send = h2 ? a4[i] : a4[i + 2];
-    const float keep = h2 ? a4[i + 2] : a4[i];
-    a2[i] = keep + __shfl_xor(send, 2, 64);
-  }
-  const bool h1 = c & 1;
-  const float x = (h1 ? a2[1] : a2[0]) + __shfl_xor(h1 ? a2[0] : a2[1], 1, 64);
-  *which = (h8 ? 8 : 0) + (h4 ? 4 : 0) + (h2 ? 2 : 0) + (h1 ? 1 : 0);
-  return x;
 }
 
 // Per-unit activation tiles for the workgroup-cooperative weight gradients:
@@ -1512,18 +1467,6 @@ hipError_t bwd_by_table(int tdt, const GridDev& gd, const void* table, const Mlp
                                         wop, s);
     default: return hipErrorInvalidValue;
   }
-}
-
-int compute_units() {
-  static int cached[64] = {0};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-  if (cached[dev] == 0) {
-    int n = 0;
-    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
-    cached[dev] = n;
-  }
-  return cached[dev];
 }
 
 }  // namespace
