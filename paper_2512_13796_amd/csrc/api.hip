@@ -25,6 +25,12 @@ struct nx_ctx {
   nx_dtype feat_dtype, mlp_dtype;
   uint32_t* pinned;  // one host word for the instance-count readback
   bool timing;
+  // The backward's second stream (default priority) on which each level's
+  // hash-scatter reduction overlaps the next level's binning, and the events
+  // that order the two; created at the first backward, on the device current
+  // then (a context serves one device).
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_bin[2] = {}, ev_red[2] = {};
   std::vector<nx_phase> phases;
   std::vector<nx_pending> pending;
   std::vector<hipEvent_t> pool;
@@ -95,12 +101,13 @@ Layout make_layout(int64_t n, const nx::CamDev& cd, int K, int64_t n_inst) {
   return L;
 }
 
-// The hash-grid scatter's record arena and slab table are shared by the
+// The hash-grid scatter's record arenas and slab tables are shared by the
 // cameras of a call (every level is reduced once for all of them); they sit
 // at the start of the workspace, before the per-camera sections.
 struct SharedLayout {
-  size_t rec_key, rec_val, slab_table, total;
-  int64_t capacity;  // records
+  // two arenas: level l files into arena l % 2 while level l - 1 is reduced
+  size_t rec_key[2], rec_val[2], slab_table[2], total;
+  int64_t capacity;  // records per arena
   int64_t rows;      // slab-table rows (bin workgroups over all cameras)
 };
 
@@ -116,9 +123,11 @@ SharedLayout make_shared_layout(const nx_camera* cams, int32_t n_cams, int K) {
     o = align_up(o + bytes);
     return at;
   };
-  S.rec_key = take(sizeof(uint16_t) * (size_t)S.capacity);
-  S.rec_val = take(sizeof(float2) * (size_t)S.capacity);
-  S.slab_table = take(sizeof(uint2) * (size_t)S.rows * nx::kScatMaxBuckets);
+  for (int a = 0; a < 2; ++a) {
+    S.rec_key[a] = take(sizeof(uint16_t) * (size_t)S.capacity);
+    S.rec_val[a] = take(sizeof(float2) * (size_t)S.capacity);
+    S.slab_table[a] = take(sizeof(uint2) * (size_t)S.rows * nx::kScatMaxBuckets);
+  }
   S.total = o;
   return S;
 }
@@ -266,6 +275,23 @@ struct PhaseTimer {
     if (b && hipEventRecord(b, s) == hipSuccess) c->pending.push_back({phase, a, b});
   }
 };
+
+// The backward's side stream and its events, created once per context.
+int side_stream(nx_ctx* c) {
+  if (c->side) return NX_OK;
+  hipStream_t st = nullptr;
+  NX_CHECK_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  hipEvent_t* evs[6] = {&c->ev_fork, &c->ev_join, &c->ev_bin[0], &c->ev_bin[1], &c->ev_red[0], &c->ev_red[1]};
+  for (hipEvent_t* e : evs) {
+    const hipError_t err = hipEventCreateWithFlags(e, hipEventDisableTiming);
+    if (err != hipSuccess) {
+      (void)hipStreamDestroy(st);
+      return fail(NX_ERR_HIP, std::string("hipEventCreateWithFlags: ") + hipGetErrorString(err));
+    }
+  }
+  c->side = st;
+  return NX_OK;
+}
 
 template <typename T>
 T* at(void* base, size_t off) {
@@ -473,6 +499,9 @@ int nx_destroy(nx_ctx* ctx) {
     (void)hipEventDestroy(p.b);
   }
   for (auto e : ctx->pool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : {ctx->ev_fork, ctx->ev_join, ctx->ev_bin[0], ctx->ev_bin[1], ctx->ev_red[0], ctx->ev_red[1]})
+    if (e) (void)hipEventDestroy(e);
+  if (ctx->side) (void)hipStreamDestroy(ctx->side);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;
   return NX_OK;
@@ -645,12 +674,21 @@ int nx_render_backward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* 
   // 2. hash-grid gradient, level by level: every camera files its records,
   //    then one reduction per level for all of them
   if (K > 0 && grads->table) {
-    uint16_t* rk = at<uint16_t>(ws, SH.rec_key);
-    float2* rv = at<float2>(ws, SH.rec_val);
-    uint2* tab = at<uint2>(ws, SH.slab_table);
+    if ((r = side_stream(ctx)) != NX_OK) return r;
     const nx::GridDev gd0 = make_grid(cams[0], grid);
     const int nb = nx::scatter_buckets(gd0.log2_size);
+    // Level l: bin on the call's stream into arena l % 2, reduce on the side
+    // stream; the bin of level l + 2 waits for the reduce of level l (same
+    // arena), the reduce of level l for its own bin; the call's stream waits
+    // for the last reduce at the end.
+    NX_CHECK_HIP(hipEventRecord(ctx->ev_fork, s));
+    NX_CHECK_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
     for (int l = 0; l < gd0.levels; ++l) {
+      const int a = l & 1;
+      uint16_t* rk = at<uint16_t>(ws, SH.rec_key[a]);
+      float2* rv = at<float2>(ws, SH.rec_val[a]);
+      uint2* tab = at<uint2>(ws, SH.slab_table[a]);
+      if (l >= 2) NX_CHECK_HIP(hipStreamWaitEvent(s, ctx->ev_red[a], 0));
       size_t coff = SH.total;
       int64_t cpix = 0, row0 = 0, slab0 = 0;
       for (int32_t c = 0; c < n_cams; ++c) {
@@ -667,9 +705,16 @@ int nx_render_backward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* 
         coff += L.total;
         cpix += (int64_t)cams[c].width * cams[c].height;
       }
-      PhaseTimer pt(ctx, "scatter_reduce", s);
-      NX_CHECK_HIP(nx::launch_hash_scatter_reduce(gd0, l, grads->table, SH.rows, tab, rk, rv, s));
+      NX_CHECK_HIP(hipEventRecord(ctx->ev_bin[a], s));
+      NX_CHECK_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_bin[a], 0));
+      {
+        PhaseTimer pt(ctx, "scatter_reduce", ctx->side);
+        NX_CHECK_HIP(nx::launch_hash_scatter_reduce(gd0, l, grads->table, SH.rows, tab, rk, rv, ctx->side));
+      }
+      NX_CHECK_HIP(hipEventRecord(ctx->ev_red[a], ctx->side));
     }
+    NX_CHECK_HIP(hipEventRecord(ctx->ev_join, ctx->side));
+    NX_CHECK_HIP(hipStreamWaitEvent(s, ctx->ev_join, 0));
   }
   g_last_error.clear();
   return NX_OK;
