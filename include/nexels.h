@@ -153,9 +153,11 @@ int nx_create(nx_ctx **out, int32_t K, int32_t tile, nx_dtype feat_dtype, nx_dty
 int nx_destroy(nx_ctx *ctx);
 
 /* Workspace bytes for n_surfels surfels seen by n_cams cameras with at most
- * max_instances (surfel, tile) pairs per camera. The workspace holds one
- * section per camera, one after another; it carries the forward's sorted
- * tile lists and per-surfel records to the backward. */
+ * max_instances (surfel, tile) pairs per camera. The workspace starts with
+ * the backward's hash-scatter scratch shared by the cameras (two record
+ * arenas of about 10 records per sample, and their slab tables), then holds
+ * one section per camera, one after another; the sections carry the
+ * forward's sorted tile lists and per-surfel records to the backward. */
 int nx_workspace_size(nx_ctx *ctx, int64_t n_surfels, const nx_camera *cams, int32_t n_cams,
                       int64_t max_instances, size_t *bytes);
 
@@ -174,7 +176,11 @@ int nx_render_forward(nx_ctx *ctx, const nx_surfels *surfels, const nx_camera *c
 /* Gradients of L through both passes given dL/dimage [P,3] (device) and the
  * optional dL/dweights [P,K] and dL/dtex [P,K,3] (device, NULL = zero), all
  * cameras concatenated as in the forward; the cameras' gradients add up in
- * grads. saved and workspace must be those of the matching forward call,
+ * grads. The call orders all its work after what stream already holds and
+ * before what is queued on it later; part of the hash-grid gradient runs on
+ * a second stream the context creates at its first backward (default
+ * priority; the context then serves the device current at that time).
+ * saved and workspace must be those of the matching forward call,
  * unmodified.
  * Discrete choices (stop, top-K, hash cell) are those the forward took.
  * Atomic accumulation makes results deterministic up to float32 summation
