@@ -25,12 +25,15 @@ struct nx_ctx {
   nx_dtype feat_dtype, mlp_dtype;
   uint32_t* pinned;  // one host word for the instance-count readback
   bool timing;
-  // The backward's second stream (default priority) on which each level's
-  // hash-scatter reduction overlaps the next level's binning, and the events
-  // that order the two; created at the first backward, on the device current
-  // then (a context serves one device).
-  hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_bin[2] = {}, ev_red[2] = {};
+  // The backward's extra streams (default priority) and the events that
+  // order them with the call's stream: `side` runs each level's hash-scatter
+  // reduction while the next level is binned, `side2` the collection-pass
+  // and preprocess backward while the hash-grid gradient is formed. Created
+  // at the first backward, on the device current then (a context serves one
+  // device).
+  hipStream_t side = nullptr, side2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_bin[2] = {}, ev_red[2] = {}, ev_tex = nullptr,
+             ev_join2 = nullptr;
   std::vector<nx_phase> phases;
   std::vector<nx_pending> pending;
   std::vector<hipEvent_t> pool;
@@ -276,20 +279,29 @@ struct PhaseTimer {
   }
 };
 
-// The backward's side stream and its events, created once per context.
-int side_stream(nx_ctx* c) {
+// The backward's extra streams and their events, created once per context.
+int side_streams(nx_ctx* c) {
   if (c->side) return NX_OK;
-  hipStream_t st = nullptr;
-  NX_CHECK_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-  hipEvent_t* evs[6] = {&c->ev_fork, &c->ev_join, &c->ev_bin[0], &c->ev_bin[1], &c->ev_red[0], &c->ev_red[1]};
+  hipStream_t st[2] = {nullptr, nullptr};
+  for (hipStream_t& x : st) {
+    const hipError_t err = hipStreamCreateWithFlags(&x, hipStreamNonBlocking);
+    if (err != hipSuccess) {
+      if (st[0]) (void)hipStreamDestroy(st[0]);
+      return fail(NX_ERR_HIP, std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(err));
+    }
+  }
+  hipEvent_t* evs[8] = {&c->ev_fork, &c->ev_join, &c->ev_bin[0], &c->ev_bin[1],
+                        &c->ev_red[0], &c->ev_red[1], &c->ev_tex, &c->ev_join2};
   for (hipEvent_t* e : evs) {
     const hipError_t err = hipEventCreateWithFlags(e, hipEventDisableTiming);
     if (err != hipSuccess) {
-      (void)hipStreamDestroy(st);
+      (void)hipStreamDestroy(st[0]);
+      (void)hipStreamDestroy(st[1]);
       return fail(NX_ERR_HIP, std::string("hipEventCreateWithFlags: ") + hipGetErrorString(err));
     }
   }
-  c->side = st;
+  c->side = st[0];
+  c->side2 = st[1];
   return NX_OK;
 }
 
@@ -409,11 +421,13 @@ int forward_one(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera& cam, co
 }
 
 // One camera of nx_render_backward: saved, grad_* point at this camera's
-// slices, workspace at its section (laid out for n_inst instances).
+// slices, workspace at its section (laid out for n_inst instances). Part 0:
+// zero the record gradients, texture backward; part 1 (after part 0 of every
+// camera): collection-pass and preprocess backward.
 int backward_one(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera& cam, const nx_hashgrid* grid,
                  const nx_mlp* mlp, const nx_fwd_out* saved, int64_t n_inst, void* workspace,
                  const float* grad_image, const float* grad_weights, const float* grad_tex, const nx_grads* grads,
-                 hipStream_t s) {
+                 hipStream_t s, int part) {
   const int K = ctx->K;
   const nx::CamDev cd = make_cam(cam);
   const int64_t n = surfels->n;
@@ -421,6 +435,20 @@ int backward_one(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera& cam, c
   void* ws = workspace;
   float* rec_grad = at<float>(ws, L.rec_grad);
   float* gdepth = at<float>(ws, L.grad_depth);
+  if (part == 1) {
+    {
+      PhaseTimer pt(ctx, "raster_backward", s);
+      NX_CHECK_HIP(nx::launch_raster_backward(K, at<float4>(ws, L.records), at<uint32_t>(ws, L.inst_ids),
+                                              at<uint2>(ws, L.tile_ranges), cd, saved->plain, saved->ids,
+                                              saved->weights, saved->tex, saved->n_iter, grad_image, grad_weights,
+                                              K > 0 ? gdepth : nullptr, rec_grad, s));
+    }
+    PhaseTimer pt(ctx, "preprocess_backward", s);
+    NX_CHECK_HIP(nx::launch_preprocess_backward(surfels->means, surfels->quats, surfels->scales, n, cd,
+                                                at<uint32_t>(ws, L.tile_counts), rec_grad, grads->means, grads->quats,
+                                                grads->scales, grads->opacities, grads->gammas, grads->colors, s));
+    return NX_OK;
+  }
   {
     PhaseTimer pt(ctx, "zero_record_grads", s);
     NX_CHECK_HIP(nx::launch_fill_f32(rec_grad, 0.0f, (int64_t)nx::kRecGrad * n, s));
@@ -441,19 +469,6 @@ int backward_one(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera& cam, c
                                                grads->mlp[0], grads->mlp[1], grads->mlp[2], gdepth,
                                                at<unsigned char>(ws, L.weight_ops), s));
     }
-  }
-  {
-  PhaseTimer pt(ctx, "raster_backward", s);
-  NX_CHECK_HIP(nx::launch_raster_backward(K, at<float4>(ws, L.records), at<uint32_t>(ws, L.inst_ids),
-                                          at<uint2>(ws, L.tile_ranges), cd, saved->plain, saved->ids, saved->weights,
-                                          saved->tex, saved->n_iter, grad_image, grad_weights,
-                                          K > 0 ? gdepth : nullptr, rec_grad, s));
-  }
-  {
-  PhaseTimer pt(ctx, "preprocess_backward", s);
-  NX_CHECK_HIP(nx::launch_preprocess_backward(surfels->means, surfels->quats, surfels->scales, n, cd,
-                                              at<uint32_t>(ws, L.tile_counts), rec_grad, grads->means, grads->quats,
-                                              grads->scales, grads->opacities, grads->gammas, grads->colors, s));
   }
   return NX_OK;
 }
@@ -499,9 +514,11 @@ int nx_destroy(nx_ctx* ctx) {
     (void)hipEventDestroy(p.b);
   }
   for (auto e : ctx->pool) (void)hipEventDestroy(e);
-  for (hipEvent_t e : {ctx->ev_fork, ctx->ev_join, ctx->ev_bin[0], ctx->ev_bin[1], ctx->ev_red[0], ctx->ev_red[1]})
+  for (hipEvent_t e : {ctx->ev_fork, ctx->ev_join, ctx->ev_bin[0], ctx->ev_bin[1], ctx->ev_red[0], ctx->ev_red[1],
+                       ctx->ev_tex, ctx->ev_join2})
     if (e) (void)hipEventDestroy(e);
   if (ctx->side) (void)hipStreamDestroy(ctx->side);
+  if (ctx->side2) (void)hipStreamDestroy(ctx->side2);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;
   return NX_OK;
@@ -659,22 +676,33 @@ int nx_render_backward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* 
   const int64_t K = ctx->K > 0 ? ctx->K : 0;
   // 1. per camera: texture backward (writes its per-level feature
   //    gradients), collection-pass backward, preprocess backward
-  size_t off = SH.total;
-  int64_t pix = 0;
-  for (int32_t c = 0; c < n_cams; ++c) {
-    const nx_fwd_out sc = camera_slice(ctx, grid, mlp, *saved, pix);
-    const int64_t n_inst = saved->n_instances[c];
-    r = backward_one(ctx, surfels, cams[c], grid, mlp, &sc, n_inst, at<char>(ws, off), grad_image + 3 * pix,
-                     grad_weights ? grad_weights + K * pix : nullptr, grad_tex ? grad_tex + 3 * K * pix : nullptr,
-                     grads, s);
-    if (r != NX_OK) return r;
-    off += make_layout(surfels->n, make_cam(cams[c]), ctx->K, n_inst).total;
-    pix += (int64_t)cams[c].width * cams[c].height;
+  if ((r = side_streams(ctx)) != NX_OK) return r;
+  // texture backward of every camera on the call's stream; then the
+  // collection-pass and preprocess backward of every camera on side2, which
+  // overlap the hash-grid gradient below (they would only take CUs from the
+  // next camera's texture backward if they started earlier)
+  for (int part = 0; part < 2; ++part) {
+    hipStream_t sp = part == 0 ? s : ctx->side2;
+    if (part == 1) {
+      NX_CHECK_HIP(hipEventRecord(ctx->ev_tex, s));
+      NX_CHECK_HIP(hipStreamWaitEvent(ctx->side2, ctx->ev_tex, 0));
+    }
+    size_t off = SH.total;
+    int64_t pix = 0;
+    for (int32_t c = 0; c < n_cams; ++c) {
+      const nx_fwd_out sc = camera_slice(ctx, grid, mlp, *saved, pix);
+      const int64_t n_inst = saved->n_instances[c];
+      r = backward_one(ctx, surfels, cams[c], grid, mlp, &sc, n_inst, at<char>(ws, off), grad_image + 3 * pix,
+                       grad_weights ? grad_weights + K * pix : nullptr, grad_tex ? grad_tex + 3 * K * pix : nullptr,
+                       grads, sp, part);
+      if (r != NX_OK) return r;
+      off += make_layout(surfels->n, make_cam(cams[c]), ctx->K, n_inst).total;
+      pix += (int64_t)cams[c].width * cams[c].height;
+    }
   }
   // 2. hash-grid gradient, level by level: every camera files its records,
   //    then one reduction per level for all of them
   if (K > 0 && grads->table) {
-    if ((r = side_stream(ctx)) != NX_OK) return r;
     const nx::GridDev gd0 = make_grid(cams[0], grid);
     const int nb = nx::scatter_buckets(gd0.log2_size);
     // Level l: bin on the call's stream into arena l % 2, reduce on the side
@@ -716,6 +744,8 @@ int nx_render_backward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* 
     NX_CHECK_HIP(hipEventRecord(ctx->ev_join, ctx->side));
     NX_CHECK_HIP(hipStreamWaitEvent(s, ctx->ev_join, 0));
   }
+  NX_CHECK_HIP(hipEventRecord(ctx->ev_join2, ctx->side2));
+  NX_CHECK_HIP(hipStreamWaitEvent(s, ctx->ev_join2, 0));
   g_last_error.clear();
   return NX_OK;
 }
