@@ -177,9 +177,10 @@ int nx_render_forward(nx_ctx *ctx, const nx_surfels *surfels, const nx_camera *c
  * optional dL/dweights [P,K] and dL/dtex [P,K,3] (device, NULL = zero), all
  * cameras concatenated as in the forward; the cameras' gradients add up in
  * grads. The call orders all its work after what stream already holds and
- * before what is queued on it later; part of the hash-grid gradient runs on
- * a second stream the context creates at its first backward (default
- * priority; the context then serves the device current at that time).
+ * before what is queued on it later; part of it (the hash-grid gradient's
+ * reductions, the collection-pass and preprocess backward) runs on two more
+ * streams the context creates at its first backward (default priority; the
+ * context then serves the device current at that time).
  * saved and workspace must be those of the matching forward call,
  * unmodified.
  * Discrete choices (stop, top-K, hash cell) are those the forward took.
