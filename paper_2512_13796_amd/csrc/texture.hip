@@ -616,6 +616,24 @@ __device__ __forceinline__ void put_rows(unsigned char* buf, int row, int c, flo
   }
 }
 
+// Rows row0 .. row0 + 3 of column c from a register tile (rows 4 g + r):
+// two values per conversion for BF16.
+template <bool BF>
+__device__ __forceinline__ void put_rows4(unsigned char* buf, int row0, int c, f4 v) {
+  if constexpr (BF) {
+    const uint32_t w01 = pack_bf16x2(v[0], v[1]), w23 = pack_bf16x2(v[2], v[3]);
+    short* p = reinterpret_cast<short*>(buf) + row0 * 16 + c;
+    p[0] = (short)(w01 & 0xFFFFu);
+    p[16] = (short)(w01 >> 16);
+    p[32] = (short)(w23 & 0xFFFFu);
+    p[48] = (short)(w23 >> 16);
+  } else {
+    float* p = reinterpret_cast<float*>(buf) + row0 * 16 + c;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) p[16 * r] = v[r];
+  }
+}
+
 // dW[out][in] += sum over 16 samples of Y[out][s] X[in][s] for output row
 // tiles mo < NMO and column tiles mi < NMI: acc[mo * NMI + mi] += the
 // 16-sample contribution (samples are the K index of the product), reading
@@ -747,12 +765,9 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 || BF) ? 2 : 1) void textur
       // factors go to this wave's tiles as soon as they exist, so the
       // activations die early (h2 after layer 3, dH2 and h1 after layer 2).
       f4 dzt[2];
+      put_rows4<BF>(T, UT::oY3 + 4 * g, c, dlog);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) put_rows<BF>(T, UT::oY3 + 4 * g + r, c, dlog[r]);
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) put_rows<BF>(T, UT::oX3 + 16 * mt + 4 * g + r, c, h2[mt][r]);
+      for (int mt = 0; mt < MT; ++mt) put_rows4<BF>(T, UT::oX3 + 16 * mt + 4 * g, c, h2[mt]);
       f4 dh2[MT];
       if constexpr (BF) {
         s8 bd;
@@ -777,12 +792,10 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 || BF) ? 2 : 1) void textur
         }
       }
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          put_rows<BF>(T, UT::oY2 + 16 * mt + 4 * g + r, c, dh2[mt][r]);
-          put_rows<BF>(T, UT::oX2 + 16 * mt + 4 * g + r, c, h1[mt][r]);
-        }
+      for (int mt = 0; mt < MT; ++mt) {
+        put_rows4<BF>(T, UT::oY2 + 16 * mt + 4 * g, c, dh2[mt]);
+        put_rows4<BF>(T, UT::oX2 + 16 * mt + 4 * g, c, h1[mt]);
+      }
       f4 dh1[MT];
       if constexpr (BF) {
         constexpr int HT = LY::HT;
@@ -813,9 +826,7 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 || BF) ? 2 : 1) void textur
         }
       }
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) put_rows<BF>(T, UT::oY1 + 16 * mt + 4 * g + r, c, dh1[mt][r]);
+      for (int mt = 0; mt < MT; ++mt) put_rows4<BF>(T, UT::oY1 + 16 * mt + 4 * g, c, dh1[mt]);
 #pragma unroll
       for (int e = 0; e < 8; ++e) put_rows<BF>(T, UT::oX1 + feat_index(g, e), c, z[e]);
       if constexpr (BF) {
