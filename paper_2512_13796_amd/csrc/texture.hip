@@ -1330,7 +1330,10 @@ __global__ __launch_bounds__(kReduceThreads) void scatter_reduce_kernel(int buck
                                                                        const uint16_t* __restrict__ rec_key,
                                                                        const float2* __restrict__ rec_val,
                                                                        float* __restrict__ g_level) {
-  __shared__ unsigned long long acc[1 << kReduceMaxLog2];
+  // the bucket's entries as (feature 0, feature 1) float pairs; sized to the
+  // bucket at launch, so that binning workgroups of the next level still fit
+  // next to it on the CU
+  extern __shared__ unsigned long long acc[];
   const int b = blockIdx.x;
   const int n_e = 1 << bucket_log2;
   for (int i = threadIdx.x; i < n_e; i += kReduceThreads) acc[i] = 0ull;
@@ -1571,7 +1574,8 @@ hipError_t launch_hash_scatter_reduce(const GridDev& grid, int level, float* g_t
   // records over at most that many entries
   const float corners = (grid.lv[level].scale + 2.0f) * (grid.lv[level].scale + 2.0f) * (grid.lv[level].scale + 2.0f);
   const int coarse = corners < 65536.0f ? 1 : 0;
-  hipLaunchKernelGGL(scatter_reduce_kernel, dim3((unsigned)sl.nb), dim3(kReduceThreads), 0, s, sl.bl, coarse, n_rows,
+  const size_t lds = sizeof(unsigned long long) << sl.bl;
+  hipLaunchKernelGGL(scatter_reduce_kernel, dim3((unsigned)sl.nb), dim3(kReduceThreads), lds, s, sl.bl, coarse, n_rows,
                      slab_table, rec_key, rec_val, g_table + 2 * ((size_t)level << grid.log2_size));
   return hipGetLastError();
 }
