@@ -249,8 +249,10 @@ hipEvent_t take_event(nx_ctx* c) {
     c->pool.pop_back();
     return e;
   }
+  // timing only: no system-scope fence (no cache writeback and invalidate
+  // around the timed launches)
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 
@@ -293,7 +295,8 @@ int side_streams(nx_ctx* c) {
   hipEvent_t* evs[8] = {&c->ev_fork, &c->ev_join, &c->ev_bin[0], &c->ev_bin[1],
                         &c->ev_red[0], &c->ev_red[1], &c->ev_tex, &c->ev_join2};
   for (hipEvent_t* e : evs) {
-    const hipError_t err = hipEventCreateWithFlags(e, hipEventDisableTiming);
+    // ordering between streams of one device: a device-scope release is enough
+    const hipError_t err = hipEventCreateWithFlags(e, hipEventDisableTiming | hipEventReleaseToDevice);
     if (err != hipSuccess) {
       (void)hipStreamDestroy(st[0]);
       (void)hipStreamDestroy(st[1]);
