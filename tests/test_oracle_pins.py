@@ -144,6 +144,185 @@ def test_two_surfels_front_to_back():
     assert np.all(out2.ids[:, 0] == 0) and np.all(out2.ids[:, 1] == 1)
 
 
+def _on_axis_stack(cam, px, py, depths, opac, scale=0.3):
+    """Facing surfels centred on the ray through the centre of pixel (px, py)."""
+    dx = (px + 0.5 - cam.cx) / cam.fx
+    dy = (py + 0.5 - cam.cy) / cam.fy
+    n = len(depths)
+    means = [[z * dx, z * dy, z] for z in depths]
+    cols = [[0.1 * (i + 1), 1.0 - 0.1 * i, 0.5] for i in range(n)]
+    return scene_from(means, [[1, 0, 0, 0]] * n, [[scale, scale]] * n, [opac] * n, [[1, 1]] * n, cols), cols
+
+
+def test_stop_rule_stack_of_opaque_surfels():
+    """Compositing stops before the surfel that would take T below 1e-4
+    (eq. composite with the 3DGS termination; reading 3). Five facing surfels
+    of alpha = 0.95 on one pixel's ray: T after three is 0.05^3 = 1.25e-4,
+    the fourth would give 6.25e-6, so exactly three are composited and
+    C = sum_{i<3} 0.95 * 0.05^i * c_i."""
+    cam = identity_camera(9, 9, 10.0)
+    sc, cols = _on_axis_stack(cam, 4, 4, [2.0, 2.5, 3.0, 3.5, 4.0], 0.95)
+    rng = np.random.default_rng(30)
+    out = oracle.render(sc, cam, random_grid(rng), random_mlp(rng, [4, 8, 8, 3]), K=0)
+    p = 4 * 9 + 4
+    assert out.n_comp[p] == 3
+    t = [1.0, 1.0 - 0.95, (1.0 - 0.95) ** 2, (1.0 - 0.95) ** 3]
+    np.testing.assert_allclose(out.t_final[p], t[3], rtol=1e-13)
+    assert out.t_final[p] > 1e-4 > out.t_final[p] * (1.0 - 0.95)
+    expect = sum(0.95 * t[i] * np.array(cols[i]) for i in range(3))
+    np.testing.assert_allclose(out.image[p], expect, rtol=1e-13)
+    # K = 4 sees the same three: the top-K slots hold them and a fourth slot stays empty
+    out4 = oracle.render(sc, cam, random_grid(rng), random_mlp(rng, [4, 8, 8, 3]), K=4)
+    assert list(out4.ids[p]) == [0, 1, 2, -1]
+    np.testing.assert_allclose(out4.weights[p, :3], [0.95 * t[i] for i in range(3)], rtol=1e-13)
+
+
+def test_alpha_clamp_at_full_opacity():
+    """alpha = min(0.99, o G) (reading 3): an opacity-1 surfel seen through its
+    centre has G = 1, so alpha = 0.99 and T_final = 0.01; away from the centre
+    the kernel is below the clamp and alpha = G."""
+    cam = identity_camera(9, 9, 10.0)
+    sc, cols = _on_axis_stack(cam, 4, 4, [2.0], 1.0, scale=0.2)
+    rng = np.random.default_rng(31)
+    out = oracle.render(sc, cam, random_grid(rng), random_mlp(rng, [4, 8, 8, 3]), K=0)
+    p = 4 * 9 + 4
+    np.testing.assert_allclose(out.t_final[p], 0.01, rtol=1e-13)
+    np.testing.assert_allclose(out.image[p], 0.99 * np.array(cols[0]), rtol=1e-13)
+    # one pixel to the right: u = 2 * 0.1 / 0.2 = 1, G = exp(-1/2) < 0.99
+    np.testing.assert_allclose(out.t_final[p + 1], 1.0 - math.exp(-0.5), rtol=1e-13)
+
+
+def _rodrigues(axis, angle):
+    """Rotation matrix of `angle` about the unit `axis`: cos I + sin [a]x + (1 - cos) a a^T."""
+    a = np.asarray(axis, dtype=np.float64)
+    a = a / np.linalg.norm(a)
+    K_ = np.array([[0.0, -a[2], a[1]], [a[2], 0.0, -a[0]], [-a[1], a[0], 0.0]])
+    return math.cos(angle) * np.eye(3) + math.sin(angle) * K_ + (1.0 - math.cos(angle)) * np.outer(a, a)
+
+
+def _axis_angle_quat(axis, angle):
+    a = np.asarray(axis, dtype=np.float64)
+    a = a / np.linalg.norm(a)
+    return np.concatenate([[math.cos(angle / 2.0)], math.sin(angle / 2.0) * a])
+
+
+def _quat_mul(p, q):
+    """Hamilton product p q of (w, x, y, z) quaternions (rotation by q, then p)."""
+    w1, x1, y1, z1 = p
+    w2, x2, y2, z2 = q
+    return np.array([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                     w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2])
+
+
+def test_quaternion_columns_are_rodrigues_axes():
+    """R = [v1 v2 v3] (Representation, Geometry) is the rotation the quaternion
+    stands for: its columns equal Rodrigues' matrix of the same axis and angle,
+    in both the rendering and the binning code."""
+    from oracle.binning import quat_columns_f64
+    from oracle.geometry import quat_columns
+    rng = np.random.default_rng(32)
+    for _ in range(20):
+        axis = rng.standard_normal(3)
+        angle = rng.uniform(0.2, 3.0)
+        R = _rodrigues(axis, angle)
+        q = _axis_angle_quat(axis, angle)
+        v = quat_columns(torch.from_numpy(q))
+        np.testing.assert_allclose(np.stack([c.numpy() for c in v], axis=1), R, atol=1e-14)
+        vb = quat_columns_f64(q[None])
+        np.testing.assert_allclose(np.stack([c[0] for c in vb], axis=1), R, atol=1e-14)
+
+
+def test_quarter_turn_swaps_the_surfel_axes():
+    """A +90 degree turn about the normal maps v1 to the camera's y axis: with
+    scales (s1, s2) it renders and bins like the unrotated surfel with
+    (s2, s1); on the tilted plane u and v follow the closed form
+    u = ((X - mu) . v1) / s1 with the hit point X of the ray-plane
+    intersection and v1, v2 from Rodrigues' formula."""
+    cam = identity_camera(24, 24, 30.0)
+    mu = [0.02, -0.01, 2.0]
+    qz = _axis_angle_quat([0, 0, 1], math.pi / 2)
+    a = scene_from([mu], [qz], [[0.3, 0.12]], [0.8], [[1, 1]], [[0.2, 0.4, 0.6]])
+    b = scene_from([mu], [[1, 0, 0, 0]], [[0.12, 0.3]], [0.8], [[1, 1]], [[0.2, 0.4, 0.6]])
+    rng = np.random.default_rng(33)
+    grid, mlp = random_grid(rng), random_mlp(rng, [4, 8, 8, 3])
+    oa, ob = oracle.render(a, cam, grid, mlp, K=0), oracle.render(b, cam, grid, mlp, K=0)
+    np.testing.assert_allclose(oa.image, ob.image, atol=1e-14)
+    ba, bb = bin_surfels(a, cam), bin_surfels(b, cam)
+    np.testing.assert_array_equal(ba["rect"], bb["rect"])
+    # tilted about the x axis by 35 degrees, then turned by 70 degrees about the new normal
+    q = _quat_mul(_axis_angle_quat([1, 0, 0], math.radians(35.0)), _axis_angle_quat([0, 0, 1], math.radians(70.0)))
+    R = _rodrigues([1, 0, 0], math.radians(35.0)) @ _rodrigues([0, 0, 1], math.radians(70.0))
+    sig = [0.4, 0.25]
+    c = scene_from([mu], [q], [sig], [0.9], [[1, 1]], [[1.0, 1.0, 1.0]])
+    oc = oracle.render(c, cam, grid, mlp, K=1)
+    py, px = np.meshgrid(np.arange(24), np.arange(24), indexing="ij")
+    d = np.stack([(px + 0.5 - 12) / 30.0, (py + 0.5 - 12) / 30.0, np.ones_like(px, dtype=float)], -1).reshape(-1, 3)
+    t = (np.asarray(mu) @ R[:, 2]) / (d @ R[:, 2])
+    X = t[:, None] * d - np.asarray(mu)[None]
+    u = X @ R[:, 0] / sig[0]
+    v = X @ R[:, 1] / sig[1]
+    alpha = 0.9 * np.exp(-0.5 * (u * u + v * v))
+    inside = (np.abs(u) <= 3) & (np.abs(v) <= 3) & (alpha >= ALPHA_MIN)
+    assert inside.sum() > 100
+    np.testing.assert_allclose(oc.t_final, np.where(inside, 1.0 - alpha, 1.0), atol=1e-13)
+    np.testing.assert_allclose(oc.depths[inside, 0], t[inside], rtol=1e-13)
+
+
+def test_camera_looks_along_its_axis():
+    """Pinhole rays (reading 7): the ray through the principal point of a
+    look-at camera starts at the eye and points at the target, and the target
+    projects to the principal point."""
+    from oracle.binning import to_camera_f64
+    from oracle.geometry import camera_origin_and_rays
+    eye, target = np.array([0.7, -1.2, 2.5]), np.array([-0.3, 0.4, -0.8])
+    cam = scenes.look_at(eye, target, (0.0, -1.0, 0.0), 33, 21)
+    o, d = camera_origin_and_rays(cam, np.array([16]), np.array([10]))
+    np.testing.assert_allclose(o.numpy(), eye, atol=1e-14)
+    dirn = (target - eye) / np.linalg.norm(target - eye)
+    dd = d.numpy()[0]
+    np.testing.assert_allclose(dd / np.linalg.norm(dd), dirn, atol=1e-14)
+    assert abs(dd @ (target - eye) / np.linalg.norm(target - eye) - 1.0) < 1e-14  # unit camera-z component
+    pc = to_camera_f64(np.asarray(cam.world_to_cam), target[None])[0]
+    np.testing.assert_allclose([cam.fx * pc[0] / pc[2] + cam.cx, cam.fy * pc[1] / pc[2] + cam.cy], [16.5, 10.5],
+                               atol=1e-12)
+
+
+def test_rigid_motion_of_scene_and_camera_changes_nothing():
+    """Moving the surfels and the camera by one rigid motion (x -> Q x + b,
+    q -> q_Q q, camera [R | t] -> [R Q^T | t - R Q^T b]) leaves every
+    camera-frame quantity unchanged, so the collection pass (ids, W, D,
+    T_final, N) and the K = 0 image are identical up to rounding."""
+    wl = scenes.make_workload(1, seed=3, width=40, height=32, n_surfels=400)
+    cam = scenes.look_at((0.4, -0.5, -2.8), (0.1, 0.0, 0.2), (0.0, -1.0, 0.0), 40, 32)
+    rng = np.random.default_rng(34)
+    axis, angle, b = rng.standard_normal(3), 1.1, np.array([0.7, -2.0, 1.3])
+    Q = _rodrigues(axis, angle)
+    qQ = _axis_angle_quat(axis, angle)
+    sc = wl.scene
+    mu = sc.means.double().numpy()
+    quats = sc.quats.double().numpy()
+    # unit to double precision: the textbook matrix is a rotation (and composes) only for |q| = 1
+    quats = quats / np.linalg.norm(quats, axis=1, keepdims=True)
+    moved = scenes.Scene(torch.from_numpy(mu @ Q.T + b), torch.from_numpy(np.stack([_quat_mul(qQ, q) for q in quats])),
+                         sc.scales.double(), sc.opacities.double(), sc.gammas.double(), sc.colors.double())
+    m = np.asarray(cam.world_to_cam)
+    Rn = m[:, :3] @ Q.T
+    cam2 = scenes.Camera(np.concatenate([Rn, (m[:, 3] - Rn @ b)[:, None]], axis=1), cam.fx, cam.fy, cam.cx, cam.cy,
+                         cam.width, cam.height)
+    base = scenes.Scene(sc.means.double(), torch.from_numpy(quats), *[t.double() for t in sc.tensors()[2:]])
+    for K in (0, 4):
+        a = oracle.render(base, cam, wl.grid, wl.mlp, K)
+        c = oracle.render(moved, cam2, wl.grid, wl.mlp, K)
+        assert (a.n_comp > 0).mean() > 0.3
+        np.testing.assert_array_equal(a.ids, c.ids)
+        np.testing.assert_array_equal(a.n_comp, c.n_comp)
+        for nm in ("weights", "t_final", "plain"):
+            np.testing.assert_allclose(getattr(a, nm), getattr(c, nm), atol=1e-11)
+        np.testing.assert_allclose(a.depths, c.depths, rtol=1e-11, atol=1e-11)
+        if K == 0:
+            np.testing.assert_allclose(a.image, c.image, atol=1e-11)
+
+
 # ---------------------------------------------------------------- kernel limits
 
 def test_kernel_gamma_one_is_gaussian():
