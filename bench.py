@@ -30,21 +30,26 @@ if ROOT not in sys.path:
 
 METRIC = "Mpix/s fwd+bwd at 400k surfels 1080p K=4 (BF16 vs FP32); % HBM roofline"
 HBM_PEAK_GBS = 8000.0
-BF16_PEAK_TFLOPS = 2500.0
-FP32_PEAK_TFLOPS = 157.3
+MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}  # dense matrix peaks of the MI355X per operand type
+# VALU peak: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz = 39.3e12 lane-instructions/s (packed FP32 is off)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# VALU instructions per (pixel, surfel) pair the collection pass tests: the gamma = 1 path of the inner loop
+# counts 27 from the record reads to the alpha threshold; composited pairs add the K-buffer and colour update.
+RASTER_OPS_PER_PAIR = 30
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic(phase, st):
-    """(HBM bytes, matrix flops) the launches of `phase` in one step must move / compute.
+def method_work(phase, st):
+    """(bound, HBM bytes, matrix flops, VALU lane-ops) the launches of `phase` in one step must move / compute.
 
-    Counts each input read once and each output written once at its storage
-    width; the hash table is counted once per camera (its re-reads are cache
-    traffic); atomically updated buffers count a read and a write. Per-surfel
-    kernels run once per camera (C cameras)."""
+    Bytes count what the method reads and writes: each input once and each output once at its storage width,
+    the hash table once per camera (its re-reads are cache traffic), atomically updated buffers as a read and a
+    write, and the binning and sort arrays the tile rasteriser needs. They do not count this design's own
+    intermediates (the per-level feature gradients and the hash-scatter records); those appear only in the
+    measured traffic. Per-surfel kernels run once per camera (C cameras)."""
     N, C, P, K, I, T = st["N"], st["C"], st["P"], st["K"], st["I"], st["n_tiles"]
     S = P * K
     L = st["L"]
@@ -52,7 +57,8 @@ def algorithmic(phase, st):
     gtable = L * st["T"] * st["F"] * 4
     mlp_flops = 2.0 * S * (st["in"] * st["H"] + st["H"] * st["H"] + 3 * st["H"])
     rec = 80
-    b = {
+    pairs = st["pairs"]
+    hbm = {
         "preprocess": C * N * (60 + 4 + 4 + 16 + rec),
         "depth_sort": C * N * (8 + 4 * 16),
         "instance_scan": C * N * 12,
@@ -60,18 +66,51 @@ def algorithmic(phase, st):
         "tile_sort": I * 16 * st["tile_passes"],
         "tile_ranges": I * 4 + T * 8,
         "raster_forward": I * (4 + rec) + T * 8 + P * (12 + 12 * K + 8),
-        "texture_forward": S * 24 + P * 24 + C * table,
+        "texture_forward": S * 12 + P * 24 + C * table,
         "zero_record_grads": C * N * 64,
-        "texture_backward": S * 16 + P * 12 + C * table + S * L * 8,
-        # per level and camera: that level's feature gradients and the sample
-        # depths in; then that level's slice of the FP32 gradient table read and written
-        "scatter_bin": S * (8 + 4) * L,
-        "scatter_reduce": C * 2 * gtable,
+        "texture_backward": S * 16 + P * 12 + C * table,
+        # the table gradient: each level's slice read and written once
+        "hash_backward": 2 * gtable,
         "raster_backward": I * (4 + rec) + T * 8 + P * (28 + 24 * K) + C * N * 120,
         "preprocess_backward": C * N * (36 + 4 + 64 + 2 * 60),
     }
-    f = {"texture_forward": mlp_flops, "texture_backward": 3.0 * mlp_flops}
-    return float(b.get(phase, 0)), float(f.get(phase, 0.0))
+    flops = {"texture_forward": mlp_flops, "texture_backward": 3.0 * mlp_flops}
+    valu = {"raster_forward": pairs * RASTER_OPS_PER_PAIR, "raster_backward": pairs * RASTER_OPS_PER_PAIR}
+    bound = "mfma" if phase in flops else ("alu" if phase in valu else "hbm")
+    return bound, float(hbm.get(phase, 0)), float(flops.get(phase, 0.0)), float(valu.get(phase, 0.0))
+
+
+# Kernel phases that together form one method step of the table: the hash-grid gradient is one pass of the
+# method (its bytes are the table slice) that this design splits over several launches.
+PHASE_GROUPS = {"hash_backward": ("scatter_bin", "scatter_reduce")}
+
+
+def rooflines(phases, steps, st, form):
+    """Per method phase: bound, achieved vs peak, from the HIP-event time per step of its launches."""
+    per_step = {k: v[0] / steps for k, v in phases.items()}
+    launches = {k: v[1] // steps for k, v in phases.items()}
+    for grp, members in PHASE_GROUPS.items():
+        if any(m in per_step for m in members):
+            per_step[grp] = sum(per_step.pop(m, 0.0) for m in members)
+            launches[grp] = sum(launches.pop(m, 0) for m in members)
+    out = {}
+    for ph, ms in per_step.items():
+        if ms <= 0:
+            continue
+        bound, nbytes, nflops, nvalu = method_work(ph, st)
+        t = ms / 1000.0
+        r = {"ms_per_step": round(ms, 4), "launches_per_step": int(launches[ph]),
+             "hbm_gbs": round(nbytes / t / 1e9, 1), "hbm_frac": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4),
+             "bytes_per_step": nbytes}
+        if nflops:
+            peak = MFMA_PEAK_TFLOPS[form]
+            r.update(mfma_tflops=round(nflops / t / 1e12, 2), mfma_peak=peak,
+                     mfma_frac=round(nflops / t / 1e12 / peak, 4))
+        if nvalu:
+            r.update(valu_tops=round(nvalu / t / 1e12, 2), valu_frac=round(nvalu / t / 1e12 / VALU_PEAK_TOPS, 4))
+        r["bound"] = bound
+        out[ph] = r
+    return out
 
 
 def kernel_source_digest():
@@ -182,7 +221,7 @@ def time_form(form, steps, warmup, workload="outdoor"):
           "I": res.n_instances, "n_tiles": sum(((c.width + 15) // 16) * ((c.height + 15) // 16) for c in cams),
           "L": wl.grid.levels, "T": 1 << wl.grid.log2_size, "F": wl.grid.feat, "tb": table.element_size(),
           "in": weights[0].shape[1], "H": weights[0].shape[0], "tile_passes": 2,
-          "width": cams[0].width, "height": cams[0].height}
+          "width": cams[0].width, "height": cams[0].height, "pairs": int(res.n_iter.to(torch.int64).sum())}
     st["workload_stats"] = workload_stats(res, wl, K=wl.K)
     return {"ms": ms, "wall_ms": 1000.0 * wall / steps, "phases": phases, "stats": st, "workload": wl}
 
@@ -205,8 +244,19 @@ def workload_stats(res, wl, K):
     return out
 
 
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(sample_pixels=4096, seed=0):
-    """The FP64 oracle, as it stands, on a bounded pixel sample of the same workload."""
+    """The FP64 oracle, as it stands, on a bounded pixel sample of the same workload: one forward + backward
+    call (every surfel tested per pixel) with a fixed upstream image gradient of the L2 loss's size."""
     import numpy as np
     import torch
 
@@ -218,16 +268,14 @@ def cpu_baseline(sample_pixels=4096, seed=0):
     P = cam.width * cam.height
     rng = np.random.default_rng(seed)
     pix = np.sort(rng.choice(P, sample_pixels, replace=False))
-    target = wl.target[0].reshape(-1, 3).double().numpy()
+    g = rng.uniform(-1.0, 1.0, (sample_pixels, 3)) * (2.0 / (3.0 * P))
     t0 = time.perf_counter()
-    out = oracle.render(wl.scene, cam, wl.grid, wl.mlp, wl.K, pixels=pix)
-    g = 2.0 * (out.image - target[pix]) / (3.0 * P)
     oracle.render_and_grad(wl.scene, cam, wl.grid, wl.mlp, wl.K, pixels=pix, grad_image=g)
     dt = time.perf_counter() - t0
     return {"value": sample_pixels / dt / 1e6, "unit": "Mpix/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
-            "sample": f"{sample_pixels} random pixels of the 1920x1080 400k-surfel frame, forward (every surfel "
-                      f"tested per pixel) then forward+backward with the L2 gradient: {dt:.1f} s"}
+            "host_cpus": os.cpu_count(), "cpu_model": cpu_model(), "kind": "oracle",
+            "sample": f"{sample_pixels} random pixels of the 1920x1080 400k-surfel frame, one forward+backward call "
+                      f"of the FP64 oracle on {torch.get_num_threads()} threads: {dt:.1f} s"}
 
 
 def main():
@@ -258,26 +306,31 @@ def main():
     st = bf["stats"]
     P = st["P"]
     value = P / (bf["ms"] / 1000.0) / 1e6
-    per_launch = {k: v[0] / max(v[1], 1) for k, v in bf["phases"].items()}
     per_step = {k: v[0] / args.steps for k, v in bf["phases"].items()}
-    dom = max(per_step, key=lambda k: per_step[k])
-    nbytes, nflops = algorithmic(dom, st)
-    dur_s = per_step[dom] / 1000.0
-    achieved = nbytes / dur_s / 1e9
-    launches = bf["phases"][dom][1] // args.steps
-    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
+    form = {"outdoor": "bf16", "multiview": "f32", "large": "bf16"}[args.workload]
+    roofs = rooflines(bf["phases"], args.steps, st, form)
+    dom = max(roofs, key=lambda k: roofs[k]["ms_per_step"])
+    rd = roofs[dom]
+    launches = max(rd["launches_per_step"], 1)
+    avg_s = rd["ms_per_step"] / 1000.0 / launches
+    if rd["bound"] == "mfma":
+        achieved, peak, unit = rd["mfma_tflops"], rd["mfma_peak"], "TFLOP/s"
+    elif rd["bound"] == "alu":
+        achieved, peak, unit = rd["valu_tops"], round(VALU_PEAK_TOPS, 2), "T VALU lane-ops/s"
+    else:
+        achieved, peak, unit = rd["hbm_gbs"], HBM_PEAK_GBS, "GB/s"
+    roof = {"kernel": dom, "bound": rd["bound"], "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": round(achieved / peak, 5),
             "traffic": measured_traffic(dom) if args.workload == "outdoor" else None,
-            "avg_ms": round(per_launch[dom], 4), "launches_per_step": launches,
-            "algorithmic_bytes": nbytes / max(launches, 1)}
-    if nflops:
-        roof["mfma_tflops"] = round(nflops / dur_s / 1e12, 2)
-        roof["mfma_frac"] = round(nflops / dur_s / 1e12 / BF16_PEAK_TFLOPS, 5)
+            "avg_ms": round(avg_s * 1000.0, 4), "launches_per_step": launches,
+            "algorithmic_bytes_per_launch": rd["bytes_per_step"] / launches}
+    if rd["bound"] != "hbm":
+        roof["hbm_frac"] = rd["hbm_frac"]
     cfg = {"workload": WORKLOADS[args.workload][1], "surfels": st["N"], "cameras": st["C"], "pixels": P,
            "K": st["K"], "instances": st["I"], "stats": st["workload_stats"]}
     if st["C"] == 1:
         cfg.update(width=st["width"], height=st["height"])
-    dtype = {"outdoor": "bf16", "multiview": "f32", "large": "bf16"}[args.workload]
+    dtype = form
     line = {
         "metric": METRIC if args.workload == "outdoor" else "Mpix/s fwd+bwd",
         "value": round(value, 2), "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps,
@@ -285,6 +338,9 @@ def main():
         "vs_baseline": None, "dtype": dtype, "data": "synthetic",
         "config": cfg,
         "roofline": roof,
+        "raster": {k: {f: roofs[k].get(f) for f in ("ms_per_step", "hbm_frac", "valu_frac")}
+                   for k in ("raster_forward", "raster_backward") if k in roofs},
+        "rooflines": roofs,
         "phases_ms_per_step": {k: round(v, 4) for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},
     }
     if args.workload != "outdoor":
@@ -295,9 +351,12 @@ def main():
         f32 = time_form("fp32", max(3, args.steps // 2), max(1, args.warmup // 2), args.workload)
         n32 = max(3, args.steps // 2)
         ph32 = {k: v[0] / n32 for k, v in f32["phases"].items()}
+        r32 = rooflines(f32["phases"], n32, f32["stats"], "f32")
         line["fp32_form"] = {"value": round(P / (f32["ms"] / 1000.0) / 1e6, 2), "ms_per_step": round(f32["ms"], 4),
                              "phases_ms_per_step": {k: round(v, 4)
-                                                    for k, v in sorted(ph32.items(), key=lambda kv: -kv[1])}}
+                                                    for k, v in sorted(ph32.items(), key=lambda kv: -kv[1])},
+                             "mfma": {k: {f: r32[k].get(f) for f in ("mfma_tflops", "mfma_peak", "mfma_frac")}
+                                      for k in ("texture_forward", "texture_backward") if k in r32}}
     if args.copy_calibration > 0:
         n = args.copy_calibration * (1 << 20) // 4
         src = torch.rand(n, device="cuda")

@@ -23,8 +23,9 @@
  *     host word per context.
  *   - Arrays are dense and row-major; [a,b] means a rows of b elements.
  *   - Work is enqueued on the HIP stream passed as `stream` (NULL = the null
- *     stream). nx_render_forward synchronises that stream once to read the
- *     number of tile instances; nx_render_backward does not synchronise.
+ *     stream). nx_render_forward synchronises that stream once per camera to
+ *     read the number of tile instances; nx_render_forward_async and
+ *     nx_render_backward do not synchronise.
  *   - Calls that share a workspace must not overlap.
  */
 #ifndef NEXELS_H
@@ -116,6 +117,10 @@ typedef struct {
  *                    masks of the hidden units with a positive pre-activation,
  *                    layer 1 words then layer 2 words, bit i of word w for
  *                    unit 32 w + i (0 for empty slots)
+ *   features [P,K,levels*feat]  OPTIONAL (NULL = not written) float32 MLP
+ *                    inputs Delta_l * H_l(s_l x) per slot, level-major (feature
+ *                    f of level l at 2 l + f), as computed before any rounding
+ *                    to the MLP's storage type (0 for empty slots)
  *   n_instances      HOST array [n_cams] written by nx_render_forward: number
  *                    of (surfel, tile) pairs per camera; read by
  *                    nx_render_backward.
@@ -129,6 +134,7 @@ typedef struct {
   uint32_t *n_iter;
   int32_t *cells;
   uint32_t *relu_masks;
+  float *features;
   int64_t *n_instances;
 } nx_fwd_out;
 
@@ -136,11 +142,20 @@ typedef struct {
  * buffers: means [n,3], quats [n,4], scales [n,2], opacities [n],
  * gammas [n,2], colors [n,3], table [levels][1<<log2_size][feat] (always
  * float32 whatever the table's storage dtype), mlp[i] [dims[i+1]][dims[i]].
- * Any pointer may be NULL to skip that gradient. */
+ * Any pointer may be NULL to skip that gradient.
+ * Densification signal (supplementary, Densification: the blended errors of
+ * Rota Bulo et al., summed over iterations): when both are non-NULL,
+ * blended_error[i] (device, [n], +=) receives sum over pixels p of
+ * w_{i,p} pixel_error[p], with w = alpha T the blending weight of every
+ * surfel the collection pass composited at p (textured or not) and
+ * pixel_error a caller-supplied device array [P] (cameras concatenated as
+ * the forward's outputs), e.g. the pixel's L1 error. */
 typedef struct {
   float *means, *quats, *scales, *opacities, *gammas, *colors;
   float *table;
   float *mlp[3];
+  const float *pixel_error;
+  float *blended_error;
 } nx_grads;
 
 /* Opaque context: fixed configuration plus one pinned host word. */
@@ -153,7 +168,12 @@ int nx_create(nx_ctx **out, int32_t K, int32_t tile, nx_dtype feat_dtype, nx_dty
 int nx_destroy(nx_ctx *ctx);
 
 /* Workspace bytes for n_surfels surfels seen by n_cams cameras with at most
- * max_instances (surfel, tile) pairs per camera. The workspace starts with
+ * max_instances (surfel, tile) pairs per camera. The pair count depends on
+ * the surfels themselves, so it cannot be known from the sizes alone: with
+ * max_instances = 0 the result is the size for a single pair, enough for
+ * nx_render_forward to count the pairs (it then
+ * returns NX_ERR_WORKSPACE with the exact size in *workspace_required, after
+ * one synchronisation per camera). The workspace starts with
  * the backward's hash-scatter scratch shared by the cameras (two record
  * arenas of about 10 records per sample, and their slab tables), then holds
  * one section per camera, one after another; the sections carry the
@@ -172,6 +192,30 @@ int nx_workspace_size(nx_ctx *ctx, int64_t n_surfels, const nx_camera *cams, int
 int nx_render_forward(nx_ctx *ctx, const nx_surfels *surfels, const nx_camera *cams, int32_t n_cams,
                       const nx_hashgrid *grid, const nx_mlp *mlp, nx_fwd_out *out, void *workspace,
                       size_t workspace_bytes, size_t *workspace_required, void *stream);
+
+/* nx_render_forward without any host synchronisation, so that it can be
+ * captured in a HIP graph or queued back to back: every camera's section of
+ * the workspace is laid out for max_instances (surfel, tile) pairs, the
+ * instance count stays on the device, and the call returns as soon as the
+ * work is queued. The workspace must hold nx_workspace_size(..., n_cams,
+ * max_instances) bytes (NX_ERR_WORKSPACE otherwise, checked on the host).
+ * out->n_instances[c] receives max_instances (the layout the backward reads).
+ * A camera with more than max_instances pairs loses the pairs of its deepest
+ * surfels (pairs are numbered in centre-depth order), and its outputs are
+ * then wrong: read the true
+ * counts with nx_instance_counts and call again with a larger bound when one
+ * exceeds it. Outputs are otherwise bit-identical to nx_render_forward's. */
+int nx_render_forward_async(nx_ctx *ctx, const nx_surfels *surfels, const nx_camera *cams, int32_t n_cams,
+                            const nx_hashgrid *grid, const nx_mlp *mlp, nx_fwd_out *out, int64_t max_instances,
+                            void *workspace, size_t workspace_bytes, void *stream);
+
+/* True (surfel, tile) pair counts per camera of the last forward into
+ * `workspace`, whose layout n_instances (as that forward left it in
+ * out->n_instances) describes; synchronises `stream` first. counts: HOST
+ * array [n_cams]. */
+int nx_instance_counts(nx_ctx *ctx, int64_t n_surfels, const nx_camera *cams, int32_t n_cams,
+                       const int64_t *n_instances, const void *workspace, size_t workspace_bytes, int64_t *counts,
+                       void *stream);
 
 /* Gradients of L through both passes given dL/dimage [P,3] (device) and the
  * optional dL/dweights [P,K] and dL/dtex [P,K,3] (device, NULL = zero), all

@@ -38,3 +38,16 @@ def mlp_forward(z, weights, relu_masks=None):
         else:
             h = h * relu_masks[i]
     return h
+
+
+def hidden_preactivations(z, weights):
+    """Pre-activations W_i h_{i-1} of every hidden layer of the natural network
+    (h_0 = z, h_i = ReLU of the i-th pre-activation), as float64 arrays.
+    The sign of each is the ReLU decision the exact network takes."""
+    h = torch.as_tensor(np.asarray(z), dtype=torch.float64)
+    pre = []
+    for w in weights[:-1]:
+        p = h @ torch.as_tensor(w, dtype=torch.float64).t()
+        pre.append(p.numpy())
+        h = torch.relu(p)
+    return pre

@@ -46,6 +46,13 @@ they are reported separately as `mlp_margin`.
 force_cells pins the hash-grid lattice cell of each textured sample to the
 one another implementation reports, so that positional gradients are
 compared on the same branch of the piecewise-trilinear interpolation.
+
+want_decisions=True also returns the natural (unforced) decisions' inputs
+of every textured slot: the lattice positions s_l x (their floors are the
+natural cells) and the features z evaluated in the natural cells (the
+hidden pre-activations of the natural MLP follow from them), so that a
+decision another implementation reports can be checked against the FP64
+one.
 """
 from __future__ import annotations
 
@@ -74,6 +81,9 @@ class OracleOutputs:
     n_comp: np.ndarray   # [P] number of composited surfels
     margin: np.ndarray   # [P] collection-pass decisions: smallest margin / FP32 error scale
     mlp_margin: np.ndarray = None  # [P] MLP ReLU decisions of the textured samples, same units
+    lattice: np.ndarray = None     # [P,K,L,3] s_l x per textured slot (NaN for empty slots), want_decisions only
+    features: np.ndarray = None    # [P,K,L*F] natural-cell features z per textured slot (0 if empty)
+    blended_error: np.ndarray = None  # [N] sum over pixels of w_{i,p} E_p, when pixel_error is given
     grads: dict | None = None
 
 
@@ -94,7 +104,7 @@ def render(scene, cam, grid, mlp, K, pixels=None, tiled=False, bins=None, **kw):
 
 def render_and_grad(scene, cam, grid, mlp, K, pixels=None, grad_image=None, grad_weights=None,
                     grad_tex=None, tiled=False, bins=None, outer_pixels=2048, pair_budget=3_000_000,
-                    force_cells=None, force_relu=None, mlp_rel_err=5e-6):
+                    force_cells=None, force_relu=None, mlp_rel_err=5e-6, want_decisions=False, pixel_error=None):
     """Render the given pixels (all by default) and optionally back-propagate.
 
     grad_image [P,3], grad_weights [P,K] and grad_tex [P,K,3] are upstream
@@ -108,7 +118,11 @@ def render_and_grad(scene, cam, grid, mlp, K, pixels=None, grad_image=None, grad
     cell per textured slot and level; force_relu [P,K,2*hidden/32] (uint32
     bit words, layer 1 then layer 2) fixes the ReLU decisions per slot;
     mlp_rel_err is the relative error scale of the MLP pre-activations used
-    for the decision margins.
+    for the decision margins. want_decisions fills ``lattice`` and ``features``.
+    pixel_error [P] (per listed pixel) fills ``blended_error``: per surfel the
+    sum over pixels of its blending weight w = alpha T times the pixel's error
+    (supplementary, Densification: the blended errors of Rota Bulo et al.,
+    accumulated by adding).
     """
     need_grad = grad_image is not None or grad_weights is not None or grad_tex is not None
     W, H = cam.width, cam.height
@@ -137,6 +151,13 @@ def render_and_grad(scene, cam, grid, mlp, K, pixels=None, grad_image=None, grad
         "tex": np.zeros((P, K, 3)), "n_comp": np.zeros(P, dtype=np.int64), "margin": np.full(P, np.inf),
         "mlp_margin": np.full(P, np.inf),
     }
+    if want_decisions:
+        L_, F_ = grid.table.shape[0], grid.table.shape[2]
+        out["lattice"] = np.full((P, K, L_, 3), np.nan)
+        out["features"] = np.zeros((P, K, L_ * F_))
+    if pixel_error is not None:
+        out["blended_error"] = np.zeros(scene.n)
+        perr = np.asarray(pixel_error, dtype=np.float64)
     if P == 0:
         return OracleOutputs(pixels=pixels, grads=_collect_grads(prm, table, weights) if need_grad else None, **out)
 
@@ -186,11 +207,17 @@ def render_and_grad(scene, cam, grid, mlp, K, pixels=None, grad_image=None, grad
         fc = None if force_cells is None else np.asarray(force_cells)[sel]
         fr = None if force_relu is None else np.asarray(force_relu)[sel]
         res = _composite_chunk(pp, ss, Pc, o, d, prm, key_np, K, table, level_scales, cam.fx, weights, fc,
-                               mlp_rel_err, fr)
+                               mlp_rel_err, fr, want_decisions)
         for nm in ("image", "plain", "weights", "depths", "t_final", "tex"):
             out[nm][sel] = res[nm].detach().numpy()
         for nm in ("ids", "n_comp", "margin", "mlp_margin"):
             out[nm][sel] = res[nm]
+        if want_decisions:
+            out["lattice"][sel] = res["lattice"]
+            out["features"][sel] = res["features"]
+        if pixel_error is not None:
+            rows, cols = np.nonzero(res["comp"])
+            np.add.at(out["blended_error"], res["sid"][rows, cols], res["wfull"][rows, cols] * perr[sel][rows])
 
         if need_grad:
             loss = torch.zeros((), dtype=torch.float64)
@@ -218,7 +245,7 @@ def _collect_grads(prm, table, weights):
 
 
 def _composite_chunk(pp, ss, Pc, o, d, prm, key_np, K, table, level_scales, focal, weights, force_cells=None,
-                     mlp_rel_err=5e-6, force_relu=None):
+                     mlp_rel_err=5e-6, force_relu=None, want_decisions=False):
     """Phase 2 for one chunk of pixels: exact decisions, compositing, texture."""
     E = pp.shape[0]
     order = np.lexsort((ss, key_np[ss].astype(np.float64), pp))
@@ -294,12 +321,21 @@ def _composite_chunk(pp, ss, Pc, o, d, prm, key_np, K, table, level_scales, foca
     rows, slots = np.nonzero(has)
     tex = torch.zeros(Pc, K, 3, dtype=torch.float64)
     relu_margin = np.full(Pc, np.inf)
+    n_lv = table.shape[0]
+    lattice = np.full((Pc, K, n_lv, 3), np.nan) if want_decisions else None
+    features = np.zeros((Pc, K, n_lv * table.shape[2])) if want_decisions else None
     if rows.shape[0] > 0:
         rt, stt = torch.from_numpy(rows), torch.from_numpy(slots)
         D = Dk[rt, stt]
         x = o + D.unsqueeze(1) * d[rt]
         cells = None if force_cells is None else force_cells[rows, slots]
         z = encode(x, D, table, level_scales, focal, cells=cells)
+        if want_decisions:
+            with torch.no_grad():
+                xd = x.detach()
+                lattice[rows, slots] = np.stack([float(level_scales[l]) * xd.numpy() for l in range(n_lv)], axis=1)
+                zn = z if cells is None else encode(xd, D.detach(), table.detach(), level_scales, focal)
+                features[rows, slots] = zn.detach().numpy()
         masks = None
         if force_relu is not None:
             masks = unpack_masks(force_relu[rows, slots], weights[0].shape[0], len(weights) - 1)
@@ -316,7 +352,8 @@ def _composite_chunk(pp, ss, Pc, o, d, prm, key_np, K, table, level_scales, foca
                       u.detach().numpy(), v.detach().numpy(), t.detach().numpy(), Ta.detach().numpy(),
                       compn, wn, K, E, gmax)
     return {"image": image, "plain": plain, "weights": Wk, "depths": Dk, "t_final": t_final, "tex": tex,
-            "ids": Ik, "n_comp": n_comp, "margin": margin, "mlp_margin": relu_margin}
+            "ids": Ik, "n_comp": n_comp, "margin": margin, "mlp_margin": relu_margin, "lattice": lattice,
+            "features": features, "comp": compn, "sid": sidn, "wfull": wn}
 
 
 def _relu_margins(z, weights):

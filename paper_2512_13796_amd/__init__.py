@@ -8,8 +8,8 @@ from . import _lib
 
 _lib.load()
 
-from .render import (Context, ForwardResult, RenderFunction, camera_struct, render,  # noqa: E402,F401
-                     render_backward, render_forward)
+from .render import (Context, ForwardResult, RenderFunction, camera_struct, instance_counts,  # noqa: E402,F401
+                     render, render_backward, render_forward, workspace_size)
 
-__all__ = ["Context", "ForwardResult", "RenderFunction", "camera_struct", "render", "render_backward",
-           "render_forward"]
+__all__ = ["Context", "ForwardResult", "RenderFunction", "camera_struct", "instance_counts", "render",
+           "render_backward", "render_forward", "workspace_size"]

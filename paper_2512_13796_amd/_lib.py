@@ -44,12 +44,14 @@ class NxMLP(ctypes.Structure):
 class NxFwdOut(ctypes.Structure):
     _fields_ = [("image", c_void_p), ("plain", c_void_p), ("ids", c_void_p), ("weights", c_void_p),
                 ("depths", c_void_p), ("t_final", c_void_p), ("tex", c_void_p), ("n_iter", c_void_p),
-                ("cells", c_void_p), ("relu_masks", c_void_p), ("n_instances", ctypes.POINTER(ctypes.c_int64))]
+                ("cells", c_void_p), ("relu_masks", c_void_p), ("features", c_void_p),
+                ("n_instances", ctypes.POINTER(ctypes.c_int64))]
 
 
 class NxGrads(ctypes.Structure):
     _fields_ = [("means", c_void_p), ("quats", c_void_p), ("scales", c_void_p), ("opacities", c_void_p),
-                ("gammas", c_void_p), ("colors", c_void_p), ("table", c_void_p), ("mlp", c_void_p * 3)]
+                ("gammas", c_void_p), ("colors", c_void_p), ("table", c_void_p), ("mlp", c_void_p * 3),
+                ("pixel_error", c_void_p), ("blended_error", c_void_p)]
 
 
 class NxWsLayout(ctypes.Structure):
@@ -74,6 +76,12 @@ SIGNATURES = {
                             ctypes.POINTER(NxHashGrid), ctypes.POINTER(NxMLP), ctypes.POINTER(NxFwdOut), c_void_p,
                             ctypes.c_size_t, c_void_p, c_void_p, c_void_p, ctypes.POINTER(NxGrads), c_void_p],
                            ctypes.c_int),
+    "nx_render_forward_async": ([c_void_p, ctypes.POINTER(NxSurfels), ctypes.POINTER(NxCamera), ctypes.c_int32,
+                                 ctypes.POINTER(NxHashGrid), ctypes.POINTER(NxMLP), ctypes.POINTER(NxFwdOut),
+                                 ctypes.c_int64, c_void_p, ctypes.c_size_t, c_void_p], ctypes.c_int),
+    "nx_instance_counts": ([c_void_p, ctypes.c_int64, ctypes.POINTER(NxCamera), ctypes.c_int32,
+                            ctypes.POINTER(ctypes.c_int64), c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int64),
+                            c_void_p], ctypes.c_int),
     "nx_timing_enable": ([c_void_p, ctypes.c_int], ctypes.c_int),
     "nx_timing_reset": ([c_void_p], ctypes.c_int),
     "nx_timing_get": ([c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),

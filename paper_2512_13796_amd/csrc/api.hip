@@ -333,23 +333,16 @@ nx_fwd_out camera_slice(const nx_ctx* ctx, const nx_hashgrid* grid, const nx_mlp
   if (o.tex) c.tex = o.tex + 3 * K * pix;
   if (o.cells && grid) c.cells = o.cells + (int64_t)3 * grid->levels * K * pix;
   if (o.relu_masks && mlp) c.relu_masks = o.relu_masks + (int64_t)2 * (mlp->dims[1] / 32) * K * pix;
+  if (o.features && grid) c.features = o.features + (int64_t)grid->levels * grid->feat * K * pix;
   return c;
 }
 
-// One camera of nx_render_forward: out points at this camera's slices of the
-// outputs, workspace at its section. *need receives the section size this
-// camera requires so far (its instance count is known after the scan).
-int forward_one(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera& cam, const nx_hashgrid* grid,
-                const nx_mlp* mlp, const nx_fwd_out* out, void* workspace, size_t workspace_bytes, size_t* need,
-                int64_t* n_inst_out, hipStream_t s) {
-  const int K = ctx->K;
-  const nx::CamDev cd = make_cam(cam);
-  const int n_tiles = cd.ntx * cd.nty;
+// Collection pass up to the instance scan: per-surfel keys, counts,
+// rectangles and records, the depth sort, and the exclusive scan of the tile
+// counts in depth order (offsets[n] = number of instances, on the device).
+int forward_prefix(nx_ctx* ctx, const nx_surfels* surfels, const nx::CamDev& cd, void* ws, const Layout& L0,
+                   hipStream_t s) {
   const int64_t n = surfels->n;
-  const Layout L0 = make_layout(n, cd, K, 0);
-  *need = L0.total;
-  if (!workspace || workspace_bytes < L0.total) return fail(NX_ERR_WORKSPACE, "workspace too small");
-  void* ws = workspace;
 
   uint32_t* depth_keys = at<uint32_t>(ws, L0.depth_keys);
   uint32_t* counts = at<uint32_t>(ws, L0.tile_counts);
@@ -365,7 +358,7 @@ int forward_one(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera& cam, co
   uint32_t* offsets = at<uint32_t>(ws, L0.offsets);
   if (n > 0) {
     PhaseTimer pt(ctx, "depth_sort", s);
-    NX_CHECK_HIP(hipMemcpyAsync(sk, depth_keys, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    NX_CHECK_HIP(nx::launch_copy_u32(depth_keys, sk, n, s));
     NX_CHECK_HIP(nx::launch_iota(sv, n, s));
     // The I-part is not laid out yet: the histogram for the depth sort uses the
     // instance area, which is at least as large as the N-sized histogram.
@@ -376,9 +369,43 @@ int forward_one(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera& cam, co
     PhaseTimer pt(ctx, "instance_scan", s);
     NX_CHECK_HIP(nx::launch_gather_scan(counts, sv, offsets, at<uint32_t>(ws, L0.scan_blocks), n, s));
   }
-  NX_CHECK_HIP(hipMemcpyAsync(ctx->pinned, offsets + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  NX_CHECK_HIP(hipStreamSynchronize(s));
-  const int64_t n_inst = (int64_t)ctx->pinned[0];
+  return NX_OK;
+}
+
+// One camera of nx_render_forward: out points at this camera's slices of the
+// outputs, workspace at its section. With cap < 0 the call reads the
+// instance count back (one synchronisation) and lays the section out for
+// exactly that many; *need receives the section size this camera requires
+// so far. With cap >= 0 the section is laid out for cap instances, nothing
+// is read back, and instances past cap are dropped (the device keeps the
+// true count at offsets[n]).
+int forward_one(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera& cam, const nx_hashgrid* grid,
+                const nx_mlp* mlp, const nx_fwd_out* out, void* workspace, size_t workspace_bytes, size_t* need,
+                int64_t* n_inst_out, hipStream_t s, int64_t cap = -1) {
+  const int K = ctx->K;
+  const nx::CamDev cd = make_cam(cam);
+  const int n_tiles = cd.ntx * cd.nty;
+  const int64_t n = surfels->n;
+  const Layout L0 = make_layout(n, cd, K, cap >= 0 ? cap : 0);
+  *need = L0.total;
+  if (!workspace || workspace_bytes < L0.total) return fail(NX_ERR_WORKSPACE, "workspace too small");
+  void* ws = workspace;
+  int r = forward_prefix(ctx, surfels, cd, ws, L0, s);
+  if (r != NX_OK) return r;
+  uint32_t* sv = at<uint32_t>(ws, L0.sort_v);
+  uint32_t* offsets = at<uint32_t>(ws, L0.offsets);
+  int4* rects = at<int4>(ws, L0.rects);
+  float4* records = at<float4>(ws, L0.records);
+  int64_t n_inst;
+  const uint32_t* n_dev = nullptr;
+  if (cap < 0) {
+    NX_CHECK_HIP(hipMemcpyAsync(ctx->pinned, offsets + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    NX_CHECK_HIP(hipStreamSynchronize(s));
+    n_inst = (int64_t)ctx->pinned[0];
+  } else {
+    n_inst = cap;
+    n_dev = offsets + n;
+  }
   const Layout L = make_layout(n, cd, K, n_inst);
   *n_inst_out = n_inst;
   *need = L.total;
@@ -388,17 +415,17 @@ int forward_one(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera& cam, co
   uint32_t* iid = at<uint32_t>(ws, L.inst_ids);
   {
     PhaseTimer pt(ctx, "duplicate", s);
-    NX_CHECK_HIP(nx::launch_duplicate(sv, offsets, rects, n, cd.ntx, it, iid, s));
+    NX_CHECK_HIP(nx::launch_duplicate(sv, offsets, rects, n, cd.ntx, n_inst, it, iid, s));
   }
   {
   PhaseTimer pt(ctx, "tile_sort", s);
   NX_CHECK_HIP(nx::radix_sort_pairs(it, iid, at<uint32_t>(ws, L.inst_tmp_tiles), at<uint32_t>(ws, L.inst_tmp_ids),
-                                    at<uint32_t>(ws, L.hist), n_inst, tile_bits(n_tiles), s));
+                                    at<uint32_t>(ws, L.hist), n_inst, tile_bits(n_tiles), s, n_dev));
   }
   uint2* ranges = at<uint2>(ws, L.tile_ranges);
   {
     PhaseTimer pt(ctx, "tile_ranges", s);
-    NX_CHECK_HIP(nx::launch_tile_ranges(it, n_inst, ranges, n_tiles, s));
+    NX_CHECK_HIP(nx::launch_tile_ranges(it, n_inst, ranges, n_tiles, s, n_dev));
   }
   {
   PhaseTimer pt(ctx, "raster_forward", s);
@@ -418,7 +445,7 @@ int forward_one(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera& cam, co
   PhaseTimer pt(ctx, "texture_forward", s);
   NX_CHECK_HIP(nx::launch_texture_forward(K, ctx->feat_dtype, ctx->mlp_dtype, gd, K > 0 ? grid->table : nullptr, md,
                                           out->ids, out->depths, out->weights, out->plain, out->tex, out->image,
-                                          out->cells, out->relu_masks, s));
+                                          out->cells, out->relu_masks, out->features, s));
   }
   return NX_OK;
 }
@@ -430,7 +457,7 @@ int forward_one(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera& cam, co
 int backward_one(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera& cam, const nx_hashgrid* grid,
                  const nx_mlp* mlp, const nx_fwd_out* saved, int64_t n_inst, void* workspace,
                  const float* grad_image, const float* grad_weights, const float* grad_tex, const nx_grads* grads,
-                 hipStream_t s, int part) {
+                 const float* pixel_error, hipStream_t s, int part) {
   const int K = ctx->K;
   const nx::CamDev cd = make_cam(cam);
   const int64_t n = surfels->n;
@@ -444,12 +471,13 @@ int backward_one(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera& cam, c
       NX_CHECK_HIP(nx::launch_raster_backward(K, at<float4>(ws, L.records), at<uint32_t>(ws, L.inst_ids),
                                               at<uint2>(ws, L.tile_ranges), cd, saved->plain, saved->ids,
                                               saved->weights, saved->tex, saved->n_iter, grad_image, grad_weights,
-                                              K > 0 ? gdepth : nullptr, rec_grad, s));
+                                              K > 0 ? gdepth : nullptr, pixel_error, rec_grad, s));
     }
     PhaseTimer pt(ctx, "preprocess_backward", s);
     NX_CHECK_HIP(nx::launch_preprocess_backward(surfels->means, surfels->quats, surfels->scales, n, cd,
                                                 at<uint32_t>(ws, L.tile_counts), rec_grad, grads->means, grads->quats,
-                                                grads->scales, grads->opacities, grads->gammas, grads->colors, s));
+                                                grads->scales, grads->opacities, grads->gammas, grads->colors,
+                                                pixel_error ? grads->blended_error : nullptr, s));
     return NX_OK;
   }
   {
@@ -480,7 +508,7 @@ int backward_one(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera& cam, c
 
 extern "C" {
 
-int nx_version(void) { return 100; }
+int nx_version(void) { return 200; }
 
 const char* nx_last_error(void) { return g_last_error.c_str(); }
 
@@ -649,6 +677,71 @@ int nx_render_forward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* c
   return NX_OK;
 }
 
+int nx_render_forward_async(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* cams, int32_t n_cams,
+                            const nx_hashgrid* grid, const nx_mlp* mlp, nx_fwd_out* out, int64_t max_instances,
+                            void* workspace, size_t workspace_bytes, void* stream) {
+  int r;
+  if ((r = check_ctx(ctx)) != NX_OK) return r;
+  if ((r = check_surfels(surfels)) != NX_OK) return r;
+  if ((r = check_camera(cams, n_cams)) != NX_OK) return r;
+  if ((r = check_grid_mlp(ctx, grid, mlp)) != NX_OK) return r;
+  if (!out || !out->image || !out->plain || !out->t_final || !out->n_iter || !out->n_instances)
+    return fail(NX_ERR_INVALID, "an output pointer is NULL");
+  if (ctx->K > 0 && (!out->ids || !out->weights || !out->depths || !out->tex))
+    return fail(NX_ERR_INVALID, "an output pointer is NULL");
+  if (max_instances < 1 || max_instances > 0xFFFFFFFFll)
+    return fail(NX_ERR_INVALID, "max_instances must be in [1, 2^32 - 1]");
+  const SharedLayout SH = make_shared_layout(cams, n_cams, ctx->K);
+  size_t total = SH.total;
+  for (int32_t c = 0; c < n_cams; ++c) total += make_layout(surfels->n, make_cam(cams[c]), ctx->K, max_instances).total;
+  if (!workspace || workspace_bytes < total)
+    return fail(NX_ERR_WORKSPACE, "workspace smaller than nx_workspace_size(..., max_instances)");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  NX_CHECK_HIP(hipGetLastError());
+  size_t off = SH.total;
+  int64_t pix = 0;
+  for (int32_t c = 0; c < n_cams; ++c) {
+    const nx_fwd_out oc = camera_slice(ctx, grid, mlp, *out, pix);
+    size_t need = 0;
+    int64_t n_inst = -1;
+    r = forward_one(ctx, surfels, cams[c], grid, mlp, &oc, at<char>(workspace, off), workspace_bytes - off, &need,
+                    &n_inst, s, max_instances);
+    if (r != NX_OK) return r;
+    out->n_instances[c] = max_instances;
+    off += need;
+    pix += (int64_t)cams[c].width * cams[c].height;
+  }
+  g_last_error.clear();
+  return NX_OK;
+}
+
+int nx_instance_counts(nx_ctx* ctx, int64_t n_surfels, const nx_camera* cams, int32_t n_cams,
+                       const int64_t* n_instances, const void* workspace, size_t workspace_bytes, int64_t* counts,
+                       void* stream) {
+  int r;
+  if ((r = check_ctx(ctx)) != NX_OK) return r;
+  if ((r = check_camera(cams, n_cams)) != NX_OK) return r;
+  if (n_surfels < 0 || !n_instances || !counts) return fail(NX_ERR_INVALID, "bad argument");
+  size_t off = make_shared_layout(cams, n_cams, ctx->K).total;
+  for (int32_t c = 0; c < n_cams; ++c) {
+    if (n_instances[c] < 0) return fail(NX_ERR_INVALID, "n_instances is negative");
+    off += make_layout(n_surfels, make_cam(cams[c]), ctx->K, n_instances[c]).total;
+  }
+  if (!workspace || workspace_bytes < off) return fail(NX_ERR_INVALID, "workspace does not match the forward");
+  NX_CHECK_HIP(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
+  off = make_shared_layout(cams, n_cams, ctx->K).total;
+  for (int32_t c = 0; c < n_cams; ++c) {
+    const Layout L = make_layout(n_surfels, make_cam(cams[c]), ctx->K, n_instances[c]);
+    uint32_t v = 0;
+    NX_CHECK_HIP(hipMemcpy(&v, at<char>(workspace, off + L.offsets + sizeof(uint32_t) * (size_t)n_surfels),
+                           sizeof(uint32_t), hipMemcpyDeviceToHost));
+    counts[c] = (int64_t)v;
+    off += L.total;
+  }
+  g_last_error.clear();
+  return NX_OK;
+}
+
 int nx_render_backward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* cams, int32_t n_cams,
                        const nx_hashgrid* grid, const nx_mlp* mlp, const nx_fwd_out* saved, const void* workspace,
                        size_t workspace_bytes, const float* grad_image, const float* grad_weights,
@@ -697,7 +790,8 @@ int nx_render_backward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* 
       const int64_t n_inst = saved->n_instances[c];
       r = backward_one(ctx, surfels, cams[c], grid, mlp, &sc, n_inst, at<char>(ws, off), grad_image + 3 * pix,
                        grad_weights ? grad_weights + K * pix : nullptr, grad_tex ? grad_tex + 3 * K * pix : nullptr,
-                       grads, sp, part);
+                       grads, (grads->pixel_error && grads->blended_error) ? grads->pixel_error + pix : nullptr, sp,
+                       part);
       if (r != NX_OK) return r;
       off += make_layout(surfels->n, make_cam(cams[c]), ctx->K, n_inst).total;
       pix += (int64_t)cams[c].width * cams[c].height;

@@ -35,7 +35,8 @@ constexpr int kRecF4 = 5;
 constexpr int kRecFloats = 4 * kRecF4;
 // Record-gradient slots (float32, per surfel): d/d of
 //   0 m_x, 1 m_y, 2 p1x, 3 p1y, 4 p2x, 5 p2y, 6 qx, 7 qy, 8 mz,
-//   9 opacity, 10 gamma1, 11 gamma2, 12 r, 13 g, 14 b
+//   9 opacity, 10 gamma1, 11 gamma2, 12 r, 13 g, 14 b,
+//   15 the blended error sum_p w_p E_p (not a gradient)
 constexpr int kRecGrad = 16;
 
 struct CamDev {
@@ -70,14 +71,19 @@ hipError_t launch_preprocess(const float* means, const float* quats, const float
 hipError_t launch_preprocess_backward(const float* means, const float* quats, const float* scales,
                                       int64_t n, const CamDev& cam, const uint32_t* tile_counts,
                                       const float* rec_grad, float* g_means, float* g_quats, float* g_scales,
-                                      float* g_opac, float* g_gammas, float* g_colors, hipStream_t s);
+                                      float* g_opac, float* g_gammas, float* g_colors, float* g_blended,
+                                      hipStream_t s);
 
 // Stable LSD radix sort of (key, value) pairs over bits [0, end_bit).
 // keys/vals hold the input and receive the output; tmp_* are scratch of the
-// same size; hist needs radix_hist_words(n) uint32 words.
+// same size; hist needs radix_hist_words(n) uint32 words. With n_dev the
+// number of pairs is min(n, *n_dev), read on the device (n is then the
+// capacity the launches are sized for, and no host synchronisation is needed).
 size_t radix_hist_words(int64_t n);
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals,
-                            uint32_t* hist, int64_t n, int end_bit, hipStream_t s);
+                            uint32_t* hist, int64_t n, int end_bit, hipStream_t s, const uint32_t* n_dev = nullptr);
+hipError_t launch_copy_u32(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s,
+                           const uint32_t* n_dev = nullptr);
 
 hipError_t launch_iota(uint32_t* out, int64_t n, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* out, uint32_t value, int64_t n, hipStream_t s);
@@ -86,10 +92,11 @@ hipError_t launch_fill_f32(float* out, float value, int64_t n, hipStream_t s);
 hipError_t launch_gather_scan(const uint32_t* counts, const uint32_t* order, uint32_t* offsets,
                               uint32_t* block_sums, int64_t n, hipStream_t s);
 size_t scan_block_words(int64_t n);
+// Instances o >= cap are not written (cap = capacity of tile_keys / ids).
 hipError_t launch_duplicate(const uint32_t* order, const uint32_t* offsets, const int4* rects, int64_t n,
-                            int ntx, uint32_t* tile_keys, uint32_t* ids, hipStream_t s);
+                            int ntx, int64_t cap, uint32_t* tile_keys, uint32_t* ids, hipStream_t s);
 hipError_t launch_tile_ranges(const uint32_t* tile_keys, int64_t n_inst, uint2* ranges, int n_tiles,
-                              hipStream_t s);
+                              hipStream_t s, const uint32_t* n_dev = nullptr);
 
 hipError_t launch_raster_forward(int K, const float4* records, const uint32_t* sorted_ids, const uint2* ranges,
                                  const CamDev& cam, float* plain, int32_t* ids, float* weights, float* depths,
@@ -99,7 +106,7 @@ hipError_t launch_raster_backward(int K, const float4* records, const uint32_t* 
                                   const CamDev& cam, const float* plain, const int32_t* ids,
                                   const float* weights, const float* tex, const uint32_t* n_iter,
                                   const float* grad_image, const float* grad_weights, const float* grad_depth,
-                                  float* rec_grad, hipStream_t s);
+                                  const float* pixel_error, float* rec_grad, hipStream_t s);
 
 struct MlpDev {
   const void* w[3];
@@ -109,7 +116,7 @@ struct MlpDev {
 hipError_t launch_texture_forward(int K, int feat_dtype, int mlp_dtype, const GridDev& grid, const void* table,
                                   const MlpDev& mlp, const int32_t* ids, const float* depths,
                                   const float* weights, const float* plain, float* tex, float* image,
-                                  int32_t* cells, uint32_t* relu_masks, hipStream_t s);
+                                  int32_t* cells, uint32_t* relu_masks, float* features, hipStream_t s);
 
 // Texture backward, first half: recompute features and MLP, back-propagate,
 // accumulate the MLP weight gradients and the depth gradient, and write the

@@ -240,11 +240,12 @@ __global__ __launch_bounds__(256) void preprocess_kernel(const float* __restrict
 __global__ __launch_bounds__(256) void preprocess_backward_kernel(
     const float* __restrict__ means, const float* __restrict__ quats, const float* __restrict__ scales, int64_t n,
     CamDev cam, const uint32_t* __restrict__ tile_counts, const float* __restrict__ rg, float* g_means,
-    float* g_quats, float* g_scales, float* g_opac, float* g_gammas, float* g_colors) {
+    float* g_quats, float* g_scales, float* g_opac, float* g_gammas, float* g_colors, float* g_blended) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (tile_counts[i] == 0) return;
   const float* r = rg + (int64_t)kRecGrad * i;
+  if (g_blended && r[15] != 0.0f) g_blended[i] += r[15];
   float gr[15];
   bool any = false;
   for (int k = 0; k < 15; ++k) {
@@ -300,11 +301,11 @@ hipError_t launch_preprocess(const float* means, const float* quats, const float
 hipError_t launch_preprocess_backward(const float* means, const float* quats, const float* scales, int64_t n,
                                       const CamDev& cam, const uint32_t* tile_counts, const float* rec_grad,
                                       float* g_means, float* g_quats, float* g_scales, float* g_opac,
-                                      float* g_gammas, float* g_colors, hipStream_t s) {
+                                      float* g_gammas, float* g_colors, float* g_blended, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const int64_t blocks = (n + 255) / 256;
   hipLaunchKernelGGL(preprocess_backward_kernel, dim3((unsigned)blocks), dim3(256), 0, s, means, quats, scales, n,
-                     cam, tile_counts, rec_grad, g_means, g_quats, g_scales, g_opac, g_gammas, g_colors);
+                     cam, tile_counts, rec_grad, g_means, g_quats, g_scales, g_opac, g_gammas, g_colors, g_blended);
   return hipGetLastError();
 }
 

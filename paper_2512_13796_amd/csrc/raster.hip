@@ -18,8 +18,9 @@
 //   dL/dalpha_i = T_i dL/dw_i - S_i / (1 - alpha_i),
 // where S starts at sum_k w_k dL/dw_k = g.N + sum_j W_j (g.Tex_j + dL/dW_j)
 // (all forward outputs) and drops by w_i dL/dw_i at every step. Per surfel
-// the 15 record gradients are reduced across the wavefront and added with
-// one atomic per value.
+// the 15 record gradients, and with a per-pixel error map the blended error
+// w_i E_p, are reduced across the wavefront and added with one atomic per
+// value.
 #include <math.h>
 
 #include "nx_internal.h"
@@ -251,7 +252,7 @@ __global__ __launch_bounds__(256) void raster_backward_kernel(
     int ntx, int width, int height, float near_z, const float* __restrict__ plain, const int32_t* __restrict__ ids,
     const float* __restrict__ weights, const float* __restrict__ tex, const uint32_t* __restrict__ n_iter,
     const float* __restrict__ grad_image, const float* __restrict__ grad_weights,
-    const float* __restrict__ grad_depth, float* __restrict__ rec_grad) {
+    const float* __restrict__ grad_depth, const float* __restrict__ pixel_error, float* __restrict__ rec_grad) {
   __shared__ float4 s_rec[kBatch * kRecF4];
   __shared__ uint32_t s_id[kBatch];
   const int tile = blockIdx.x;
@@ -261,7 +262,7 @@ __global__ __launch_bounds__(256) void raster_backward_kernel(
   const int lane = threadIdx.x & 63;
 
   constexpr int KB = K > 0 ? K : 1;
-  float g0 = 0.f, g1 = 0.f, g2 = 0.f, S = 0.f;
+  float g0 = 0.f, g1 = 0.f, g2 = 0.f, S = 0.f, perr = 0.f;
   int kid[KB];
   float gsel[KB], gdep[KB];
   uint32_t my_n = 0;
@@ -277,6 +278,7 @@ __global__ __launch_bounds__(256) void raster_backward_kernel(
     g1 = grad_image[3 * p + 1];
     g2 = grad_image[3 * p + 2];
     S = g0 * plain[3 * p] + g1 * plain[3 * p + 1] + g2 * plain[3 * p + 2];
+    if (pixel_error) perr = pixel_error[p];
     if (K > 0) {
 #pragma unroll
       for (int s = 0; s < KB; ++s) {
@@ -366,11 +368,12 @@ __global__ __launch_bounds__(256) void raster_backward_kernel(
         gv[7] = dden * e.dy;
         gv[0] = -(dnu * r1.x + dnv * r1.z + dden * r2.x);
         gv[1] = -(dnu * r1.y + dnv * r1.w + dden * r2.y);
+        gv[15] = w * perr;
         T *= one_m;
       }
       int which;
       const float tot = wave_transpose_sum16(gv, lane, &which);
-      if ((lane & 3) == 0 && which < 15 && tot != 0.0f)
+      if ((lane & 3) == 0 && tot != 0.0f)
         atomicAdd(&rec_grad[(int64_t)s_id[j] * kRecGrad + which], tot);
     }
   }
@@ -390,11 +393,11 @@ template <int K>
 hipError_t launch_bwd_k(const float4* records, const uint32_t* sorted_ids, const uint2* ranges, const CamDev& cam,
                         const float* plain, const int32_t* ids, const float* weights, const float* tex,
                         const uint32_t* n_iter, const float* grad_image, const float* grad_weights,
-                        const float* grad_depth, float* rec_grad, hipStream_t s) {
+                        const float* grad_depth, const float* pixel_error, float* rec_grad, hipStream_t s) {
   const int n_tiles = cam.ntx * cam.nty;
   hipLaunchKernelGGL(raster_backward_kernel<K>, dim3(n_tiles), dim3(256), 0, s, records, sorted_ids, ranges,
                      cam.ntx, cam.width, cam.height, (float)cam.near_z, plain, ids, weights, tex, n_iter, grad_image,
-                     grad_weights, grad_depth, rec_grad);
+                     grad_weights, grad_depth, pixel_error, rec_grad);
   return hipGetLastError();
 }
 
@@ -418,11 +421,11 @@ hipError_t launch_raster_forward(int K, const float4* records, const uint32_t* s
 hipError_t launch_raster_backward(int K, const float4* records, const uint32_t* sorted_ids, const uint2* ranges,
                                   const CamDev& cam, const float* plain, const int32_t* ids, const float* weights,
                                   const float* tex, const uint32_t* n_iter, const float* grad_image,
-                                  const float* grad_weights, const float* grad_depth, float* rec_grad,
-                                  hipStream_t s) {
+                                  const float* grad_weights, const float* grad_depth, const float* pixel_error,
+                                  float* rec_grad, hipStream_t s) {
 #define NX_BWD(KK)                                                                                             \
   return launch_bwd_k<KK>(records, sorted_ids, ranges, cam, plain, ids, weights, tex, n_iter, grad_image, \
-                          grad_weights, grad_depth, rec_grad, s)
+                          grad_weights, grad_depth, pixel_error, rec_grad, s)
   switch (K) {
     case 0: NX_BWD(0);
     case 1: NX_BWD(1);

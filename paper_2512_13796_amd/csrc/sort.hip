@@ -116,10 +116,19 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const uint32_t
   if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = block_sums[nb];
 }
 
+// The element count is n, or min(n, *n_dev) when n_dev is given (a count
+// that only the device knows, with n the capacity the launch was sized for).
+__device__ __forceinline__ int64_t live_count(int64_t n, const uint32_t* n_dev) {
+  if (!n_dev) return n;
+  const int64_t d = (int64_t)*n_dev;
+  return d < n ? d : n;
+}
+
 __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint32_t* __restrict__ keys, int64_t n,
-                                                                     int shift, int nblocks,
-                                                                     uint32_t* __restrict__ hist) {
+                                                                     const uint32_t* __restrict__ n_dev, int shift,
+                                                                     int nblocks, uint32_t* __restrict__ hist) {
   __shared__ uint32_t h[kSortWaves][256];
+  n = live_count(n, n_dev);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   for (int d = tid; d < kSortWaves * 256; d += kSortThreads) (&h[0][0])[d] = 0;
   __syncthreads();
@@ -135,8 +144,10 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint3
 
 __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
-    uint32_t* __restrict__ vals_out, const uint32_t* __restrict__ hist, int64_t n, int shift, int nblocks) {
+    uint32_t* __restrict__ vals_out, const uint32_t* __restrict__ hist, int64_t n, const uint32_t* __restrict__ n_dev,
+    int shift, int nblocks) {
   __shared__ uint32_t wcount[kSortWaves][256];
+  n = live_count(n, n_dev);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   for (int d = tid; d < kSortWaves * 256; d += kSortThreads) (&wcount[0][0])[d] = 0;
   __syncthreads();
@@ -192,6 +203,13 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
   }
 }
 
+__global__ void copy_u32_kernel(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int64_t n,
+                                const uint32_t* __restrict__ n_dev) {
+  n = live_count(n, n_dev);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = in[i];
+}
+
 __global__ void iota_kernel(uint32_t* out, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = (uint32_t)i;
@@ -211,11 +229,12 @@ __global__ void fill_f32_kernel(float* out, float value, int64_t n) {
 // form one contiguous range, which the wave writes with consecutive lanes on
 // consecutive instances (coalesced, and long tile lists are shared by all
 // lanes). Instance o of surfel j is tile (x0 + t mod w, y0 + t div w) with
-// t = o - offsets[j], row-major over its rectangle.
+// t = o - offsets[j], row-major over its rectangle. Instances at or past
+// `cap` (the capacity of tile_keys / ids) are not written.
 __global__ __launch_bounds__(256) void duplicate_kernel(const uint32_t* __restrict__ order,
                                                         const uint32_t* __restrict__ offsets,
                                                         const int4* __restrict__ rects, int64_t n, int ntx,
-                                                        uint32_t* __restrict__ tile_keys,
+                                                        uint32_t cap, uint32_t* __restrict__ tile_keys,
                                                         uint32_t* __restrict__ ids) {
   __shared__ uint32_t soff[4][65];
   __shared__ uint32_t sid[4][64];
@@ -236,7 +255,9 @@ __global__ __launch_bounds__(256) void duplicate_kernel(const uint32_t* __restri
   __builtin_amdgcn_wave_barrier();
   asm volatile("" ::: "memory");
   __builtin_amdgcn_wave_barrier();
-  const uint32_t base = soff[wave][0], total = soff[wave][64] - base;
+  const uint32_t base = soff[wave][0];
+  const uint32_t end = soff[wave][64] < cap ? soff[wave][64] : cap;
+  const uint32_t total = end > base ? end - base : 0u;
   for (uint32_t k = lane; k < total; k += 64) {
     const uint32_t o = base + k;
     // last surfel j whose range starts at or before o (non-empty: o < its end)
@@ -254,7 +275,9 @@ __global__ __launch_bounds__(256) void duplicate_kernel(const uint32_t* __restri
 }
 
 __global__ __launch_bounds__(256) void tile_ranges_kernel(const uint32_t* __restrict__ keys, int64_t n,
+                                                          const uint32_t* __restrict__ n_dev,
                                                           uint2* __restrict__ ranges) {
+  n = live_count(n, n_dev);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint32_t t = keys[i];
@@ -286,7 +309,7 @@ hipError_t launch_gather_scan(const uint32_t* counts, const uint32_t* order, uin
 }
 
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals, uint32_t* hist,
-                            int64_t n, int end_bit, hipStream_t s) {
+                            int64_t n, int end_bit, hipStream_t s, const uint32_t* n_dev) {
   if (n <= 1 || end_bit <= 0) return hipSuccess;
   const int nblocks = (int)((n + kBlockItems - 1) / kBlockItems);
   const int64_t hn = 256 * (int64_t)nblocks;
@@ -295,7 +318,8 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, 
   uint32_t *ki = keys, *vi = vals, *ko = tmp_keys, *vo = tmp_vals;
   int passes = 0;
   for (int shift = 0; shift < end_bit; shift += 8, ++passes) {
-    hipLaunchKernelGGL(radix_upsweep_kernel, dim3(nblocks), dim3(kSortThreads), 0, s, ki, n, shift, nblocks, hist);
+    hipLaunchKernelGGL(radix_upsweep_kernel, dim3(nblocks), dim3(kSortThreads), 0, s, ki, n, n_dev, shift, nblocks,
+                       hist);
     hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)snb), dim3(kScanThreads), 0, s, hist, nullptr, hn,
                        scan_tmp);
     hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(kScanThreads), 0, s, scan_tmp, snb);
@@ -303,17 +327,25 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, 
     hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)snb), dim3(kScanThreads), 0, s, hist, nullptr, hn, scan_tmp,
                        hist, snb);
     hipLaunchKernelGGL(radix_downsweep_kernel, dim3(nblocks), dim3(kSortThreads), 0, s, ki, vi, ko, vo, hist, n,
-                       shift, nblocks);
+                       n_dev, shift, nblocks);
     uint32_t* t;
     t = ki; ki = ko; ko = t;
     t = vi; vi = vo; vo = t;
   }
   if (passes & 1) {
-    hipError_t e = hipMemcpyAsync(keys, ki, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+    hipError_t e = launch_copy_u32(ki, keys, n, s, n_dev);
     if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(vals, vi, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+    e = launch_copy_u32(vi, vals, n, s, n_dev);
     if (e != hipSuccess) return e;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_u32(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s, const uint32_t* n_dev) {
+  if (n == 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(copy_u32_kernel, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, s, in, out, n,
+                     n_dev);
   return hipGetLastError();
 }
 
@@ -336,18 +368,19 @@ hipError_t launch_fill_f32(float* out, float value, int64_t n, hipStream_t s) {
 }
 
 hipError_t launch_duplicate(const uint32_t* order, const uint32_t* offsets, const int4* rects, int64_t n, int ntx,
-                            uint32_t* tile_keys, uint32_t* ids, hipStream_t s) {
-  if (n == 0) return hipSuccess;
+                            int64_t cap, uint32_t* tile_keys, uint32_t* ids, hipStream_t s) {
+  if (n == 0 || cap <= 0) return hipSuccess;
   hipLaunchKernelGGL(duplicate_kernel, dim3(grid1d(n, 256)), dim3(256), 0, s, order, offsets, rects, n, ntx,
-                     tile_keys, ids);
+                     (uint32_t)(cap < 0xFFFFFFFFll ? cap : 0xFFFFFFFFll), tile_keys, ids);
   return hipGetLastError();
 }
 
 hipError_t launch_tile_ranges(const uint32_t* tile_keys, int64_t n_inst, uint2* ranges, int n_tiles,
-                              hipStream_t s) {
+                              hipStream_t s, const uint32_t* n_dev) {
   hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * (int64_t)n_tiles, s);
   if (e != hipSuccess || n_inst == 0) return e;
-  hipLaunchKernelGGL(tile_ranges_kernel, dim3(grid1d(n_inst, 256)), dim3(256), 0, s, tile_keys, n_inst, ranges);
+  hipLaunchKernelGGL(tile_ranges_kernel, dim3(grid1d(n_inst, 256)), dim3(256), 0, s, tile_keys, n_inst, n_dev,
+                     ranges);
   return hipGetLastError();
 }
 

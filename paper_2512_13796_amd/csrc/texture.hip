@@ -524,7 +524,8 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 && BF && TDT != NX_F32) ? 3
                                                                       float* __restrict__ tex,
                                                                       float* __restrict__ image,
                                                                       int32_t* __restrict__ cells,
-                                                                      uint32_t* __restrict__ relu_masks) {
+                                                                      uint32_t* __restrict__ relu_masks,
+                                                                      float* __restrict__ features) {
   using LY = WLayout<BF, HID>;
   constexpr int MT = LY::MT;
   __shared__ __attribute__((aligned(16))) unsigned char lds[LY::nFwd * LY::slot_bytes];
@@ -553,6 +554,17 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 && BF && TDT != NX_F32) ? 3
         // the features are complete here: keep the table entries from
         // living on into the MLP
         asm volatile("" : "+v"(z[2 * i]), "+v"(z[2 * i + 1]));
+      }
+      if (features && si.valid) {
+        float* fp = features + si.s * gd.levels * 2;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int l = lane_level(g, i);
+          if (l < gd.levels) {
+            fp[2 * l] = z[2 * i];
+            fp[2 * l + 1] = z[2 * i + 1];
+          }
+        }
       }
       f4 h1[MT], h2[MT];
       const f4 o = mlp_forward<BF, HID>(lds, lane, z, h1, h2);
@@ -1418,14 +1430,14 @@ int ilog2(int k) {
 template <int TDT, bool BF, int HID>
 hipError_t fwd_inst(const GridDev& gd, const void* table, const MlpDev& mlp, int K, int64_t n_samples,
                     const int32_t* ids, const float* depths, const float* weights, const float* plain, float* tex,
-                    float* image, int32_t* cells, uint32_t* masks, hipStream_t s) {
+                    float* image, int32_t* cells, uint32_t* masks, float* feats, hipStream_t s) {
   const int64_t n_q = n_patches(gd);
   int64_t grid = (n_q + kWaves - 1) / kWaves;
   if (grid > 4096) grid = 4096;
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL((texture_forward_kernel<TDT, BF, HID>), dim3((unsigned)grid), dim3(kTexThreads), 0, s, gd, table,
                      mlp.w[0], mlp.w[1], mlp.w[2], mlp.in_dim, K, ilog2(K), n_samples, ids, depths, weights, plain,
-                     tex, image, cells, masks);
+                     tex, image, cells, masks, feats);
   return hipGetLastError();
 }
 
@@ -1452,14 +1464,17 @@ hipError_t bwd_inst(const GridDev& gd, const void* table, const MlpDev& mlp, int
 template <bool BF, int HID>
 hipError_t fwd_by_table(int tdt, const GridDev& gd, const void* table, const MlpDev& mlp, int K, int64_t n,
                         const int32_t* ids, const float* depths, const float* weights, const float* plain,
-                        float* tex, float* image, int32_t* cells, uint32_t* masks, hipStream_t s) {
+                        float* tex, float* image, int32_t* cells, uint32_t* masks, float* feats, hipStream_t s) {
   switch (tdt) {
     case NX_F32:
-      return fwd_inst<NX_F32, BF, HID>(gd, table, mlp, K, n, ids, depths, weights, plain, tex, image, cells, masks, s);
+      return fwd_inst<NX_F32, BF, HID>(gd, table, mlp, K, n, ids, depths, weights, plain, tex, image, cells, masks,
+                                       feats, s);
     case NX_F16:
-      return fwd_inst<NX_F16, BF, HID>(gd, table, mlp, K, n, ids, depths, weights, plain, tex, image, cells, masks, s);
+      return fwd_inst<NX_F16, BF, HID>(gd, table, mlp, K, n, ids, depths, weights, plain, tex, image, cells, masks,
+                                       feats, s);
     case NX_BF16:
-      return fwd_inst<NX_BF16, BF, HID>(gd, table, mlp, K, n, ids, depths, weights, plain, tex, image, cells, masks, s);
+      return fwd_inst<NX_BF16, BF, HID>(gd, table, mlp, K, n, ids, depths, weights, plain, tex, image, cells, masks,
+                                        feats, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1488,7 +1503,7 @@ hipError_t bwd_by_table(int tdt, const GridDev& gd, const void* table, const Mlp
 hipError_t launch_texture_forward(int K, int feat_dtype, int mlp_dtype, const GridDev& grid, const void* table,
                                   const MlpDev& mlp, const int32_t* ids, const float* depths, const float* weights,
                                   const float* plain, float* tex, float* image, int32_t* cells, uint32_t* masks,
-                                  hipStream_t s) {
+                                  float* feats, hipStream_t s) {
   const int64_t P = (int64_t)grid.width * grid.height;
   if (K == 0) {
     if (P == 0) return hipSuccess;
@@ -1500,14 +1515,14 @@ hipError_t launch_texture_forward(int K, int feat_dtype, int mlp_dtype, const Gr
   const bool bf = mlp_dtype == NX_BF16;
   if (mlp.hidden == 64)
     return bf ? fwd_by_table<true, 64>(feat_dtype, grid, table, mlp, K, n, ids, depths, weights, plain, tex, image,
-                                       cells, masks, s)
+                                       cells, masks, feats, s)
               : fwd_by_table<false, 64>(feat_dtype, grid, table, mlp, K, n, ids, depths, weights, plain, tex, image,
-                                        cells, masks, s);
+                                        cells, masks, feats, s);
   if (mlp.hidden == 128)
     return bf ? fwd_by_table<true, 128>(feat_dtype, grid, table, mlp, K, n, ids, depths, weights, plain, tex, image,
-                                        cells, masks, s)
+                                        cells, masks, feats, s)
               : fwd_by_table<false, 128>(feat_dtype, grid, table, mlp, K, n, ids, depths, weights, plain, tex, image,
-                                         cells, masks, s);
+                                         cells, masks, feats, s);
   return hipErrorInvalidValue;
 }
 

@@ -117,6 +117,7 @@ class ForwardResult:
     near: float = 0.2
     cells: torch.Tensor = None
     relu_masks: torch.Tensor = None
+    features: torch.Tensor = None
 
 
 def _structs(ctx, surfels, table, level_scales, weights, device):
@@ -154,15 +155,45 @@ def _cameras(cam):
     return list(cam) if isinstance(cam, (list, tuple)) else [cam]
 
 
+def workspace_size(ctx: Context, n_surfels, cam, max_instances, near=0.2):
+    """nx_workspace_size for one camera or a list of cameras."""
+    cams = _cameras(cam)
+    cs = (L.NxCamera * len(cams))(*[camera_struct(c, near) for c in cams])
+    size = ctypes.c_size_t()
+    L.check(ctx.lib.nx_workspace_size(ctx.handle, int(n_surfels), cs, len(cams), int(max_instances),
+                                      ctypes.byref(size)))
+    return int(size.value)
+
+
+def instance_counts(ctx: Context, n_surfels, res: ForwardResult):
+    """True (surfel, tile) pair counts per camera of the forward that produced res (nx_instance_counts;
+    synchronises the current stream)."""
+    cams = _cameras(res.camera)
+    cs = (L.NxCamera * len(cams))(*[camera_struct(c, res.near) for c in cams])
+    lay = (ctypes.c_int64 * len(cams))(*res.n_instances_cam)
+    out = (ctypes.c_int64 * len(cams))()
+    stream = ctypes.c_void_p(torch.cuda.current_stream(res.workspace.device).cuda_stream)
+    L.check(ctx.lib.nx_instance_counts(ctx.handle, int(n_surfels), cs, len(cams), lay, _ptr(res.workspace),
+                                       res.workspace.numel(), out, stream))
+    return [int(v) for v in out]
+
+
 def render_forward(ctx: Context, surfels, cam, table=None, level_scales=None, weights=None, near=0.2,
-                   workspace=None, want_cells=False) -> ForwardResult:
+                   workspace=None, want_cells=False, max_instances=None) -> ForwardResult:
     """Collection and texturing passes (nx_render_forward) for one camera or a
     list of cameras; with several cameras every per-pixel output holds the
     cameras one after another.
 
+    max_instances (per camera) selects nx_render_forward_async: no host
+    synchronisation, the workspace laid out for that many (surfel, tile)
+    pairs (allocated here unless `workspace` is given), n_instances_cam set
+    to that bound and n_instances to -1; instance_counts() reads the true
+    counts.
+
     want_cells=True also returns the hash-grid lattice cells the texturing
-    pass used ([P, K, levels, 3] int32) and its ReLU decisions
-    ([P, K, 2*hidden/32] int32 bit masks), for decision-level comparisons."""
+    pass used ([P, K, levels, 3] int32), its ReLU decisions
+    ([P, K, 2*hidden/32] int32 bit masks) and the MLP inputs it formed
+    ([P, K, levels*feat] float32), for decision-level comparisons."""
     device = surfels[0].device
     s, g, m, keep = _structs(ctx, surfels, table, level_scales, weights, device)
     cams = _cameras(cam)
@@ -180,11 +211,23 @@ def render_forward(ctx: Context, surfels, cam, table=None, level_scales=None, we
     if want_cells and K > 0:
         res.cells = torch.zeros(P, K, table.shape[0], 3, device=device, dtype=torch.int32)
         res.relu_masks = torch.zeros(P, K, 2 * weights[0].shape[0] // 32, device=device, dtype=torch.int32)
+        res.features = torch.zeros(P, K, table.shape[0] * table.shape[2], device=device, dtype=torch.float32)
     n_inst = (ctypes.c_int64 * len(cams))()
     out = L.NxFwdOut(_ptr(res.image), _ptr(res.plain), _ptr(res.ids), _ptr(res.weights), _ptr(res.depths),
                      _ptr(res.t_final), _ptr(res.tex), _ptr(res.n_iter), _ptr(res.cells), _ptr(res.relu_masks),
-                     n_inst)
+                     _ptr(res.features), n_inst)
     stream = ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+    if max_instances is not None:
+        size = workspace_size(ctx, surfels[0].shape[0], cams, max_instances, near)
+        ws = workspace if workspace is not None else torch.empty(size, device=device, dtype=torch.uint8)
+        L.check(ctx.lib.nx_render_forward_async(ctx.handle, ctypes.byref(s), cs, len(cams), ctypes.byref(g),
+                                                ctypes.byref(m), ctypes.byref(out), int(max_instances), _ptr(ws),
+                                                ws.numel(), stream))
+        res.n_instances_cam = [int(v) for v in n_inst]
+        res.n_instances = -1
+        res.workspace = ws
+        del keep
+        return res
     need = ctypes.c_size_t(0)
     ws = workspace
     for _ in range(len(cams) + 3):
@@ -210,8 +253,11 @@ def render_forward(ctx: Context, surfels, cam, table=None, level_scales=None, we
 
 
 def render_backward(ctx: Context, surfels, fwd: ForwardResult, table=None, level_scales=None, weights=None,
-                    grad_image=None, grad_weights=None, grad_tex=None, grads=None):
-    """Accumulate gradients into ``grads`` (dict of float32 tensors; missing keys are skipped)."""
+                    grad_image=None, grad_weights=None, grad_tex=None, grads=None, pixel_error=None):
+    """Accumulate gradients into ``grads`` (dict of float32 tensors; missing keys are skipped).
+
+    pixel_error [P] (optional) adds the blended errors sum_p w_{i,p} pixel_error[p] into grads["blended_error"]
+    [n] (the densification signal)."""
     device = surfels[0].device
     s, g, m, keep = _structs(ctx, surfels, table, level_scales, weights, device)
     cams = _cameras(fwd.camera)
@@ -233,9 +279,14 @@ def render_backward(ctx: Context, surfels, fwd: ForwardResult, table=None, level
                    _ptr(grads.get("table")))
     for i in range(3):
         gs.mlp[i] = None if gm[i] is None else gm[i].data_ptr()
+    if pixel_error is not None:
+        _check_dev("pixel_error", pixel_error, device, torch.float32, (P,))
+        _check_dev("grads[blended_error]", grads["blended_error"], device, torch.float32, (surfels[0].shape[0],))
+        gs.pixel_error = _ptr(pixel_error)
+        gs.blended_error = _ptr(grads["blended_error"])
     n_inst = (ctypes.c_int64 * len(cams))(*fwd.n_instances_cam)
     out = L.NxFwdOut(_ptr(fwd.image), _ptr(fwd.plain), _ptr(fwd.ids), _ptr(fwd.weights), _ptr(fwd.depths),
-                     _ptr(fwd.t_final), _ptr(fwd.tex), _ptr(fwd.n_iter), None, None, n_inst)
+                     _ptr(fwd.t_final), _ptr(fwd.tex), _ptr(fwd.n_iter), None, None, None, n_inst)
     stream = ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
     L.check(ctx.lib.nx_render_backward(ctx.handle, ctypes.byref(s), cs, len(cams), ctypes.byref(g),
                                        ctypes.byref(m), ctypes.byref(out), _ptr(fwd.workspace), fwd.workspace.numel(),

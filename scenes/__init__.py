@@ -333,7 +333,7 @@ def _target_images(rng, cams):
 
 
 def make_workload(config: int, seed: int = 0, *, n_surfels=None, width=None, height=None,
-                  feat_dtype=None, mlp_dtype=None, K=None) -> Workload:
+                  feat_dtype=None, mlp_dtype=None, K=None, grid_amp=1e-2) -> Workload:
     """Build one of the five synthetic workloads.
 
     1: 2000 surfels uniform in [-1,1]^3, 128x128, K=4, grid 8 x 2^14 x 2 fp32, MLP 16-64-64-3 fp32.
@@ -345,7 +345,8 @@ def make_workload(config: int, seed: int = 0, *, n_surfels=None, width=None, hei
     5: config-3 generator at 1M, 2560x1440, K=8, grid 16 x 2^21 x 2 bf16, MLP 32-128-128-3 bf16.
 
     Keyword overrides shrink a workload for tests (surfel count, image size,
-    dtypes, K); the draw order is unchanged.
+    dtypes, K) or scale the table's initial entries to U(-grid_amp, grid_amp);
+    the draw order is unchanged.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     if config == 1:
@@ -353,7 +354,7 @@ def make_workload(config: int, seed: int = 0, *, n_surfels=None, width=None, hei
         scene = _uniform_scene(rng, n)
         w, h = width or 128, height or 128
         cam = look_at((0.0, 0.0, -3.0), (0.0, 0.0, 0.0), (0.0, -1.0, 0.0), w, h)
-        grid = _grid(rng, 8, 14, 2, feat_dtype or torch.float32)
+        grid = _grid(rng, 8, 14, 2, feat_dtype or torch.float32, amp=grid_amp)
         mlp = _mlp(rng, [16, 64, 64, 3], mlp_dtype or torch.float32)
         cams = [cam]
         target = _target_images(rng, cams)
@@ -378,7 +379,7 @@ def make_workload(config: int, seed: int = 0, *, n_surfels=None, width=None, hei
                 if width is not None:
                     rw, rh = width, height
                 cams.append(look_at(eye, tgt, (0.0, -1.0, 0.0), rw, rh))
-        grid = _grid(rng, 16, 19, 2, feat_dtype or torch.float32)
+        grid = _grid(rng, 16, 19, 2, feat_dtype or torch.float32, amp=grid_amp)
         mlp = _mlp(rng, [32, 64, 64, 3], mlp_dtype or torch.float32)
         target = _target_images(rng, cams)
         return Workload(CONFIG_NAMES[config], scene, cams, grid, mlp, K or 4, target)
@@ -395,11 +396,11 @@ def make_workload(config: int, seed: int = 0, *, n_surfels=None, width=None, hei
         fwd = np.array([0.0, -math.sin(pitch), math.cos(pitch)])
         cam = look_at(eye, eye + fwd, (0.0, 1.0, 0.0), w, h)
         if config == 3:
-            grid = _grid(rng, 16, 19, 2, feat_dtype or torch.float16)
+            grid = _grid(rng, 16, 19, 2, feat_dtype or torch.float16, amp=grid_amp)
             mlp = _mlp(rng, [32, 64, 64, 3], mlp_dtype or torch.bfloat16)
             kk = K or 4
         else:
-            grid = _grid(rng, 16, 21, 2, feat_dtype or torch.bfloat16)
+            grid = _grid(rng, 16, 21, 2, feat_dtype or torch.bfloat16, amp=grid_amp)
             mlp = _mlp(rng, [32, 128, 128, 3], mlp_dtype or torch.bfloat16)
             kk = K or 8
         cams = [cam]

@@ -104,19 +104,115 @@ def psnr(a, b):
 
 
 def grad_errors(g_gpu, g_orc):
-    """Per-tensor relative L2 error, and the fraction of elements over the
-    per-element bound 1e-3 max(|g|, 0.1 rms(g)).
+    """Error statistics of one gradient tensor against the oracle's.
 
-    The floor at a tenth of the tensor's rms reflects FP32 accumulation over
-    thousands of samples: every element carries an absolute error of order
-    1e-5 rms(g) whatever its own size, so smaller elements are compared in
-    absolute terms."""
+    rel_l2      ||g_gpu - g||_2 / ||g||_2
+    viol        fraction of elements over 1e-3 max(|g|, 1e-2 rms(g)) (the
+                per-element rule)
+    viol_coarse fraction over 1e-3 max(|g|, 1e-1 rms(g))
+    max_abs, mean_abs, rms  absolute errors and the tensor's own rms."""
     g_gpu = np.asarray(g_gpu, dtype=np.float64).reshape(-1)
     g_orc = np.asarray(g_orc, dtype=np.float64).reshape(-1)
     diff = np.abs(g_gpu - g_orc)
     norm = np.linalg.norm(g_orc)
     rel_l2 = float(np.linalg.norm(g_gpu - g_orc) / norm) if norm > 0 else float(np.linalg.norm(g_gpu))
     rms = math.sqrt(float(np.mean(g_orc ** 2))) if g_orc.size else 0.0
-    bound = 1e-3 * np.maximum(np.abs(g_orc), 0.1 * rms)
-    viol = float(np.mean(diff > bound)) if diff.size else 0.0
-    return rel_l2, viol, float(diff.max()) if diff.size else 0.0
+    n = max(diff.size, 1)
+    return {"rel_l2": rel_l2,
+            "viol": float(np.sum(diff > 1e-3 * np.maximum(np.abs(g_orc), 1e-2 * rms))) / n,
+            "viol_coarse": float(np.sum(diff > 1e-3 * np.maximum(np.abs(g_orc), 1e-1 * rms))) / n,
+            "max_abs": float(diff.max()) if diff.size else 0.0, "mean_abs": float(diff.mean()) if diff.size else 0.0,
+            "rms": rms}
+
+
+def fmt_grad_report(rep):
+    return {k: f"rel {v['rel_l2']:.2e} viol {v['viol']:.1e}/{v['viol_coarse']:.1e} max {v['max_abs']:.2e} "
+               f"mean {v['mean_abs']:.2e} rms {v['rms']:.2e}" for k, v in rep.items()}
+
+
+# Relative error scales of the MLP pre-activations per layer, as inputs to the
+# decision check: FP32 matrix cores accumulate at most 128 products (a few
+# units of 2^-24 of sum |W x|); BF16 matrix cores see inputs rounded to BF16
+# (2^-9 each) and accumulate in FP32.
+MLP_REL_ERR = {"f32": 4e-6, "bf16": 2.0 ** -8}
+
+
+def check_forced_decisions(orc, gpu_cells, gpu_masks, gpu_feats, gpu_depths, cam, level_scales, weights, form,
+                           label="", feat_tol=1e-5):
+    """Check the decisions the kernel reported against the FP64 oracle's own.
+
+    orc must come from oracle.render(..., want_decisions=True) on the same
+    pixels (decisive pixels only are checked; there the ids agree).
+      * Hash cell per slot, level and axis: equal to floor(s_l x) of the
+        oracle's FP64 point x = o + D d, unless that coordinate lies within
+        its FP32 error bound of a cell face (then off by one towards it).
+        Bound (two times): |s_l D d_a| |D_gpu - D| / D (the depth the kernel
+        was given) + 4e-7 s_l D |d| (ray direction) + 2e-7 (|s_l D d_a| + 1)
+        (FP32 rounding of the camera-relative coordinate) + 1e-6.
+      * Features z: within feat_tol max(1, max|z|) of the oracle's FP64 ones.
+      * ReLU bit per hidden unit: equal to the sign of the FP64 pre-activation
+        of the natural network, unless |pre| is within two times its error
+        bound: layer 1 e1 = |W1| |z_gpu - z| + r |W1| |z|, layer 2
+        e2 = |W2| (e1 + r |h1|) + r |W2| |h1| (r = MLP_REL_ERR[form]).
+    Returns the counts; raises AssertionError on a decision outside its band."""
+    from oracle.mlp import hidden_preactivations
+
+    dec = (orc.margin > SAFETY)
+    K = orc.ids.shape[1]
+    has = (orc.ids >= 0) & dec[:, None]
+    stats = {"slots": int(has.sum())}
+    if stats["slots"] == 0:
+        return stats
+    L = orc.lattice.shape[2]
+    m = np.asarray(cam.world_to_cam, dtype=np.float64)
+    o_world = -m[:, :3].T @ m[:, 3]
+    s = np.asarray(level_scales, dtype=np.float64)
+    lat = orc.lattice[has]                                   # [n, L, 3]
+    D = orc.depths[has]                                      # [n]
+    Dg = np.asarray(gpu_depths, dtype=np.float64)[has]
+    cells = np.asarray(gpu_cells, dtype=np.int64)[has]       # [n, L, 3]
+    nat = np.floor(lat).astype(np.int64)
+    sDd = lat - s[None, :, None] * o_world[None, None, :]
+    sD = s[None, :] * D[:, None]                             # [n, L]
+    dnorm = np.linalg.norm(sDd, axis=2) / sD
+    bound = 2.0 * (np.abs(sDd) * (np.abs(Dg - D) / D)[:, None, None] + 4e-7 * (sD * dnorm)[:, :, None]
+                   + 2e-7 * (np.abs(sDd) + 1.0) + 1e-6)
+    diff = cells != nat
+    up_ok = (cells == nat + 1) & (nat + 1 - lat <= bound)
+    dn_ok = (cells == nat - 1) & (lat - nat <= bound)
+    bad = diff & ~(up_ok | dn_ok)
+    stats.update(cell_coords=int(diff.size), cell_diff=int(diff.sum()), cell_bad=int(bad.sum()),
+                 cell_near_face=int((np.minimum(lat - nat, nat + 1 - lat) <= bound).sum()))
+    if bad.any():
+        i = np.argwhere(bad)[:3]
+        raise AssertionError(f"{label}: hash cell differs from floor(s_l x) away from a face at "
+                             f"{[(tuple(x), float(lat[tuple(x)]), int(cells[tuple(x)]), float(bound[tuple(x)])) for x in i]}")
+    z = orc.features[has]
+    zg = np.asarray(gpu_feats, dtype=np.float64)[has]
+    ferr = np.abs(zg - z)
+    stats["feat_max_err"] = float(ferr.max())
+    tol = feat_tol * max(1.0, float(np.abs(z).max()))
+    assert stats["feat_max_err"] <= tol, f"{label}: feature error {stats['feat_max_err']:.3e} > {tol:.1e}"
+    r = MLP_REL_ERR[form]
+    W = [np.asarray(w.detach().cpu().double().numpy() if hasattr(w, "detach") else w, dtype=np.float64)
+         for w in weights]
+    pre1, pre2 = hidden_preactivations(z, W)
+    h1 = np.maximum(pre1, 0.0)
+    e1 = ferr @ np.abs(W[0]).T + r * (np.abs(z) @ np.abs(W[0]).T)
+    e2 = (e1 + r * h1) @ np.abs(W[1]).T + r * (h1 @ np.abs(W[1]).T)
+    H = W[0].shape[0]
+    words = np.asarray(gpu_masks).astype(np.uint32)[has].reshape(-1, 2, H // 32)
+    bits = ((words[:, :, :, None] >> np.arange(32, dtype=np.uint32)) & 1).reshape(-1, 2, H).astype(bool)
+    out = {}
+    for li, (pre, e) in enumerate(((pre1, e1), (pre2, e2))):
+        nat_bit = pre > 0
+        d = bits[:, li] != nat_bit
+        band = np.abs(pre) <= 2.0 * e
+        out[li] = (int(d.sum()), int((d & ~band).sum()), int(band.sum()))
+        if (d & ~band).any():
+            i = np.argwhere(d & ~band)[:3]
+            raise AssertionError(f"{label}: ReLU layer {li + 1} bit differs from the FP64 sign outside its error "
+                                 f"band at {[(tuple(x), float(pre[tuple(x)]), float(e[tuple(x)])) for x in i]}")
+    stats.update(relu_units=int(pre1.size + pre2.size), relu_diff=out[0][0] + out[1][0],
+                 relu_band=out[0][2] + out[1][2])
+    return stats

@@ -67,6 +67,6 @@ def test_struct_sizes_match_the_header():
     assert ctypes.sizeof(L.NxCamera) == 12 * 8 + 5 * 8 + 2 * 4
     assert ctypes.sizeof(L.NxHashGrid) == 32
     assert ctypes.sizeof(L.NxMLP) == 48
-    assert ctypes.sizeof(L.NxFwdOut) == 11 * 8
+    assert ctypes.sizeof(L.NxFwdOut) == 12 * 8
     assert ctypes.sizeof(L.NxSurfels) == 7 * 8
-    assert ctypes.sizeof(L.NxGrads) == 10 * 8
+    assert ctypes.sizeof(L.NxGrads) == 12 * 8

@@ -1,0 +1,137 @@
+"""The synchronisation-free forward (nx_render_forward_async) and a captured
+HIP graph of a whole multi-camera training step (needs an MI355X).
+
+  * the async forward with a sufficient bound equals nx_render_forward bit
+    for bit, and nx_instance_counts returns the synced call's counts;
+  * a bound below the true count is reported by nx_instance_counts (the
+    pairs past it are dropped, every kernel stays in bounds);
+  * forward (async) + image-loss gradient + gradient zeroing + backward of
+    several cameras of mixed resolution, captured once in a HIP graph and
+    replayed several times with eager work in between: every replay's
+    outputs equal the eager call's bit for bit, and its gradients equal the
+    eager gradients up to float32 atomic summation order.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import scenes
+from tests.gpu_helpers import device_inputs, log
+
+pytestmark = pytest.mark.gpu
+
+FWD_FIELDS = ("image", "plain", "ids", "weights", "depths", "t_final", "tex", "n_iter")
+
+
+@pytest.fixture(scope="module")
+def nx():
+    import paper_2512_13796_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def views():
+    wl = scenes.make_workload(4, seed=1, n_surfels=30_000)
+    return wl, wl.cameras[:4]
+
+
+def _zero_grads(surf, table, weights):
+    z = lambda t: torch.zeros(t.shape, device=t.device, dtype=torch.float32)
+    return {"means": z(surf[0]), "quats": z(surf[1]), "scales": z(surf[2]), "opacities": z(surf[3]),
+            "gammas": z(surf[4]), "colors": z(surf[5]), "table": z(table), "mlp": [z(w) for w in weights]}
+
+
+def test_async_forward_equals_synced_forward(nx, views):
+    wl, cams = views
+    surf, table, weights = device_inputs(wl)
+    ctx = nx.Context(wl.K, table.dtype, weights[0].dtype)
+    ref = nx.render_forward(ctx, surf, cams, table, wl.grid.level_scales, weights)
+    cap = max(ref.n_instances_cam) + 1000
+    res = nx.render_forward(ctx, surf, cams, table, wl.grid.level_scales, weights, max_instances=cap)
+    counts = nx.instance_counts(ctx, wl.scene.n, res)
+    log("async forward: counts", counts, "synced", ref.n_instances_cam, "bound", cap)
+    assert counts == ref.n_instances_cam
+    for nm in FWD_FIELDS:
+        assert torch.equal(getattr(res, nm), getattr(ref, nm)), nm
+    # the backward reads the async forward's layout
+    P = ref.image.shape[0]
+    gi = torch.randn(P, 3, device="cuda", generator=torch.Generator(device="cuda").manual_seed(5)) * 1e-3
+    ga, gb = _zero_grads(surf, table, weights), _zero_grads(surf, table, weights)
+    nx.render_backward(ctx, surf, ref, table, wl.grid.level_scales, weights, gi, None, None, ga)
+    nx.render_backward(ctx, surf, res, table, wl.grid.level_scales, weights, gi, None, None, gb)
+    torch.cuda.synchronize()
+    for nm in ("means", "quats", "scales", "opacities", "gammas", "colors", "table"):
+        a, b = ga[nm].double(), gb[nm].double()
+        assert float((a - b).norm()) <= 1e-5 * max(float(a.norm()), 1e-30), nm
+
+
+def test_async_forward_reports_overflow(nx, views):
+    wl, cams = views
+    surf, table, weights = device_inputs(wl)
+    ctx = nx.Context(wl.K, table.dtype, weights[0].dtype)
+    ref = nx.render_forward(ctx, surf, cams[0], table, wl.grid.level_scales, weights)
+    cap = ref.n_instances // 3
+    res = nx.render_forward(ctx, surf, cams[0], table, wl.grid.level_scales, weights, max_instances=cap)
+    counts = nx.instance_counts(ctx, wl.scene.n, res)
+    torch.cuda.synchronize()
+    log("overflow: true count", counts, "bound", cap)
+    assert counts == [ref.n_instances] and counts[0] > cap
+    assert bool(torch.isfinite(res.image).all())
+
+
+def test_captured_training_step_replays_exactly(nx, views):
+    wl, cams = views
+    surf, table, weights = device_inputs(wl)
+    ctx = nx.Context(wl.K, table.dtype, weights[0].dtype)
+    P = sum(c.width * c.height for c in cams)
+    target = torch.rand(P, 3, device="cuda", generator=torch.Generator(device="cuda").manual_seed(7))
+    ref = nx.render_forward(ctx, surf, cams, table, wl.grid.level_scales, weights)
+    cap = max(ref.n_instances_cam) + 4096
+    size = nx.workspace_size(ctx, wl.scene.n, cams, cap)
+    ws = torch.empty(size, device="cuda", dtype=torch.uint8)
+    grads = _zero_grads(surf, table, weights)
+    scale = 2.0 / (3.0 * P)
+    out = {}
+
+    def step():
+        res = nx.render_forward(ctx, surf, cams, table, wl.grid.level_scales, weights, workspace=ws,
+                                max_instances=cap)
+        g = (res.image - target).mul_(scale)
+        for k, t in grads.items():
+            for x in (t if k == "mlp" else [t]):
+                x.zero_()
+        nx.render_backward(ctx, surf, res, table, wl.grid.level_scales, weights, g, None, None, grads)
+        out["res"] = res
+
+    # eager reference (this also creates the backward's side streams before capture)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    eager = {nm: getattr(out["res"], nm).clone() for nm in FWD_FIELDS}
+    eager_g = {k: ([x.clone() for x in v] if k == "mlp" else v.clone()) for k, v in grads.items()}
+    assert nx.instance_counts(ctx, wl.scene.n, out["res"]) == ref.n_instances_cam
+
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    res_g = out["res"]
+    for rep in range(3):
+        # eager work between replays overwrites the gradient buffers
+        for k, t in grads.items():
+            for x in (t if k == "mlp" else [t]):
+                x.fill_(float(rep + 1))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for nm in FWD_FIELDS:
+            assert torch.equal(getattr(res_g, nm), eager[nm]), f"replay {rep}: {nm}"
+        for k, v in grads.items():
+            for a, b in zip(v if k == "mlp" else [v], eager_g[k] if k == "mlp" else [eager_g[k]]):
+                d = float((a.double() - b.double()).norm())
+                assert d <= 1e-5 * max(float(b.double().norm()), 1e-30), f"replay {rep}: {k} differs by {d:.3e}"
+    log("graph replays match the eager step:", [c.width * c.height for c in cams], "pixels per camera")

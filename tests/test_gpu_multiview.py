@@ -18,7 +18,8 @@ import torch
 
 import oracle
 import scenes
-from tests.gpu_helpers import SAFETY, compare_forward, device_inputs, grad_errors, log, to_np
+from tests.gpu_helpers import (SAFETY, check_forced_decisions, compare_forward, device_inputs, fmt_grad_report,
+                               grad_errors, log, to_np)
 from tests.test_gpu_parity import _sample_pixels
 
 pytestmark = pytest.mark.gpu
@@ -109,6 +110,10 @@ def test_joint_call_against_oracle(nx, setup):
         glob = pix + off[i]
         cells = res.cells[torch.from_numpy(glob).cuda()].cpu().numpy()
         masks = res.relu_masks[torch.from_numpy(glob).cuda()].cpu().numpy().view(np.uint32)
+        feats = res.features[torch.from_numpy(glob).cuda()].cpu().numpy()
+        nat = oracle.render(wl.scene, cam, grid, mlp, K, pixels=pix, want_decisions=True)
+        log(f"cam {i} decisions:", check_forced_decisions(nat, cells, masks, feats, gpu["depths"][glob], cam,
+                                                          wl.grid.level_scales, weights, "f32", label=f"cam {i}"))
         orc = oracle.render(wl.scene, cam, grid, mlp, K, pixels=pix, force_cells=cells, force_relu=masks)
         sub = {k: v[off[i]:off[i + 1]] for k, v in gpu.items()}
         stats = compare_forward(sub, orc, pix, K, label=f"cam {i}")
@@ -132,16 +137,13 @@ def test_joint_call_against_oracle(nx, setup):
                     total[k] = [a + b for a, b in zip(total[k], v)]
                 else:
                     total[k] = total[k] + v
-    report = {}
-    for nm in ("means", "quats", "scales", "opacities", "gammas", "colors", "table"):
-        rel, viol, _ = grad_errors(grads[nm].cpu().numpy(), total[nm])
-        report[nm] = (rel, viol)
+    report = {nm: grad_errors(grads[nm].cpu().numpy(), total[nm])
+              for nm in ("means", "quats", "scales", "opacities", "gammas", "colors", "table")}
     for i in range(3):
-        rel, viol, _ = grad_errors(grads["mlp"][i].cpu().numpy(), total["mlp"][i])
-        report[f"mlp{i}"] = (rel, viol)
-    log("multi-view grads (relL2, frac over bound):", {k: (f"{a:.2e}", f"{b:.1e}") for k, (a, b) in report.items()})
-    for k, (rel, viol) in report.items():
-        assert rel <= 1e-3 and viol <= 5e-3, f"{k}: rel {rel:.2e} viol {viol:.2e}"
+        report[f"mlp{i}"] = grad_errors(grads["mlp"][i].cpu().numpy(), total["mlp"][i])
+    log("multi-view grads:", fmt_grad_report(report))
+    for k, r in report.items():
+        assert r["rel_l2"] <= 1e-3 and r["viol_coarse"] <= 5e-3, f"{k}: {fmt_grad_report({k: r})}"
 
 
 def test_full_size_all_cameras_against_oracle(nx):
@@ -168,6 +170,11 @@ def test_full_size_all_cameras_against_oracle(nx):
         glob = pix + off[i]
         cells = res.cells[torch.from_numpy(glob).cuda()].cpu().numpy()
         masks = res.relu_masks[torch.from_numpy(glob).cuda()].cpu().numpy().view(np.uint32)
+        feats = res.features[torch.from_numpy(glob).cuda()].cpu().numpy()
+        nat = oracle.render(wl.scene, cam, grid, mlp, K, pixels=pix, want_decisions=True)
+        log(f"full-size cam {i} decisions:",
+            check_forced_decisions(nat, cells, masks, feats, gpu["depths"][glob], cam, wl.grid.level_scales, weights,
+                                   "f32", label=f"full-size cam {i}"))
         orc = oracle.render(wl.scene, cam, grid, mlp, K, pixels=pix, force_cells=cells, force_relu=masks)
         sub = {k: v[off[i]:off[i + 1]] for k, v in gpu.items()}
         # the fraction of pixels within FP32 error of a decision is checked over all cameras below
@@ -192,14 +199,10 @@ def test_full_size_all_cameras_against_oracle(nx):
         else:
             for k, v in og.items():
                 total[k] = [a + b for a, b in zip(total[k], v)] if k == "mlp" else total[k] + v
-    report = {}
-    for nm in ("means", "quats", "scales", "opacities", "gammas", "colors", "table"):
-        rel, viol, _ = grad_errors(grads[nm].cpu().numpy(), total[nm])
-        report[nm] = (rel, viol)
+    report = {nm: grad_errors(grads[nm].cpu().numpy(), total[nm])
+              for nm in ("means", "quats", "scales", "opacities", "gammas", "colors", "table")}
     for i in range(3):
-        rel, viol, _ = grad_errors(grads["mlp"][i].cpu().numpy(), total["mlp"][i])
-        report[f"mlp{i}"] = (rel, viol)
-    log("full-size multi-view grads (relL2, frac over bound):",
-        {k: (f"{a:.2e}", f"{b:.1e}") for k, (a, b) in report.items()})
-    for k, (rel, viol) in report.items():
-        assert rel <= 1e-3 and viol <= 5e-3, f"{k}: rel {rel:.2e} viol {viol:.2e}"
+        report[f"mlp{i}"] = grad_errors(grads["mlp"][i].cpu().numpy(), total["mlp"][i])
+    log("full-size multi-view grads:", fmt_grad_report(report))
+    for k, r in report.items():
+        assert r["rel_l2"] <= 1e-3 and r["viol_coarse"] <= 5e-3, f"{k}: {fmt_grad_report({k: r})}"

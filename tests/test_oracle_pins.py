@@ -323,6 +323,30 @@ def test_rigid_motion_of_scene_and_camera_changes_nothing():
             np.testing.assert_allclose(a.image, c.image, atol=1e-11)
 
 
+def test_blended_error_closed_forms():
+    """Blended errors (supplementary, Densification): per surfel the sum over
+    pixels of its blending weight times the pixel's error. For two facing
+    surfels w1 = alpha1 and w2 = alpha2 (1 - alpha1) per pixel; with a unit
+    error everywhere the surfels' errors and the pixels' final transmittance
+    add up to the number of pixels (sum_i w_i + T_final = 1)."""
+    cam = identity_camera(8, 8, 10.0)
+    sc = scene_from([[0, 0, 2.0], [0, 0, 3.0]], [[1, 0, 0, 0]] * 2, [[1.0, 1.0], [1.5, 1.5]], [0.6, 0.7],
+                    [[1, 1]] * 2, [[1, 0, 0], [0, 1, 0]])
+    rng = np.random.default_rng(35)
+    E = rng.uniform(0.0, 2.0, 64)
+    out = oracle.render(sc, cam, random_grid(rng), random_mlp(rng, [4, 8, 8, 3]), K=1, pixel_error=E)
+    py, px = np.meshgrid(np.arange(8), np.arange(8), indexing="ij")
+    dx = ((px + 0.5 - 4) / 10.0).reshape(-1)
+    dy = ((py + 0.5 - 4) / 10.0).reshape(-1)
+    a1 = 0.6 * np.exp(-0.5 * ((2 * dx) ** 2 + (2 * dy) ** 2))
+    a2 = 0.7 * np.exp(-0.5 * ((3 * dx / 1.5) ** 2 + (3 * dy / 1.5) ** 2))
+    np.testing.assert_allclose(out.blended_error, [(a1 * E).sum(), (a2 * (1 - a1) * E).sum()], rtol=1e-13)
+    wl = scenes.make_workload(1, seed=4, width=40, height=30)
+    ones = oracle.render(wl.scene, wl.cameras[0], wl.grid, wl.mlp, 4, pixel_error=np.ones(1200))
+    assert (ones.blended_error > 0).sum() > 50
+    np.testing.assert_allclose(ones.blended_error.sum() + ones.t_final.sum(), 1200.0, rtol=1e-12)
+
+
 # ---------------------------------------------------------------- kernel limits
 
 def test_kernel_gamma_one_is_gaussian():
