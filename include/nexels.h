@@ -20,7 +20,8 @@
  *   - "device" pointers must point to GPU memory of the current HIP device;
  *     "host" pointers to CPU memory. All device buffers are owned by the
  *     caller; the library allocates no device memory except a small pinned
- *     host word per context.
+ *     host word per context (and the fixed scratch array of
+ *     nx_render_forward_noalloc, part of the loaded code object).
  *   - Arrays are dense and row-major; [a,b] means a rows of b elements.
  *   - Work is enqueued on the HIP stream passed as `stream` (NULL = the null
  *     stream). nx_render_forward synchronises that stream once per camera to
@@ -208,6 +209,28 @@ int nx_render_forward(nx_ctx *ctx, const nx_surfels *surfels, const nx_camera *c
 int nx_render_forward_async(nx_ctx *ctx, const nx_surfels *surfels, const nx_camera *cams, int32_t n_cams,
                             const nx_hashgrid *grid, const nx_mlp *mlp, nx_fwd_out *out, int64_t max_instances,
                             void *workspace, size_t workspace_bytes, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * nx_render_forward_async without a workspace argument. The call's
+ * intermediate arrays live in a fixed array of NX_NOALLOC_SCRATCH_BYTES
+ * inside the library (one per device, held from the library's first use on
+ * that device until the process ends); the call allocates nothing and does
+ * not synchronise. The caller still passes every output. Limit: the
+ * forward-only layout for n_cams cameras at max_instances (surfel, tile)
+ * pairs each (about 124 bytes per surfel plus 16 per pair, per camera) must
+ * fit in the array, else NX_ERR_UNSUPPORTED with the size needed. Outputs
+ * are bit-identical to nx_render_forward_async's (same overflow rule for a
+ * camera with more than max_instances pairs); out->n_instances[c] receives
+ * max_instances. Every call on one device shares that device's array and
+ * leaves its contents behind: calls that overlap on one device (two
+ * streams, two threads) race, and the array cannot serve a later
+ * nx_render_backward (render with a workspace for training). Per-phase
+ * timing records nothing during this call. */
+#define NX_NOALLOC_SCRATCH_BYTES (64u << 20)
+int nx_render_forward_noalloc(nx_ctx *ctx, const nx_surfels *surfels, const nx_camera *cams, int32_t n_cams,
+                              const nx_hashgrid *grid, const nx_mlp *mlp, nx_fwd_out *out, int64_t max_instances,
+                              void *stream);
 
 /* True (surfel, tile) pair counts per camera of the last forward into
  * `workspace`, whose layout n_instances (as that forward left it in

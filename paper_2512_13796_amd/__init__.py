@@ -9,7 +9,7 @@ from . import _lib
 _lib.load()
 
 from .render import (Context, ForwardResult, RenderFunction, camera_struct, instance_counts,  # noqa: E402,F401
-                     render, render_backward, render_forward, workspace_size)
+                     render, render_backward, render_forward, render_forward_noalloc, workspace_size)
 
 __all__ = ["Context", "ForwardResult", "RenderFunction", "camera_struct", "instance_counts", "render",
-           "render_backward", "render_forward", "workspace_size"]
+           "render_backward", "render_forward", "render_forward_noalloc", "workspace_size"]

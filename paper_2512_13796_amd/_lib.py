@@ -79,6 +79,9 @@ SIGNATURES = {
     "nx_render_forward_async": ([c_void_p, ctypes.POINTER(NxSurfels), ctypes.POINTER(NxCamera), ctypes.c_int32,
                                  ctypes.POINTER(NxHashGrid), ctypes.POINTER(NxMLP), ctypes.POINTER(NxFwdOut),
                                  ctypes.c_int64, c_void_p, ctypes.c_size_t, c_void_p], ctypes.c_int),
+    "nx_render_forward_noalloc": ([c_void_p, ctypes.POINTER(NxSurfels), ctypes.POINTER(NxCamera), ctypes.c_int32,
+                                   ctypes.POINTER(NxHashGrid), ctypes.POINTER(NxMLP), ctypes.POINTER(NxFwdOut),
+                                   ctypes.c_int64, c_void_p], ctypes.c_int),
     "nx_instance_counts": ([c_void_p, ctypes.c_int64, ctypes.POINTER(NxCamera), ctypes.c_int32,
                             ctypes.POINTER(ctypes.c_int64), c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int64),
                             c_void_p], ctypes.c_int),

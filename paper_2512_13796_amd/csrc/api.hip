@@ -3,6 +3,7 @@
 #include <math.h>
 #include <stdio.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -67,7 +68,9 @@ struct Layout {
   size_t total;
 };
 
-Layout make_layout(int64_t n, const nx::CamDev& cd, int K, int64_t n_inst) {
+// fwd_only: leave out the arrays only the backward uses (record gradients,
+// depth and feature gradients, weight operands).
+Layout make_layout(int64_t n, const nx::CamDev& cd, int K, int64_t n_inst, bool fwd_only = false) {
   Layout L{};
   const int64_t n_pix = (int64_t)cd.width * cd.height;
   const int n_tiles = cd.ntx * cd.nty;
@@ -89,10 +92,10 @@ Layout make_layout(int64_t n, const nx::CamDev& cd, int K, int64_t n_inst) {
   L.offsets = take(4 * (nn + 1));
   L.scan_blocks = take(4 * nx::scan_block_words((int64_t)nn));
   L.tile_ranges = take(8 * (size_t)n_tiles);
-  L.rec_grad = take(sizeof(float) * nx::kRecGrad * nn);
-  L.grad_depth = take(sizeof(float) * (size_t)(n_pix * (K > 0 ? K : 1)));
-  L.feat_grad = take(sizeof(float2) * (size_t)nx::feat_grad_elems(cd.width, cd.height, K));
-  L.weight_ops = take(K > 0 ? nx::kWeightOperandBytes : 0);
+  L.rec_grad = take(fwd_only ? 0 : sizeof(float) * nx::kRecGrad * nn);
+  L.grad_depth = take(fwd_only ? 0 : sizeof(float) * (size_t)(n_pix * (K > 0 ? K : 1)));
+  L.feat_grad = take(fwd_only ? 0 : sizeof(float2) * (size_t)nx::feat_grad_elems(cd.width, cd.height, K));
+  L.weight_ops = take(fwd_only || K == 0 ? 0 : nx::kWeightOperandBytes);
   const int64_t ni = n_inst > 0 ? n_inst : 1;
   const int64_t hist_n = ni > (int64_t)nn ? ni : (int64_t)nn;
   L.hist = take(4 * nx::radix_hist_words(hist_n));
@@ -381,12 +384,12 @@ int forward_prefix(nx_ctx* ctx, const nx_surfels* surfels, const nx::CamDev& cd,
 // true count at offsets[n]).
 int forward_one(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera& cam, const nx_hashgrid* grid,
                 const nx_mlp* mlp, const nx_fwd_out* out, void* workspace, size_t workspace_bytes, size_t* need,
-                int64_t* n_inst_out, hipStream_t s, int64_t cap = -1) {
+                int64_t* n_inst_out, hipStream_t s, int64_t cap = -1, bool fwd_only = false) {
   const int K = ctx->K;
   const nx::CamDev cd = make_cam(cam);
   const int n_tiles = cd.ntx * cd.nty;
   const int64_t n = surfels->n;
-  const Layout L0 = make_layout(n, cd, K, cap >= 0 ? cap : 0);
+  const Layout L0 = make_layout(n, cd, K, cap >= 0 ? cap : 0, fwd_only);
   *need = L0.total;
   if (!workspace || workspace_bytes < L0.total) return fail(NX_ERR_WORKSPACE, "workspace too small");
   void* ws = workspace;
@@ -406,7 +409,7 @@ int forward_one(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera& cam, co
     n_inst = cap;
     n_dev = offsets + n;
   }
-  const Layout L = make_layout(n, cd, K, n_inst);
+  const Layout L = make_layout(n, cd, K, n_inst, fwd_only);
   *n_inst_out = n_inst;
   *need = L.total;
   if (workspace_bytes < L.total) return fail(NX_ERR_WORKSPACE, "workspace too small for the tile instances");
@@ -504,6 +507,43 @@ int backward_one(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera& cam, c
   return NX_OK;
 }
 
+// Workspace of nx_render_forward_noalloc: a fixed device array, so that the
+// call needs no allocation. Each device that loads the library holds its own
+// copy until the process ends. In host code its name is not a device
+// address: kernels and copies get the address hipGetSymbolAddress returns
+// for the current device, kept per device below.
+__device__ __align__(256) unsigned char scratch[NX_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch array's device address on the current device (looked up once
+// per device).
+int scratch_address(void** out) {
+  int dev = -1;
+  NX_CHECK_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(NX_ERR_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    NX_CHECK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(NX_ERR_HIP, "hipGetSymbolAddress returned a null address for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return NX_OK;
+}
+
+// Turns per-phase timing off for the lifetime of the guard (event creation
+// is an allocation the no-allocation entry point must not make).
+struct TimingOff {
+  nx_ctx* c;
+  bool was;
+  explicit TimingOff(nx_ctx* ctx) : c(ctx), was(ctx->timing) { c->timing = false; }
+  ~TimingOff() { c->timing = was; }
+};
+
 }  // namespace
 
 extern "C" {
@@ -532,6 +572,14 @@ int nx_create(nx_ctx** out, int32_t K, int32_t tile, nx_dtype feat_dtype, nx_dty
   if (e != hipSuccess) {
     delete c;
     return fail(NX_ERR_HIP, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+  }
+  // set-up of the no-allocation entry point's scratch on the current device
+  void* sp = nullptr;
+  const int rs = scratch_address(&sp);
+  if (rs != NX_OK) {
+    (void)hipHostFree(c->pinned);
+    delete c;
+    return rs;
   }
   *out = c;
   g_last_error.clear();
@@ -706,6 +754,50 @@ int nx_render_forward_async(nx_ctx* ctx, const nx_surfels* surfels, const nx_cam
     int64_t n_inst = -1;
     r = forward_one(ctx, surfels, cams[c], grid, mlp, &oc, at<char>(workspace, off), workspace_bytes - off, &need,
                     &n_inst, s, max_instances);
+    if (r != NX_OK) return r;
+    out->n_instances[c] = max_instances;
+    off += need;
+    pix += (int64_t)cams[c].width * cams[c].height;
+  }
+  g_last_error.clear();
+  return NX_OK;
+}
+
+int nx_render_forward_noalloc(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* cams, int32_t n_cams,
+                              const nx_hashgrid* grid, const nx_mlp* mlp, nx_fwd_out* out, int64_t max_instances,
+                              void* stream) {
+  int r;
+  if ((r = check_ctx(ctx)) != NX_OK) return r;
+  if ((r = check_surfels(surfels)) != NX_OK) return r;
+  if ((r = check_camera(cams, n_cams)) != NX_OK) return r;
+  if ((r = check_grid_mlp(ctx, grid, mlp)) != NX_OK) return r;
+  if (!out || !out->image || !out->plain || !out->t_final || !out->n_iter || !out->n_instances)
+    return fail(NX_ERR_INVALID, "an output pointer is NULL");
+  if (ctx->K > 0 && (!out->ids || !out->weights || !out->depths || !out->tex))
+    return fail(NX_ERR_INVALID, "an output pointer is NULL");
+  if (max_instances < 1 || max_instances > 0xFFFFFFFFll)
+    return fail(NX_ERR_INVALID, "max_instances must be in [1, 2^32 - 1]");
+  size_t total = 0;
+  for (int32_t c = 0; c < n_cams; ++c)
+    total += make_layout(surfels->n, make_cam(cams[c]), ctx->K, max_instances, true).total;
+  if (total > (size_t)NX_NOALLOC_SCRATCH_BYTES)
+    return fail(NX_ERR_UNSUPPORTED, "nx_render_forward_noalloc needs " + std::to_string(total) +
+                                        " bytes of scratch for these sizes; the library holds " +
+                                        std::to_string((size_t)NX_NOALLOC_SCRATCH_BYTES) +
+                                        " (use nx_render_forward_async with a workspace)");
+  void* ws = nullptr;
+  if ((r = scratch_address(&ws)) != NX_OK) return r;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  NX_CHECK_HIP(hipGetLastError());
+  TimingOff no_events(ctx);
+  size_t off = 0;
+  int64_t pix = 0;
+  for (int32_t c = 0; c < n_cams; ++c) {
+    const nx_fwd_out oc = camera_slice(ctx, grid, mlp, *out, pix);
+    size_t need = 0;
+    int64_t n_inst = -1;
+    r = forward_one(ctx, surfels, cams[c], grid, mlp, &oc, at<char>(ws, off), (size_t)NX_NOALLOC_SCRATCH_BYTES - off,
+                    &need, &n_inst, s, max_instances, true);
     if (r != NX_OK) return r;
     out->n_instances[c] = max_instances;
     off += need;

@@ -252,6 +252,38 @@ def render_forward(ctx: Context, surfels, cam, table=None, level_scales=None, we
     return res
 
 
+def render_forward_noalloc(ctx: Context, surfels, cam, table=None, level_scales=None, weights=None,
+                           max_instances=1, near=0.2) -> ForwardResult:
+    """nx_render_forward_noalloc: the forward without a workspace argument (the
+    library's fixed scratch array holds the intermediates; nothing is
+    allocated inside the call and the host does not wait). The output tensors
+    are allocated here, before the call. The result has no workspace, so it
+    cannot feed render_backward."""
+    device = surfels[0].device
+    s, g, m, keep = _structs(ctx, surfels, table, level_scales, weights, device)
+    cams = _cameras(cam)
+    cs = (L.NxCamera * len(cams))(*[camera_struct(c, near) for c in cams])
+    P = sum(c.width * c.height for c in cams)
+    K = ctx.K
+    f32 = dict(device=device, dtype=torch.float32)
+    res = ForwardResult(
+        image=torch.empty(P, 3, **f32), plain=torch.empty(P, 3, **f32),
+        ids=torch.empty(P, max(K, 1), device=device, dtype=torch.int32),
+        weights=torch.empty(P, max(K, 1), **f32), depths=torch.empty(P, max(K, 1), **f32),
+        t_final=torch.empty(P, **f32), tex=torch.empty(P, max(K, 1), 3, **f32),
+        n_iter=torch.empty(P, device=device, dtype=torch.int32), n_instances=-1, workspace=None, camera=cam,
+        near=near)
+    n_inst = (ctypes.c_int64 * len(cams))()
+    out = L.NxFwdOut(_ptr(res.image), _ptr(res.plain), _ptr(res.ids), _ptr(res.weights), _ptr(res.depths),
+                     _ptr(res.t_final), _ptr(res.tex), _ptr(res.n_iter), None, None, None, n_inst)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+    L.check(ctx.lib.nx_render_forward_noalloc(ctx.handle, ctypes.byref(s), cs, len(cams), ctypes.byref(g),
+                                              ctypes.byref(m), ctypes.byref(out), int(max_instances), stream))
+    res.n_instances_cam = [int(v) for v in n_inst]
+    del keep
+    return res
+
+
 def render_backward(ctx: Context, surfels, fwd: ForwardResult, table=None, level_scales=None, weights=None,
                     grad_image=None, grad_weights=None, grad_tex=None, grads=None, pixel_error=None):
     """Accumulate gradients into ``grads`` (dict of float32 tensors; missing keys are skipped).
