@@ -19,6 +19,13 @@ What it computes (paper: Nexels, arXiv 2512.13796):
                  eq. downweighting; supplementary Implementation Details).
   * mlp.py       bias-free ReLU MLP with a sigmoid head (Results,
                  implementation details; supplementary Anti-aliasing).
+  * sh.py        degree-3 real spherical harmonics and the view-dependent
+                 colour decode (Representation, Appearance).
+  * losses.py    the auxiliary losses L_alpha, L_texture, L_opacity, L_grid and
+                 their gradients (Optimization, Losses).
+  * adc.py       farthest point sampling, error-weighted split selection, the
+                 split geometry and pruning (supplementary, Adaptive Density
+                 Control).
   * render.py    collection pass (eq. composite, eq. notexture, K-buffer by
                  weight), texturing pass (eq. texture) and the final
                  composite (eq. final), untiled, with a per-pixel brute-force

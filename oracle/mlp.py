@@ -1,8 +1,9 @@
 """The texture decoder MLP in FP64 (oracle).
 
 Paper, Results (implementation): the MLP has hidden layers without bias
-terms and ReLU activations. The workloads used here have a 3-channel RGB
-head; a sigmoid maps it into (0, 1). Weights are [out, in] matrices and are
+terms and ReLU activations. The RGB workloads have a 3-channel head that a
+sigmoid maps into (0, 1); the spherical-harmonics appearance (Representation,
+Appearance) has a 48-value linear head decoded by oracle.sh. Weights are [out, in] matrices and are
 converted exactly from their storage dtype to float64.
 """
 from __future__ import annotations
@@ -19,8 +20,9 @@ def unpack_masks(words, hidden, n_hidden_layers):
     return [torch.from_numpy(bits[:, i].astype(np.float64)) for i in range(n_hidden_layers)]
 
 
-def mlp_forward(z, weights, relu_masks=None):
-    """sigmoid(W_n ... ReLU(W_1 z)), no biases.
+def mlp_forward(z, weights, relu_masks=None, head="sigmoid"):
+    """sigmoid(W_n ... ReLU(W_1 z)), no biases (head="linear": no sigmoid, for the
+    spherical-harmonics head, whose coefficients are decoded by the caller).
 
     relu_masks (optional, per hidden layer [S, hidden] 0/1) replaces the ReLU
     decision h > 0 by a given one: the layer output is pre * mask. At a
@@ -32,7 +34,7 @@ def mlp_forward(z, weights, relu_masks=None):
     for i, w in enumerate(weights):
         h = h @ w.t()
         if i == last:
-            h = torch.sigmoid(h)
+            h = torch.sigmoid(h) if head == "sigmoid" else h
         elif relu_masks is None:
             h = torch.relu(h)
         else:

@@ -66,6 +66,7 @@ from .constants import ALPHA_MAX, ALPHA_MIN, NEAR, SUPPORT, T_MIN
 from .geometry import camera_origin_and_rays, intersect, kernel, quat_columns
 from .hashgrid import encode
 from .mlp import mlp_forward, unpack_masks
+from .sh import colour as sh_colour
 
 
 @dataclasses.dataclass
@@ -104,7 +105,8 @@ def render(scene, cam, grid, mlp, K, pixels=None, tiled=False, bins=None, **kw):
 
 def render_and_grad(scene, cam, grid, mlp, K, pixels=None, grad_image=None, grad_weights=None,
                     grad_tex=None, tiled=False, bins=None, outer_pixels=2048, pair_budget=3_000_000,
-                    force_cells=None, force_relu=None, mlp_rel_err=5e-6, want_decisions=False, pixel_error=None):
+                    force_cells=None, force_relu=None, mlp_rel_err=5e-6, want_decisions=False, pixel_error=None,
+                    sh_degree=None):
     """Render the given pixels (all by default) and optionally back-propagate.
 
     grad_image [P,3], grad_weights [P,K] and grad_tex [P,K,3] are upstream
@@ -123,6 +125,12 @@ def render_and_grad(scene, cam, grid, mlp, K, pixels=None, grad_image=None, grad
     sum over pixels of its blending weight w = alpha T times the pixel's error
     (supplementary, Densification: the blended errors of Rota Bulo et al.,
     accumulated by adding).
+    sh_degree (None: RGB colours [N,3] and a sigmoid head) selects the
+    spherical-harmonics appearance (Representation, Appearance): colours
+    [N,3 (d+1)^2] are per-surfel coefficients decoded along the unit
+    direction from the camera centre to the surfel centre, and the MLP head's
+    3 (d+1)^2 outputs are coefficients decoded along the pixel's unit ray
+    direction (oracle.sh.colour: max(0, sum_k Y_k a_k + 0.5)).
     """
     need_grad = grad_image is not None or grad_weights is not None or grad_tex is not None
     W, H = cam.width, cam.height
@@ -207,7 +215,7 @@ def render_and_grad(scene, cam, grid, mlp, K, pixels=None, grad_image=None, grad
         fc = None if force_cells is None else np.asarray(force_cells)[sel]
         fr = None if force_relu is None else np.asarray(force_relu)[sel]
         res = _composite_chunk(pp, ss, Pc, o, d, prm, key_np, K, table, level_scales, cam.fx, weights, fc,
-                               mlp_rel_err, fr, want_decisions)
+                               mlp_rel_err, fr, want_decisions, sh_degree)
         for nm in ("image", "plain", "weights", "depths", "t_final", "tex"):
             out[nm][sel] = res[nm].detach().numpy()
         for nm in ("ids", "n_comp", "margin", "mlp_margin"):
@@ -244,8 +252,12 @@ def _collect_grads(prm, table, weights):
     return g
 
 
+def _unit(v):
+    return v / torch.sqrt((v * v).sum(dim=-1, keepdim=True))
+
+
 def _composite_chunk(pp, ss, Pc, o, d, prm, key_np, K, table, level_scales, focal, weights, force_cells=None,
-                     mlp_rel_err=5e-6, force_relu=None, want_decisions=False):
+                     mlp_rel_err=5e-6, force_relu=None, want_decisions=False, sh_degree=None):
     """Phase 2 for one chunk of pixels: exact decisions, compositing, texture."""
     E = pp.shape[0]
     order = np.lexsort((ss, key_np[ss].astype(np.float64), pp))
@@ -275,7 +287,11 @@ def _composite_chunk(pp, ss, Pc, o, d, prm, key_np, K, table, level_scales, foca
     Td = zeros.index_put((ptt, colt), t.where(supp, torch.zeros_like(t)))
     vd = torch.zeros(Pc, M, dtype=torch.bool).index_put((ptt, colt), valid)
     sid_d = torch.full((Pc, M), -1, dtype=torch.int64).index_put((ptt, colt), st)
-    cols_d = torch.zeros(Pc, M, 3, dtype=torch.float64).index_put((ptt, colt), prm["colors"][st])
+    if sh_degree is None:
+        pair_col = prm["colors"][st]
+    else:
+        pair_col = sh_colour(prm["colors"][st], _unit(mu - o), sh_degree)
+    cols_d = torch.zeros(Pc, M, 3, dtype=torch.float64).index_put((ptt, colt), pair_col)
 
     Ta = torch.cumprod(1.0 - A, dim=1)
     Tb = torch.cat([torch.ones(Pc, 1, dtype=torch.float64), Ta[:, :-1]], dim=1)
@@ -339,7 +355,10 @@ def _composite_chunk(pp, ss, Pc, o, d, prm, key_np, K, table, level_scales, foca
         masks = None
         if force_relu is not None:
             masks = unpack_masks(force_relu[rows, slots], weights[0].shape[0], len(weights) - 1)
-        out = mlp_forward(z, weights, relu_masks=masks)
+        if sh_degree is None:
+            out = mlp_forward(z, weights, relu_masks=masks)
+        else:
+            out = sh_colour(mlp_forward(z, weights, relu_masks=masks, head="linear"), _unit(d[rt]), sh_degree)
         tex = tex.index_put((rt, stt), out)
         with torch.no_grad():
             sm = _relu_margins(z.detach(), [w.detach() for w in weights]) / mlp_rel_err
