@@ -60,7 +60,8 @@ typedef enum { NX_F32 = 0, NX_F16 = 1, NX_BF16 = 2 } nx_dtype;
  *   scales    [n,2]  s1, s2 > 0 along v1, v2
  *   opacities [n]    in [0,1]
  *   gammas    [n,2]  generalised-Gaussian exponents, >= 1
- *   colors    [n,3]  plain (non-textured) RGB colour
+ *   colors    [n,3]  plain (non-textured) RGB colour, or [n,48] SH
+ *                    coefficients (nx_set_sh_degree)
  * Surfels with a non-finite parameter, a scale <= 0 or a centre at camera
  * depth <= near are culled (never drawn, zero gradient). */
 typedef struct {
@@ -92,8 +93,9 @@ typedef struct {
 
 /* Texture MLP without biases (Results, implementation): w[i] is a device
  * [dims[i+1]][dims[i]] matrix in `dtype` (NX_F32 or NX_BF16). Hidden layers
- * use ReLU, the 3-channel head a sigmoid.
- * Supported: dims = {levels*feat (<= 32), 64 or 128, same, 3}. NX_F32 runs
+ * use ReLU; the 3-channel RGB head a sigmoid, the 48-value SH head none (see
+ * nx_set_sh_degree).
+ * Supported: dims = {levels*feat (<= 32), 64 or 128, same, 3 or 48}. NX_F32 runs
  * on FP32 matrix cores, NX_BF16 on BF16 matrix cores with FP32 accumulation. */
 typedef struct {
   const void *w[3];
@@ -168,6 +170,20 @@ typedef struct nx_ctx nx_ctx;
 int nx_create(nx_ctx **out, int32_t K, int32_t tile, nx_dtype feat_dtype, nx_dtype mlp_dtype);
 int nx_destroy(nx_ctx *ctx);
 
+/* Appearance (Representation, Appearance; Results: "degree 3 ... an MLP output
+ * dimension of 48"). degree -1 (the default): nx_surfels.colors is [n,3] RGB
+ * and the MLP head has 3 outputs through a sigmoid. degree 3: colors is
+ * [n,48] spherical-harmonics coefficients in the layout [16][3] (coefficient
+ * k of channel c at 3k + c), decoded along the unit direction from the camera
+ * centre to the surfel centre as max(0, sum_k Y_k a_k + 0.5); the MLP head has
+ * 48 outputs, the same coefficients for the texture, decoded the same way
+ * along the pixel's unit ray direction; Y_k is the real SH basis with
+ * orthonormal constants. Gradients: colors [n,48], and the surfel centre
+ * also receives the gradient through the view direction. Other degrees:
+ * NX_ERR_UNSUPPORTED. Set before the first forward; calls that share a
+ * workspace must use one setting. */
+int nx_set_sh_degree(nx_ctx *ctx, int32_t degree);
+
 /* Workspace bytes for n_surfels surfels seen by n_cams cameras with at most
  * max_instances (surfel, tile) pairs per camera. The pair count depends on
  * the surfels themselves, so it cannot be known from the sizes alone: with
@@ -181,6 +197,18 @@ int nx_destroy(nx_ctx *ctx);
  * forward's sorted tile lists and per-surfel records to the backward. */
 int nx_workspace_size(nx_ctx *ctx, int64_t n_surfels, const nx_camera *cams, int32_t n_cams,
                       int64_t max_instances, size_t *bytes);
+
+/* The exact workspace size for these surfels and cameras (the pair counts
+ * depend on the surfels, so nx_workspace_size with max_instances = 0 gives
+ * only the size this call needs): runs the preprocess, the depth sort and the
+ * pair count of each camera in `workspace` (at least
+ * nx_workspace_size(ctx, n, cams + c, 1, 0) for every camera c; its contents
+ * are overwritten), synchronises the stream once per camera, and stores in
+ * *bytes the size nx_render_forward (or nx_render_forward_async with
+ * max_instances = the largest count) needs, and in counts[c] (host array
+ * [n_cams], may be NULL) camera c's number of (surfel, tile) pairs. */
+int nx_workspace_size_exact(nx_ctx *ctx, const nx_surfels *surfels, const nx_camera *cams, int32_t n_cams,
+                            void *workspace, size_t workspace_bytes, size_t *bytes, int64_t *counts, void *stream);
 
 /* Collection pass, then texturing pass (Rendering), for each of the n_cams
  * cameras in cams (host array, 1 <= n_cams <= NX_MAX_CAMS, at most 2^30
@@ -259,6 +287,75 @@ int nx_render_backward(nx_ctx *ctx, const nx_surfels *surfels, const nx_camera *
                        const void *workspace, size_t workspace_bytes, const float *grad_image,
                        const float *grad_weights, const float *grad_tex, const nx_grads *grads, void *stream);
 
+/* Auxiliary losses of the optimisation (Optimization, Losses) and their
+ * gradients, for the P pixels (cameras concatenated) of a forward with this
+ * context's K:
+ *   L_alpha   = 1/P sum_p (1 - sum_j W_pj)
+ *   L_texture = 1/(3P) sum_p sum_c |GT_pc - sum_j W_pj Tex_pjc / sum_j W_pj|
+ *               (pixels whose weights sum to 0 add nothing)
+ *   L_opacity = 1/n sum_i o_i
+ *   L_grid    = sum_l s_l^-3 sum_i sum_f H_lif^2 (the paper prints the term
+ *               linear in H; it is read as this size-normalised weight decay)
+ * weights [P,K], tex [P,K,3] (the forward's outputs), target [P,3],
+ * opacities [n]: device float32; grid may be NULL (no L_grid). The gradient
+ * of lambda_alpha L_alpha + lambda_texture L_texture + lambda_opacity
+ * L_opacity + lambda_grid L_grid is ADDED (+=) to grad_weights [P,K] and
+ * grad_tex [P,K,3] (pass them to nx_render_backward as dL/dW and dL/dTex),
+ * grad_opacities [n] and grad_table (float32, the table's shape); any may be
+ * NULL. losses: device float32 [4], set to the unweighted L_alpha,
+ * L_texture, L_opacity, L_grid (workgroup partial sums added with atomics:
+ * the last bits vary run to run). Enqueued on stream; no synchronisation. */
+typedef struct {
+  float alpha, texture, opacity, grid;
+} nx_aux_lambdas;
+int nx_aux_losses(nx_ctx *ctx, int64_t n_pixels, const float *weights, const float *tex, const float *target,
+                  int64_t n_surfels, const float *opacities, const nx_hashgrid *grid, const nx_aux_lambdas *lambdas,
+                  float *grad_weights, float *grad_tex, float *grad_opacities, float *grad_table, float *losses,
+                  void *stream);
+
+/* Adaptive density control (supplementary, Adaptive Density Control). */
+
+/* Initialisation by farthest point sampling: order[0..m) receives the first
+ * m points of the FPS order of points [n,3] (device float32), starting at
+ * point 0, each next point maximising its distance to the points taken
+ * before it; dist2[i] receives that squared distance (the squared initial
+ * scale of point order[i]; dist2[0] = dist2[1]). Squared distances are
+ * evaluated in float32 as (dx dx + dy dy) + dz dz with every operation
+ * rounded; ties go to the smallest index. 1 <= m <= n < 2^31. order [m]
+ * int32, dist2 [m] float32: device. One cooperative launch (a grid barrier
+ * per point taken); the workspace needs nx_fps_workspace_size bytes. */
+int nx_fps_workspace_size(int64_t n, size_t *bytes);
+int nx_fps(nx_ctx *ctx, const float *points, int64_t n, int64_t m, int32_t *order, float *dist2, void *workspace,
+           size_t workspace_bytes, void *stream);
+
+/* Output of nx_densify: device float32 arrays of `capacity` surfels in the
+ * layout of nx_surfels, and parent [capacity] int32 (the input surfel each
+ * output came from). */
+typedef struct {
+  float *means, *quats, *scales, *opacities, *gammas, *colors;
+  int32_t *parent;
+  int64_t capacity;
+} nx_surfels_out;
+
+/* One densification step: draw n_split surfels for splitting with
+ * probability in proportion to their blended errors (nx_grads.blended_error
+ * summed over iterations), without replacement, by exponential clocks:
+ * surfel i gets the key exp_draws[i] / blended_error[i] (float32; the caller
+ * supplies exp_draws [n] >= 0, i.i.d. Exp(1)) and the n_split smallest finite
+ * keys are drawn (surfels with error <= 0 never are; ties to the smaller
+ * index). A drawn surfel with s1 >= s2 becomes two with scales (s1/2, s2) and
+ * centres mu -/+ (s1/2) v1 (v2 and s2 when s2 > s1); rotation, opacity,
+ * gammas and colour are copied. Then every surfel with opacity below
+ * min_opacity (the paper uses 0.005) is dropped. Survivors keep their input
+ * order (a split surfel's first child in its place); the second children
+ * follow, in input order. out->capacity must be at least n + n_split; the
+ * call synchronises the stream once to return the output count in *n_out
+ * (host). The workspace needs nx_densify_workspace_size bytes. */
+int nx_densify_workspace_size(int64_t n, size_t *bytes);
+int nx_densify(nx_ctx *ctx, const nx_surfels *in, const float *blended_error, const float *exp_draws, int64_t n_split,
+               float min_opacity, const nx_surfels_out *out, int64_t *n_out, void *workspace, size_t workspace_bytes,
+               void *stream);
+
 /* Byte offsets of the forward's intermediate arrays inside the workspace,
  * for inspection: depth keys [n] uint32 (float32 bits of the camera-space
  * centre depth), tile counts [n] uint32, tile rectangles [n,4] int32
@@ -270,6 +367,15 @@ typedef struct {
 } nx_ws_layout;
 int nx_workspace_layout(nx_ctx *ctx, int64_t n_surfels, const nx_camera *cams, int32_t n_cams,
                         int64_t n_instances, nx_ws_layout *layout);
+
+/* Diagnostics: limits that force the hash-grid gradient's fallback paths,
+ * which the default sizes leave idle. slab_records > 0 caps the records a
+ * workgroup files per bucket slab (records beyond go straight to the table
+ * with float atomics); cas_rounds > 0 caps the reduction's LDS
+ * compare-and-swap retries (a record that loses them is added with a global
+ * float atomic). 0 restores the default. Results stay the same up to float32
+ * summation order; only speed changes. */
+int nx_debug_limits(nx_ctx *ctx, int64_t slab_records, int32_t cas_rounds);
 
 /* Per-phase timing for diagnostics and benchmarks. While enabled, every
  * kernel group a call launches (e.g. "raster_forward") is bracketed by two

@@ -8,8 +8,11 @@ from . import _lib
 
 _lib.load()
 
-from .render import (Context, ForwardResult, RenderFunction, camera_struct, instance_counts,  # noqa: E402,F401
-                     render, render_backward, render_forward, render_forward_noalloc, workspace_size)
+from .render import (Context, ForwardResult, RenderFunction, aux_losses, camera_struct, densify, fps,  # noqa: E402,F401
+                     instance_counts, render, render_backward, render_forward, render_forward_noalloc, workspace_size,
+                     workspace_size_exact)
 
-__all__ = ["Context", "ForwardResult", "RenderFunction", "camera_struct", "instance_counts", "render",
-           "render_backward", "render_forward", "render_forward_noalloc", "workspace_size"]
+__all__ = ["Context", "ForwardResult", "RenderFunction", "aux_losses", "camera_struct", "densify", "fps",
+           "instance_counts", "render",
+           "render_backward", "render_forward", "render_forward_noalloc", "workspace_size",
+           "workspace_size_exact"]

@@ -54,6 +54,16 @@ class NxGrads(ctypes.Structure):
                 ("pixel_error", c_void_p), ("blended_error", c_void_p)]
 
 
+class NxAuxLambdas(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_float), ("texture", ctypes.c_float), ("opacity", ctypes.c_float),
+                ("grid", ctypes.c_float)]
+
+
+class NxSurfelsOut(ctypes.Structure):
+    _fields_ = [("means", c_void_p), ("quats", c_void_p), ("scales", c_void_p), ("opacities", c_void_p),
+                ("gammas", c_void_p), ("colors", c_void_p), ("parent", c_void_p), ("capacity", ctypes.c_int64)]
+
+
 class NxWsLayout(ctypes.Structure):
     _fields_ = [(nm, ctypes.c_size_t) for nm in ("depth_keys", "tile_counts", "rects", "records", "sorted_tiles",
                                                   "sorted_ids", "tile_ranges", "total")]
@@ -65,8 +75,13 @@ SIGNATURES = {
     "nx_last_error": ([], ctypes.c_char_p),
     "nx_create": ([ctypes.POINTER(c_void_p), ctypes.c_int32, ctypes.c_int32, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "nx_destroy": ([c_void_p], ctypes.c_int),
+    "nx_set_sh_degree": ([c_void_p, ctypes.c_int32], ctypes.c_int),
+    "nx_debug_limits": ([c_void_p, ctypes.c_int64, ctypes.c_int32], ctypes.c_int),
     "nx_workspace_size": ([c_void_p, ctypes.c_int64, ctypes.POINTER(NxCamera), ctypes.c_int32, ctypes.c_int64,
                            ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "nx_workspace_size_exact": ([c_void_p, ctypes.POINTER(NxSurfels), ctypes.POINTER(NxCamera), ctypes.c_int32,
+                                 c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t),
+                                 ctypes.POINTER(ctypes.c_int64), c_void_p], ctypes.c_int),
     "nx_workspace_layout": ([c_void_p, ctypes.c_int64, ctypes.POINTER(NxCamera), ctypes.c_int32, ctypes.c_int64,
                              ctypes.POINTER(NxWsLayout)], ctypes.c_int),
     "nx_render_forward": ([c_void_p, ctypes.POINTER(NxSurfels), ctypes.POINTER(NxCamera), ctypes.c_int32,
@@ -82,6 +97,16 @@ SIGNATURES = {
     "nx_render_forward_noalloc": ([c_void_p, ctypes.POINTER(NxSurfels), ctypes.POINTER(NxCamera), ctypes.c_int32,
                                    ctypes.POINTER(NxHashGrid), ctypes.POINTER(NxMLP), ctypes.POINTER(NxFwdOut),
                                    ctypes.c_int64, c_void_p], ctypes.c_int),
+    "nx_aux_losses": ([c_void_p, ctypes.c_int64, c_void_p, c_void_p, c_void_p, ctypes.c_int64, c_void_p,
+                       ctypes.POINTER(NxHashGrid), ctypes.POINTER(NxAuxLambdas), c_void_p, c_void_p, c_void_p,
+                       c_void_p, c_void_p, c_void_p], ctypes.c_int),
+    "nx_fps_workspace_size": ([ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "nx_fps": ([c_void_p, c_void_p, ctypes.c_int64, ctypes.c_int64, c_void_p, c_void_p, c_void_p, ctypes.c_size_t,
+                c_void_p], ctypes.c_int),
+    "nx_densify_workspace_size": ([ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "nx_densify": ([c_void_p, ctypes.POINTER(NxSurfels), c_void_p, c_void_p, ctypes.c_int64, ctypes.c_float,
+                    ctypes.POINTER(NxSurfelsOut), ctypes.POINTER(ctypes.c_int64), c_void_p, ctypes.c_size_t,
+                    c_void_p], ctypes.c_int),
     "nx_instance_counts": ([c_void_p, ctypes.c_int64, ctypes.POINTER(NxCamera), ctypes.c_int32,
                             ctypes.POINTER(ctypes.c_int64), c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int64),
                             c_void_p], ctypes.c_int),

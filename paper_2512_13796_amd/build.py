@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnexels.so")
-SOURCES = ["api.hip", "preprocess.hip", "sort.hip", "raster.hip", "texture.hip"]
+SOURCES = ["api.hip", "preprocess.hip", "sort.hip", "raster.hip", "texture.hip", "aux.hip", "adc.hip"]
 
 
 def hipcc() -> str:

@@ -24,6 +24,9 @@ struct nx_ctx {
   int32_t K;
   int32_t tile;
   nx_dtype feat_dtype, mlp_dtype;
+  int sh = 0;        // 1: spherical-harmonics appearance (48 coefficients per surfel and MLP head)
+  int64_t debug_slab = 0;  // > 0: records per hash-scatter slab (forces the slab-full fallback)
+  int debug_cas = 0;       // > 0: LDS compare-and-swap retries before a global atomic
   uint32_t* pinned;  // one host word for the instance-count readback
   bool timing;
   // The backward's extra streams (default priority) and the events that
@@ -190,7 +193,9 @@ int check_grid_mlp(const nx_ctx* ctx, const nx_hashgrid* g, const nx_mlp* m) {
   if (m->dims[0] != g->levels * g->feat) return fail(NX_ERR_INVALID, "mlp dims[0] must equal levels * feat");
   if (m->dims[1] != m->dims[2] || (m->dims[1] != 64 && m->dims[1] != 128))
     return fail(NX_ERR_UNSUPPORTED, "hidden widths must be equal and 64 or 128");
-  if (m->dims[3] != 3) return fail(NX_ERR_UNSUPPORTED, "the MLP head must have 3 outputs");
+  if (m->dims[3] != (ctx->sh ? 48 : 3))
+    return fail(NX_ERR_UNSUPPORTED, ctx->sh ? "the MLP head must have 48 outputs (degree-3 SH coefficients)"
+                                            : "the MLP head must have 3 outputs");
   return NX_OK;
 }
 
@@ -354,7 +359,8 @@ int forward_prefix(nx_ctx* ctx, const nx_surfels* surfels, const nx::CamDev& cd,
   {
   PhaseTimer pt(ctx, "preprocess", s);
   NX_CHECK_HIP(nx::launch_preprocess(surfels->means, surfels->quats, surfels->scales, surfels->opacities,
-                                     surfels->gammas, surfels->colors, n, cd, depth_keys, counts, rects, records, s));
+                                     surfels->gammas, surfels->colors, ctx->sh, n, cd, depth_keys, counts, rects,
+                                     records, s));
   }
   uint32_t* sk = at<uint32_t>(ws, L0.sort_k);
   uint32_t* sv = at<uint32_t>(ws, L0.sort_v);
@@ -446,7 +452,7 @@ int forward_one(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera& cam, co
   }
   {
   PhaseTimer pt(ctx, "texture_forward", s);
-  NX_CHECK_HIP(nx::launch_texture_forward(K, ctx->feat_dtype, ctx->mlp_dtype, gd, K > 0 ? grid->table : nullptr, md,
+  NX_CHECK_HIP(nx::launch_texture_forward(K, ctx->feat_dtype, ctx->mlp_dtype, ctx->sh, gd, K > 0 ? grid->table : nullptr, md,
                                           out->ids, out->depths, out->weights, out->plain, out->tex, out->image,
                                           out->cells, out->relu_masks, out->features, s));
   }
@@ -477,7 +483,8 @@ int backward_one(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera& cam, c
                                               K > 0 ? gdepth : nullptr, pixel_error, rec_grad, s));
     }
     PhaseTimer pt(ctx, "preprocess_backward", s);
-    NX_CHECK_HIP(nx::launch_preprocess_backward(surfels->means, surfels->quats, surfels->scales, n, cd,
+    NX_CHECK_HIP(nx::launch_preprocess_backward(surfels->means, surfels->quats, surfels->scales, surfels->colors,
+                                                ctx->sh, n, cd,
                                                 at<uint32_t>(ws, L.tile_counts), rec_grad, grads->means, grads->quats,
                                                 grads->scales, grads->opacities, grads->gammas, grads->colors,
                                                 pixel_error ? grads->blended_error : nullptr, s));
@@ -498,7 +505,7 @@ int backward_one(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera& cam, c
     float2* fgrad = grads->table ? at<float2>(ws, L.feat_grad) : nullptr;
     {
       PhaseTimer pt(ctx, "texture_backward", s);
-      NX_CHECK_HIP(nx::launch_texture_backward(K, ctx->feat_dtype, ctx->mlp_dtype, gd, grid->table, md, saved->ids,
+      NX_CHECK_HIP(nx::launch_texture_backward(K, ctx->feat_dtype, ctx->mlp_dtype, ctx->sh, gd, grid->table, md, saved->ids,
                                                saved->depths, saved->weights, grad_image, grad_tex, fgrad,
                                                grads->mlp[0], grads->mlp[1], grads->mlp[2], gdepth,
                                                at<unsigned char>(ws, L.weight_ops), s));
@@ -586,6 +593,23 @@ int nx_create(nx_ctx** out, int32_t K, int32_t tile, nx_dtype feat_dtype, nx_dty
   return NX_OK;
 }
 
+int nx_debug_limits(nx_ctx* ctx, int64_t slab_records, int32_t cas_rounds) {
+  int r;
+  if ((r = check_ctx(ctx)) != NX_OK) return r;
+  if (slab_records < 0 || cas_rounds < 0) return fail(NX_ERR_INVALID, "limits must be >= 0");
+  ctx->debug_slab = slab_records;
+  ctx->debug_cas = cas_rounds;
+  return NX_OK;
+}
+
+int nx_set_sh_degree(nx_ctx* ctx, int32_t degree) {
+  int r;
+  if ((r = check_ctx(ctx)) != NX_OK) return r;
+  if (degree != -1 && degree != 3) return fail(NX_ERR_UNSUPPORTED, "sh degree must be -1 (RGB) or 3");
+  ctx->sh = degree == 3 ? 1 : 0;
+  return NX_OK;
+}
+
 int nx_destroy(nx_ctx* ctx) {
   if (!ctx) return NX_OK;
   for (auto& p : ctx->pending) {
@@ -656,6 +680,39 @@ int nx_workspace_size(nx_ctx* ctx, int64_t n_surfels, const nx_camera* cams, int
   size_t total = make_shared_layout(cams, n_cams, ctx->K).total;
   for (int32_t c = 0; c < n_cams; ++c) total += make_layout(n_surfels, make_cam(cams[c]), ctx->K, max_instances).total;
   *bytes = total;
+  return NX_OK;
+}
+
+int nx_workspace_size_exact(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* cams, int32_t n_cams,
+                            void* workspace, size_t workspace_bytes, size_t* bytes, int64_t* counts, void* stream) {
+  int r;
+  if ((r = check_ctx(ctx)) != NX_OK) return r;
+  if ((r = check_surfels(surfels)) != NX_OK) return r;
+  if ((r = check_camera(cams, n_cams)) != NX_OK) return r;
+  if (!bytes) return fail(NX_ERR_INVALID, "bytes is NULL");
+  size_t need0 = 0;
+  for (int32_t c = 0; c < n_cams; ++c) {
+    const size_t t = make_layout(surfels->n, make_cam(cams[c]), ctx->K, 0).total;
+    need0 = t > need0 ? t : need0;
+  }
+  if (!workspace || workspace_bytes < need0)
+    return fail(NX_ERR_WORKSPACE, "workspace smaller than nx_workspace_size(..., n_cams = 1, max_instances = 0)");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  NX_CHECK_HIP(hipGetLastError());
+  size_t total = make_shared_layout(cams, n_cams, ctx->K).total;
+  for (int32_t c = 0; c < n_cams; ++c) {
+    const nx::CamDev cd = make_cam(cams[c]);
+    const Layout L0 = make_layout(surfels->n, cd, ctx->K, 0);
+    if ((r = forward_prefix(ctx, surfels, cd, workspace, L0, s)) != NX_OK) return r;
+    const uint32_t* offsets = at<uint32_t>(workspace, L0.offsets);
+    NX_CHECK_HIP(hipMemcpyAsync(ctx->pinned, offsets + surfels->n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    NX_CHECK_HIP(hipStreamSynchronize(s));
+    const int64_t n_inst = (int64_t)ctx->pinned[0];
+    if (counts) counts[c] = n_inst;
+    total += make_layout(surfels->n, cd, ctx->K, n_inst).total;
+  }
+  *bytes = total;
+  g_last_error.clear();
   return NX_OK;
 }
 
@@ -807,6 +864,148 @@ int nx_render_forward_noalloc(nx_ctx* ctx, const nx_surfels* surfels, const nx_c
   return NX_OK;
 }
 
+int nx_aux_losses(nx_ctx* ctx, int64_t n_pixels, const float* weights, const float* tex, const float* target,
+                  int64_t n_surfels, const float* opacities, const nx_hashgrid* grid, const nx_aux_lambdas* lambdas,
+                  float* grad_weights, float* grad_tex, float* grad_opacities, float* grad_table, float* losses,
+                  void* stream) {
+  int r;
+  if ((r = check_ctx(ctx)) != NX_OK) return r;
+  if (!lambdas || !losses) return fail(NX_ERR_INVALID, "lambdas or losses is NULL");
+  if (n_pixels < 0 || n_surfels < 0) return fail(NX_ERR_INVALID, "negative size");
+  if (n_pixels > 0 && ctx->K > 0 && (!weights || !tex || !target))
+    return fail(NX_ERR_INVALID, "weights, tex or target is NULL");
+  if (n_surfels > 0 && !opacities) return fail(NX_ERR_INVALID, "opacities is NULL");
+  for (float v : {lambdas->alpha, lambdas->texture, lambdas->opacity, lambdas->grid})
+    if (!isfinite(v)) return fail(NX_ERR_INVALID, "lambdas must be finite");
+  if (grid) {
+    if (!grid->table || !grid->level_scales) return fail(NX_ERR_INVALID, "grid table or level_scales is NULL");
+    if (grid->dtype != ctx->feat_dtype) return fail(NX_ERR_INVALID, "grid dtype differs from the context's feat_dtype");
+    if (grid->feat != 2) return fail(NX_ERR_UNSUPPORTED, "only feat == 2 is supported");
+    if (grid->levels < 1 || grid->levels > 16) return fail(NX_ERR_UNSUPPORTED, "levels must be in [1, 16]");
+    if (grid->log2_size < 4 || grid->log2_size > 24) return fail(NX_ERR_UNSUPPORTED, "log2_size must be in [4, 24]");
+    for (int l = 0; l < grid->levels; ++l)
+      if (!(grid->level_scales[l] > 0.0f) || !isfinite(grid->level_scales[l]))
+        return fail(NX_ERR_INVALID, "level scales must be positive and finite");
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  NX_CHECK_HIP(hipGetLastError());
+  NX_CHECK_HIP(nx::launch_aux_losses(n_pixels, ctx->K, weights, tex, target, lambdas->alpha, lambdas->texture,
+                                     grad_weights, grad_tex, n_surfels, opacities, lambdas->opacity, grad_opacities,
+                                     grid ? grid->dtype : NX_F32, grid ? grid->table : nullptr, grid ? grid->levels : 0,
+                                     grid ? grid->log2_size : 0, grid ? grid->level_scales : nullptr, lambdas->grid,
+                                     grad_table, losses, s));
+  g_last_error.clear();
+  return NX_OK;
+}
+
+namespace {
+constexpr int kFpsMaxGrid = 8192;
+
+struct DensifyLayout {
+  size_t keys, ids, tmp_keys, tmp_ids, hist, chosen, keep1, keep2, off1, off2, iota, scan_blocks, total;
+};
+
+DensifyLayout densify_layout(int64_t n) {
+  DensifyLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  const size_t nn = (size_t)(n > 0 ? n : 1);
+  L.keys = take(4 * nn);
+  L.ids = take(4 * nn);
+  L.tmp_keys = take(4 * nn);
+  L.tmp_ids = take(4 * nn);
+  L.hist = take(4 * nx::radix_hist_words((int64_t)nn));
+  L.chosen = take(4 * nn);
+  L.keep1 = take(4 * nn);
+  L.keep2 = take(4 * nn);
+  L.off1 = take(4 * (nn + 1));
+  L.off2 = take(4 * (nn + 1));
+  L.iota = take(4 * nn);
+  L.scan_blocks = take(4 * nx::scan_block_words((int64_t)nn));
+  L.total = o;
+  return L;
+}
+
+size_t fps_workspace(int64_t n) { return align_up(sizeof(float) * (size_t)(n > 0 ? n : 1)) + nx::fps_slot_bytes(kFpsMaxGrid); }
+}  // namespace
+
+int nx_fps_workspace_size(int64_t n, size_t* bytes) {
+  if (!bytes || n < 0) return fail(NX_ERR_INVALID, "bad argument");
+  *bytes = fps_workspace(n);
+  return NX_OK;
+}
+
+int nx_fps(nx_ctx* ctx, const float* points, int64_t n, int64_t m, int32_t* order, float* dist2, void* workspace,
+           size_t workspace_bytes, void* stream) {
+  int r;
+  if ((r = check_ctx(ctx)) != NX_OK) return r;
+  if (!points || !order || !dist2) return fail(NX_ERR_INVALID, "points, order or dist2 is NULL");
+  if (n < 1 || n >= ((int64_t)1 << 31)) return fail(NX_ERR_INVALID, "n must be in [1, 2^31)");
+  if (m < 1 || m > n) return fail(NX_ERR_INVALID, "m must be in [1, n]");
+  if (!workspace || workspace_bytes < fps_workspace(n)) return fail(NX_ERR_WORKSPACE, "workspace too small");
+  int grid = 1;
+  NX_CHECK_HIP(nx::fps_grid(n, &grid));
+  if (grid > kFpsMaxGrid) grid = kFpsMaxGrid;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  NX_CHECK_HIP(hipGetLastError());
+  float* best = static_cast<float*>(workspace);
+  auto* slots = at<unsigned long long>(workspace, align_up(sizeof(float) * (size_t)n));
+  NX_CHECK_HIP(nx::launch_fps(points, n, m, best, slots, grid, order, dist2, s));
+  g_last_error.clear();
+  return NX_OK;
+}
+
+int nx_densify_workspace_size(int64_t n, size_t* bytes) {
+  if (!bytes || n < 0) return fail(NX_ERR_INVALID, "bad argument");
+  *bytes = densify_layout(n).total;
+  return NX_OK;
+}
+
+int nx_densify(nx_ctx* ctx, const nx_surfels* in, const float* blended_error, const float* exp_draws, int64_t n_split,
+               float min_opacity, const nx_surfels_out* out, int64_t* n_out, void* workspace, size_t workspace_bytes,
+               void* stream) {
+  int r;
+  if ((r = check_ctx(ctx)) != NX_OK) return r;
+  if ((r = check_surfels(in)) != NX_OK) return r;
+  const int64_t n = in->n;
+  if (!out || !n_out) return fail(NX_ERR_INVALID, "out or n_out is NULL");
+  if (n_split < 0) return fail(NX_ERR_INVALID, "n_split is negative");
+  if (n_split > n) n_split = n;
+  if (n > 0 && (!blended_error || !exp_draws)) return fail(NX_ERR_INVALID, "blended_error or exp_draws is NULL");
+  if (!isfinite(min_opacity)) return fail(NX_ERR_INVALID, "min_opacity must be finite");
+  if (out->capacity < n + n_split) return fail(NX_ERR_INVALID, "out->capacity is below n + n_split");
+  if (n + n_split >= ((int64_t)1 << 31)) return fail(NX_ERR_UNSUPPORTED, "too many surfels");
+  if (n + n_split > 0 &&
+      (!out->means || !out->quats || !out->scales || !out->opacities || !out->gammas || !out->colors))
+    return fail(NX_ERR_INVALID, "an output pointer is NULL");
+  const DensifyLayout L = densify_layout(n);
+  if (!workspace || workspace_bytes < L.total) return fail(NX_ERR_WORKSPACE, "workspace too small");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  NX_CHECK_HIP(hipGetLastError());
+  void* ws = workspace;
+  uint32_t* chosen = at<uint32_t>(ws, L.chosen);
+  NX_CHECK_HIP(nx::launch_split_select(n, n_split, blended_error, exp_draws, at<uint32_t>(ws, L.keys),
+                                       at<uint32_t>(ws, L.ids), at<uint32_t>(ws, L.tmp_keys),
+                                       at<uint32_t>(ws, L.tmp_ids), at<uint32_t>(ws, L.hist), chosen, s));
+  uint32_t* off1 = at<uint32_t>(ws, L.off1);
+  uint32_t* off2 = at<uint32_t>(ws, L.off2);
+  NX_CHECK_HIP(nx::launch_split_prune(n, in->means, in->quats, in->scales, in->opacities, in->gammas, in->colors,
+                                      chosen, min_opacity, at<uint32_t>(ws, L.keep1), at<uint32_t>(ws, L.keep2), off1,
+                                      off2, at<uint32_t>(ws, L.iota), at<uint32_t>(ws, L.scan_blocks), out->means,
+                                      out->quats, out->scales, out->opacities, out->gammas, out->colors, out->parent,
+                                      s));
+  NX_CHECK_HIP(hipMemcpyAsync(ctx->pinned, off1 + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  NX_CHECK_HIP(hipMemcpyAsync(ctx->pinned + 1, off2 + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  NX_CHECK_HIP(hipStreamSynchronize(s));
+  *n_out = (int64_t)ctx->pinned[0] + (int64_t)ctx->pinned[1];
+  g_last_error.clear();
+  return NX_OK;
+}
+
 int nx_instance_counts(nx_ctx* ctx, int64_t n_surfels, const nx_camera* cams, int32_t n_cams,
                        const int64_t* n_instances, const void* workspace, size_t workspace_bytes, int64_t* counts,
                        void* stream) {
@@ -915,7 +1114,7 @@ int nx_render_backward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* 
         PhaseTimer pt(ctx, "scatter_bin", s);
         NX_CHECK_HIP(nx::launch_hash_scatter_bin(ctx->K, gd, l, saved->depths + K * cpix,
                                                  at<float2>(ws, coff + L.feat_grad), grads->table,
-                                                 (uint32_t)slab0, row0, SH.rows, tab, rk, rv, s));
+                                                 (uint32_t)slab0, row0, SH.rows, tab, rk, rv, ctx->debug_slab, s));
         const nx::ScatterSlabs sb = nx::scatter_slabs(cams[c].width, cams[c].height, ctx->K, nb);
         row0 += sb.wgs;
         slab0 += sb.wgs * nb * sb.slab;
@@ -926,7 +1125,8 @@ int nx_render_backward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* 
       NX_CHECK_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_bin[a], 0));
       {
         PhaseTimer pt(ctx, "scatter_reduce", ctx->side);
-        NX_CHECK_HIP(nx::launch_hash_scatter_reduce(gd0, l, grads->table, SH.rows, tab, rk, rv, ctx->side));
+        NX_CHECK_HIP(nx::launch_hash_scatter_reduce(gd0, l, grads->table, SH.rows, tab, rk, rv, ctx->debug_cas,
+                                                    ctx->side));
       }
       NX_CHECK_HIP(hipEventRecord(ctx->ev_red[a], ctx->side));
     }

@@ -63,16 +63,18 @@ struct GridDev {
 };
 
 // ---------------------------------------------------------------- launchers
+// sh: colors holds 48 spherical-harmonics coefficients per surfel ([16][3])
+// decoded along the direction from the camera centre, instead of RGB.
 hipError_t launch_preprocess(const float* means, const float* quats, const float* scales, const float* opac,
-                             const float* gammas, const float* colors, int64_t n, const CamDev& cam,
+                             const float* gammas, const float* colors, int sh, int64_t n, const CamDev& cam,
                              uint32_t* depth_keys, uint32_t* tile_counts, int4* rects, float4* records,
                              hipStream_t s);
 
 hipError_t launch_preprocess_backward(const float* means, const float* quats, const float* scales,
-                                      int64_t n, const CamDev& cam, const uint32_t* tile_counts,
-                                      const float* rec_grad, float* g_means, float* g_quats, float* g_scales,
-                                      float* g_opac, float* g_gammas, float* g_colors, float* g_blended,
-                                      hipStream_t s);
+                                      const float* colors, int sh, int64_t n, const CamDev& cam,
+                                      const uint32_t* tile_counts, const float* rec_grad, float* g_means,
+                                      float* g_quats, float* g_scales, float* g_opac, float* g_gammas,
+                                      float* g_colors, float* g_blended, hipStream_t s);
 
 // Stable LSD radix sort of (key, value) pairs over bits [0, end_bit).
 // keys/vals hold the input and receive the output; tmp_* are scratch of the
@@ -113,8 +115,11 @@ struct MlpDev {
   int in_dim, hidden;
 };
 
-hipError_t launch_texture_forward(int K, int feat_dtype, int mlp_dtype, const GridDev& grid, const void* table,
-                                  const MlpDev& mlp, const int32_t* ids, const float* depths,
+// sh: the MLP head has 48 outputs, degree-3 SH coefficients decoded along
+// the unit ray (colour = max(0, sum_k Y_k a_k + 0.5)), instead of a sigmoid RGB
+// head of 3.
+hipError_t launch_texture_forward(int K, int feat_dtype, int mlp_dtype, int sh, const GridDev& grid,
+                                  const void* table, const MlpDev& mlp, const int32_t* ids, const float* depths,
                                   const float* weights, const float* plain, float* tex, float* image,
                                   int32_t* cells, uint32_t* relu_masks, float* features, hipStream_t s);
 
@@ -122,15 +127,15 @@ hipError_t launch_texture_forward(int K, int feat_dtype, int mlp_dtype, const Gr
 // accumulate the MLP weight gradients and the depth gradient, and write the
 // gradient with respect to each level's interpolated feature pair (already
 // scaled by Delta_l) to feat_grad (layout below).
-hipError_t launch_texture_backward(int K, int feat_dtype, int mlp_dtype, const GridDev& grid, const void* table,
-                                   const MlpDev& mlp, const int32_t* ids, const float* depths,
+hipError_t launch_texture_backward(int K, int feat_dtype, int mlp_dtype, int sh, const GridDev& grid,
+                                   const void* table, const MlpDev& mlp, const int32_t* ids, const float* depths,
                                    const float* weights, const float* grad_image, const float* grad_tex,
                                    float2* feat_grad, float* g_mlp0, float* g_mlp1, float* g_mlp2,
                                    float* grad_depth, unsigned char* weight_ops, hipStream_t s);
 
 // Workspace section for the backward's MLP operand slots in global memory
 // (used for hidden width 128).
-constexpr size_t kWeightOperandBytes = 192 * 1024;
+constexpr size_t kWeightOperandBytes = 256 * 1024;
 
 // Texture backward, second half: distribute feat_grad over the 8 cell
 // corners of every level and add the result into g_table, level by level:
@@ -144,16 +149,49 @@ constexpr size_t kWeightOperandBytes = 192 * 1024;
 // ends by writing (slab start, records in it) to row row0 + w of the bucket's
 // slab-table column (slab_table[b * n_rows + row]). A slab that fills up
 // sends further records straight to the table with atomics (correct,
-// slower). The arena (rec_key, rec_val) and the slab table are shared by all
+// slower). slab_cap > 0 shrinks the slabs and cas_rounds > 0 bounds the
+// reduction's LDS compare-and-swap retries (then a global atomic), to
+// exercise both fallbacks in tests; 0 keeps the defaults. The arena (rec_key, rec_val) and the slab table are shared by all
 // cameras of a call: camera c takes the next wgs rows and the next
 // wgs * nb * slab records.
 hipError_t launch_hash_scatter_bin(int K, const GridDev& grid, int level, const float* depths,
                                    const float2* feat_grad, float* g_table, uint32_t slab0, int64_t row0,
                                    int64_t n_rows, uint2* slab_table, uint16_t* rec_key, float2* rec_val,
+                                   int64_t slab_cap,
                                    hipStream_t s);
 hipError_t launch_hash_scatter_reduce(const GridDev& grid, int level, float* g_table, int64_t n_rows,
                                       const uint2* slab_table, const uint16_t* rec_key, const float2* rec_val,
+                                      int cas_rounds,
                                       hipStream_t s);
+
+// Auxiliary losses (L_alpha, L_texture over P pixels with K slots; L_opacity
+// over n surfels; L_grid over the table): gradients scaled by the lambdas are
+// added to gW [P,K], gTex [P,K,3], g_opac [n], g_table [levels][2^log2_size][2]
+// (each may be null); losses[0..3] receive the unweighted values.
+hipError_t launch_aux_losses(int64_t P, int K, const float* W, const float* tex, const float* target, float lam_alpha,
+                             float lam_texture, float* gW, float* gTex, int64_t n, const float* opac, float lam_opacity,
+                             float* g_opac, int feat_dtype, const void* table, int levels, int log2_size,
+                             const float* level_scales, float lam_grid, float* g_table, float* losses, hipStream_t s);
+
+// Adaptive density control. FPS: one cooperative launch of `grid`
+// workgroups (fps_grid: the co-resident maximum, at most what n needs);
+// best: n floats of scratch, slots: fps_slot_bytes(grid) bytes.
+size_t fps_slot_bytes(int grid);
+hipError_t fps_grid(int64_t n, int* grid);
+hipError_t launch_fps(const float* pts, int64_t n, int64_t m, float* best, unsigned long long* slots, int grid,
+                      int32_t* order, float* d2, hipStream_t s);
+// Split selection: chosen[i] = 1 for the k smallest keys err/draw (finite
+// keys only); keys, ids, tmp_* are n words, hist radix_hist_words(n).
+hipError_t launch_split_select(int64_t n, int64_t k, const float* err, const float* draws, uint32_t* keys,
+                               uint32_t* ids, uint32_t* tmp_keys, uint32_t* tmp_ids, uint32_t* hist,
+                               uint32_t* chosen, hipStream_t s);
+// Split the chosen surfels and drop those with opacity < min_opacity;
+// off1[n] + off2[n] (device) is the number written.
+hipError_t launch_split_prune(int64_t n, const float* means, const float* quats, const float* scales,
+                              const float* opac, const float* gammas, const float* colors, const uint32_t* chosen,
+                              float min_opacity, uint32_t* keep1, uint32_t* keep2, uint32_t* off1, uint32_t* off2,
+                              uint32_t* iota, uint32_t* scan_blocks, float* o_means, float* o_quats, float* o_scales,
+                              float* o_opac, float* o_gammas, float* o_colors, int32_t* o_parent, hipStream_t s);
 
 // Screen blocks of the hash scatter: bw x bh patches of 4x4 pixels with
 // bw * bh * K = kScatUnits (patch, slot) units, i.e. at most 4096 corner

@@ -126,6 +126,62 @@ __device__ __forceinline__ Dual operator/(Dual a, Dual b) {
 __device__ __forceinline__ double val(double a) { return a; }
 __device__ __forceinline__ double val(Dual a) { return a.v; }
 
+__device__ __forceinline__ Dual sqrt_d(Dual a) {
+  const double r = sqrt(a.v);
+  return Dual(r, a.d / (2.0 * r));
+}
+__device__ __forceinline__ double sqrt_d(double a) { return sqrt(a); }
+
+// Real spherical harmonics up to degree 3 of a unit direction (x, y, z), in
+// the usual Cartesian form with orthonormal constants (Representation,
+// Appearance: channel-wise coefficients, 16 per channel). The colour of a
+// channel is sum_k Y_k a_k + 0.5, clamped below at 0.
+template <typename T>
+__device__ void sh_basis16(T x, T y, T z, T Y[16]) {
+  const double C0 = 0.28209479177387814, C1 = 0.4886025119029199;
+  const double C2[5] = {1.0925484305920792, -1.0925484305920792, 0.31539156525252005, -1.0925484305920792,
+                        0.5462742152960396};
+  const double C3[7] = {-0.5900435899266435, 2.890611442640554, -0.4570457994644658, 0.3731763325901154,
+                        -0.4570457994644658, 1.445305721320277, -0.5900435899266435};
+  const T xx = x * x, yy = y * y, zz = z * z;
+  Y[0] = T(C0);
+  Y[1] = T(-C1) * y;
+  Y[2] = T(C1) * z;
+  Y[3] = T(-C1) * x;
+  Y[4] = T(C2[0]) * (x * y);
+  Y[5] = T(C2[1]) * (y * z);
+  Y[6] = T(C2[2]) * (T(2.0) * zz - xx - yy);
+  Y[7] = T(C2[3]) * (x * z);
+  Y[8] = T(C2[4]) * (xx - yy);
+  Y[9] = T(C3[0]) * y * (T(3.0) * xx - yy);
+  Y[10] = T(C3[1]) * (x * y) * z;
+  Y[11] = T(C3[2]) * y * (T(4.0) * zz - xx - yy);
+  Y[12] = T(C3[3]) * z * (T(2.0) * zz - T(3.0) * xx - T(3.0) * yy);
+  Y[13] = T(C3[4]) * x * (T(4.0) * zz - xx - yy);
+  Y[14] = T(C3[5]) * z * (xx - yy);
+  Y[15] = T(C3[6]) * x * (xx - T(3.0) * yy);
+}
+
+// The three channels before the clamp, sum_k Y_k(d) a_{3k+c} + 0.5, for the
+// unit direction d from the camera centre o to the surfel centre mu.
+template <typename T>
+__device__ void sh_colour_raw(const T mu[3], const double o[3], const float* a, T rgb[3]) {
+  const T dx = mu[0] - T(o[0]), dy = mu[1] - T(o[1]), dz = mu[2] - T(o[2]);
+  const T len = sqrt_d(dx * dx + dy * dy + dz * dz);
+  T Y[16];
+  sh_basis16<T>(dx / len, dy / len, dz / len, Y);
+  for (int c = 0; c < 3; ++c) {
+    T acc(0.5);
+    for (int k = 0; k < 16; ++k) acc = acc + Y[k] * T((double)a[3 * k + c]);
+    rgb[c] = acc;
+  }
+}
+
+// World-space camera centre o = -R^T t.
+__device__ __forceinline__ void camera_centre(const CamDev& c, double o[3]) {
+  for (int k = 0; k < 3; ++k) o[k] = -(c.m[k] * c.m[3] + c.m[4 + k] * c.m[7] + c.m[8 + k] * c.m[11]);
+}
+
 template <typename T>
 struct Geo {
   T mx, my, p1x, p1y, p2x, p2y, qx, qy, mz;
@@ -180,8 +236,8 @@ __global__ __launch_bounds__(256) void preprocess_kernel(const float* __restrict
                                                          const float* __restrict__ scales,
                                                          const float* __restrict__ opac,
                                                          const float* __restrict__ gammas,
-                                                         const float* __restrict__ colors, int64_t n, CamDev cam,
-                                                         uint32_t* __restrict__ depth_keys,
+                                                         const float* __restrict__ colors, int sh, int64_t n,
+                                                         CamDev cam, uint32_t* __restrict__ depth_keys,
                                                          uint32_t* __restrict__ tile_counts,
                                                          int4* __restrict__ rects, float4* __restrict__ records) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -191,9 +247,11 @@ __global__ __launch_bounds__(256) void preprocess_kernel(const float* __restrict
   const float fs[2] = {scales[2 * i], scales[2 * i + 1]};
   const float fo = opac[i];
   const float fg[2] = {gammas[2 * i], gammas[2 * i + 1]};
-  const float fc[3] = {colors[3 * i], colors[3 * i + 1], colors[3 * i + 2]};
+  const int nc = sh ? 48 : 3;  // colour values per surfel: RGB, or 16 SH coefficients per channel
+  const float* col = colors + (int64_t)nc * i;
   bool ok = true;
-  for (int k = 0; k < 3; ++k) ok &= finite_f(fm[k]) && finite_f(fc[k]);
+  for (int k = 0; k < nc; ++k) ok &= finite_f(col[k]);
+  for (int k = 0; k < 3; ++k) ok &= finite_f(fm[k]);
   for (int k = 0; k < 4; ++k) ok &= finite_f(fq[k]);
   for (int k = 0; k < 2; ++k) ok &= finite_f(fs[k]) && finite_f(fg[k]);
   ok &= finite_f(fo);
@@ -224,6 +282,13 @@ __global__ __launch_bounds__(256) void preprocess_kernel(const float* __restrict
     const double dq[4] = {fq[0], fq[1], fq[2], fq[3]};
     const double ds[2] = {fs[0], fs[1]};
     const Geo<double> g = record_geometry<double>(cam, mu, dq, ds);
+    float fc[3] = {col[0], col[1], col[2]};
+    if (sh) {
+      double o[3], rgb[3];
+      camera_centre(cam, o);
+      sh_colour_raw<double>(mu, o, col, rgb);
+      for (int c = 0; c < 3; ++c) fc[c] = (float)fmax(rgb[c], 0.0);
+    }
     if (!g.degenerate) {
       const double mxi = floor(g.mx), myi = floor(g.my);
       rec[0] = make_float4((float)mxi, (float)myi, (float)(0.5 - (g.mx - mxi)), (float)(0.5 - (g.my - myi)));
@@ -239,8 +304,9 @@ __global__ __launch_bounds__(256) void preprocess_kernel(const float* __restrict
 
 __global__ __launch_bounds__(256) void preprocess_backward_kernel(
     const float* __restrict__ means, const float* __restrict__ quats, const float* __restrict__ scales, int64_t n,
-    CamDev cam, const uint32_t* __restrict__ tile_counts, const float* __restrict__ rg, float* g_means,
-    float* g_quats, float* g_scales, float* g_opac, float* g_gammas, float* g_colors, float* g_blended) {
+    const float* __restrict__ colors, int sh, CamDev cam, const uint32_t* __restrict__ tile_counts,
+    const float* __restrict__ rg, float* g_means, float* g_quats, float* g_scales, float* g_opac, float* g_gammas,
+    float* g_colors, float* g_blended) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (tile_counts[i] == 0) return;
@@ -258,7 +324,35 @@ __global__ __launch_bounds__(256) void preprocess_backward_kernel(
     g_gammas[2 * i] += gr[10];
     g_gammas[2 * i + 1] += gr[11];
   }
-  if (g_colors) {
+  double sh_mu[3] = {0.0, 0.0, 0.0};  // gradient reaching mu through the view direction
+  if (sh) {
+    // c = max(0, sum_k Y_k(d) a_k + 0.5), d = (mu - o) / |mu - o|:
+    // dL/da_{3k+c} = [raw_c > 0] Y_k dL/dc, and dL/dmu by forward mode in mu.
+    const float* a = colors + (int64_t)48 * i;
+    double o[3];
+    camera_centre(cam, o);
+    const double m0[3] = {means[3 * i], means[3 * i + 1], means[3 * i + 2]};
+    double rgb[3];
+    sh_colour_raw<double>(m0, o, a, rgb);
+    double gc[3];
+    for (int c = 0; c < 3; ++c) gc[c] = rgb[c] > 0.0 ? (double)gr[12 + c] : 0.0;
+    if (g_colors) {
+      const double dx = m0[0] - o[0], dy = m0[1] - o[1], dz = m0[2] - o[2];
+      const double len = sqrt(dx * dx + dy * dy + dz * dz);
+      double Y[16];
+      sh_basis16<double>(dx / len, dy / len, dz / len, Y);
+      for (int k = 0; k < 16; ++k)
+        for (int c = 0; c < 3; ++c)
+          if (gc[c] != 0.0) g_colors[48 * i + 3 * k + c] += (float)(Y[k] * gc[c]);
+    }
+    for (int j = 0; j < 3; ++j) {
+      Dual m[3];
+      for (int k = 0; k < 3; ++k) m[k] = Dual(m0[k], k == j ? 1.0 : 0.0);
+      Dual c3[3];
+      sh_colour_raw<Dual>(m, o, a, c3);
+      sh_mu[j] = gc[0] * c3[0].d + gc[1] * c3[1].d + gc[2] * c3[2].d;
+    }
+  } else if (g_colors) {
     g_colors[3 * i] += gr[12];
     g_colors[3 * i + 1] += gr[13];
     g_colors[3 * i + 2] += gr[14];
@@ -277,6 +371,7 @@ __global__ __launch_bounds__(256) void preprocess_backward_kernel(
     out[dir] = gr[0] * g.mx.d + gr[1] * g.my.d + gr[2] * g.p1x.d + gr[3] * g.p1y.d + gr[4] * g.p2x.d +
                gr[5] * g.p2y.d + gr[6] * g.qx.d + gr[7] * g.qy.d + gr[8] * g.mz.d;
   }
+  for (int k = 0; k < 3; ++k) out[k] += sh_mu[k];
   if (g_means)
     for (int k = 0; k < 3; ++k) g_means[3 * i + k] += (float)out[k];
   if (g_quats)
@@ -288,24 +383,26 @@ __global__ __launch_bounds__(256) void preprocess_backward_kernel(
 }  // namespace
 
 hipError_t launch_preprocess(const float* means, const float* quats, const float* scales, const float* opac,
-                             const float* gammas, const float* colors, int64_t n, const CamDev& cam,
+                             const float* gammas, const float* colors, int sh, int64_t n, const CamDev& cam,
                              uint32_t* depth_keys, uint32_t* tile_counts, int4* rects, float4* records,
                              hipStream_t s) {
   if (n == 0) return hipSuccess;
   const int64_t blocks = (n + 255) / 256;
   hipLaunchKernelGGL(preprocess_kernel, dim3((unsigned)blocks), dim3(256), 0, s, means, quats, scales, opac, gammas,
-                     colors, n, cam, depth_keys, tile_counts, rects, records);
+                     colors, sh, n, cam, depth_keys, tile_counts, rects, records);
   return hipGetLastError();
 }
 
-hipError_t launch_preprocess_backward(const float* means, const float* quats, const float* scales, int64_t n,
-                                      const CamDev& cam, const uint32_t* tile_counts, const float* rec_grad,
-                                      float* g_means, float* g_quats, float* g_scales, float* g_opac,
-                                      float* g_gammas, float* g_colors, float* g_blended, hipStream_t s) {
+hipError_t launch_preprocess_backward(const float* means, const float* quats, const float* scales,
+                                      const float* colors, int sh, int64_t n, const CamDev& cam,
+                                      const uint32_t* tile_counts, const float* rec_grad, float* g_means,
+                                      float* g_quats, float* g_scales, float* g_opac, float* g_gammas,
+                                      float* g_colors, float* g_blended, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const int64_t blocks = (n + 255) / 256;
   hipLaunchKernelGGL(preprocess_backward_kernel, dim3((unsigned)blocks), dim3(256), 0, s, means, quats, scales, n,
-                     cam, tile_counts, rec_grad, g_means, g_quats, g_scales, g_opac, g_gammas, g_colors, g_blended);
+                     colors, sh, cam, tile_counts, rec_grad, g_means, g_quats, g_scales, g_opac, g_gammas, g_colors,
+                     g_blended);
   return hipGetLastError();
 }
 

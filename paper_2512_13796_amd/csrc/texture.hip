@@ -23,10 +23,13 @@
 //              rounded to BF16 between layers.
 //   FP32 form: v_mfma_f32_16x16x4_f32 (full FP32).
 // The backward recomputes the features and the MLP, back-propagates through
-// the MLP with the transposed weights, forms the weight gradients with a
-// per-wave LDS transpose (samples become the K index), accumulates them in
-// LDS per workgroup and adds them to global memory once, and scatters the
-// hash-grid gradient with FP32 atomics.
+// the MLP with the transposed weights, and forms the weight gradients from
+// per-unit activation tiles staged in LDS (samples become the K index of the
+// product), kept in MFMA accumulators for the whole launch and added to
+// global memory once. It writes each sample's per-level feature gradients;
+// the hash-grid gradient is then formed level by level without floating-point
+// global atomics (scatter_bin files corner records into per-workgroup slabs,
+// scatter_reduce sums each bucket's records in LDS).
 #include <hip/hip_fp16.h>
 #include <type_traits>
 #include <math.h>
@@ -111,16 +114,21 @@ __device__ __forceinline__ float load_w(const void* w, int idx) {
 // ------------------------------------------------------------------ weights in LDS
 // Operand slots. BF16 form: a slot is 64 lanes x 8 bf16 (one 16x16x32 A
 // operand). FP32 form: a slot is 64 lanes x 1 float (one 16x16x4 A operand).
-template <bool BF, int HID>
+// SH: the head has 48 outputs (degree-3 spherical-harmonics coefficients,
+// three 16-row tiles) instead of 3 (one tile, rows 0..2 used).
+template <bool BF, int HID, bool SH = false>
 struct WLayout {
   static constexpr int MT = HID / 16;
   static constexpr int HT = HID / 32;
+  static constexpr int OT = SH ? 3 : 1;        // head row tiles
+  static constexpr int NOUT = SH ? 48 : 3;     // head rows used
+  static constexpr int HO = (OT + 1) / 2;      // 32-deep K chunks of the head's transpose (BF16)
   // forward
   static constexpr int nA1 = BF ? MT : MT * 8;
   static constexpr int nA2 = BF ? MT * HT : MT * MT * 4;
-  static constexpr int nA3 = BF ? HT : MT * 4;
+  static constexpr int nA3 = BF ? HT * OT : MT * 4 * OT;
   // backward (transposed)
-  static constexpr int nA3T = BF ? MT : MT * 4;
+  static constexpr int nA3T = BF ? MT * HO : MT * 4 * OT;
   static constexpr int nA2T = BF ? MT * HT : MT * MT * 4;
   static constexpr int nA1T = BF ? 2 * HT : 2 * MT * 4;
   static constexpr int oA1 = 0, oA2 = oA1 + nA1, oA3 = oA2 + nA2;
@@ -131,10 +139,11 @@ struct WLayout {
 };
 
 // Value of element e of lane (g, c) in operand slot `slot`.
-template <bool BF, int HID>
+template <bool BF, int HID, bool SH>
 __device__ float weight_operand(int slot, int g, int c, int e, const void* w1, const void* w2, const void* w3,
                                 int in_dim) {
-  using LY = WLayout<BF, HID>;
+  using LY = WLayout<BF, HID, SH>;
+  constexpr int NOUT = LY::NOUT;
   constexpr int MT = LY::MT;
   if constexpr (BF) {
     if (slot < LY::oA2) {  // A1[mt]
@@ -143,12 +152,12 @@ __device__ float weight_operand(int slot, int g, int c, int e, const void* w1, c
     } else if (slot < LY::oA3) {  // A2[mt][h]
       const int q = slot - LY::oA2, mt = q / LY::HT, h = q % LY::HT;
       return load_w<BF>(w2, (16 * mt + c) * HID + hid_index(h, g, e));
-    } else if (slot < LY::oA3T) {  // A3[h]
-      const int h = slot - LY::oA3;
-      return c < 3 ? load_w<BF>(w3, c * HID + hid_index(h, g, e)) : 0.f;
-    } else if (slot < LY::oA2T) {  // A3T[mt]
-      const int mt = slot - LY::oA3T;
-      return (g == 0 && e < 3) ? load_w<BF>(w3, e * HID + 16 * mt + c) : 0.f;
+    } else if (slot < LY::oA3T) {  // A3[ot][h]
+      const int q = slot - LY::oA3, ot = q / LY::HT, h = q % LY::HT, row = 16 * ot + c;
+      return row < NOUT ? load_w<BF>(w3, row * HID + hid_index(h, g, e)) : 0.f;
+    } else if (slot < LY::oA2T) {  // A3T[mt][ho]
+      const int q = slot - LY::oA3T, mt = q / LY::HO, ho = q % LY::HO, o = hid_index(ho, g, e);
+      return o < NOUT ? load_w<BF>(w3, o * HID + 16 * mt + c) : 0.f;
     } else if (slot < LY::oA1T) {  // A2T[mt][h]
       const int q = slot - LY::oA2T, mt = q / LY::HT, h = q % LY::HT;
       return load_w<BF>(w2, hid_index(h, g, e) * HID + 16 * mt + c);
@@ -164,12 +173,13 @@ __device__ float weight_operand(int slot, int g, int c, int e, const void* w1, c
     } else if (slot < LY::oA3) {  // A2[mt][mi][r]
       const int q = slot - LY::oA2, mt = q / (MT * 4), mi = (q / 4) % MT, r = q % 4;
       return load_w<BF>(w2, (16 * mt + c) * HID + 16 * mi + 4 * g + r);
-    } else if (slot < LY::oA3T) {  // A3[mi][r]
-      const int q = slot - LY::oA3, mi = q / 4, r = q % 4;
-      return c < 3 ? load_w<BF>(w3, c * HID + 16 * mi + 4 * g + r) : 0.f;
-    } else if (slot < LY::oA2T) {  // A3T[mt][r]
-      const int q = slot - LY::oA3T, mt = q / 4, r = q % 4, o = 4 * g + r;
-      return o < 3 ? load_w<BF>(w3, o * HID + 16 * mt + c) : 0.f;
+    } else if (slot < LY::oA3T) {  // A3[ot][mi][r]
+      const int q = slot - LY::oA3, ot = q / (MT * 4), mi = (q / 4) % MT, r = q % 4, row = 16 * ot + c;
+      return row < NOUT ? load_w<BF>(w3, row * HID + 16 * mi + 4 * g + r) : 0.f;
+    } else if (slot < LY::oA2T) {  // A3T[mt][ot][r]
+      const int q = slot - LY::oA3T, mt = q / (LY::OT * 4), ot = (q / 4) % LY::OT, r = q % 4;
+      const int o = 16 * ot + 4 * g + r;
+      return o < NOUT ? load_w<BF>(w3, o * HID + 16 * mt + c) : 0.f;
     } else if (slot < LY::oA1T) {  // A2T[mt][mi][r]
       const int q = slot - LY::oA2T, mt = q / (MT * 4), mi = (q / 4) % MT, r = q % 4;
       return load_w<BF>(w2, (16 * mi + 4 * g + r) * HID + 16 * mt + c);
@@ -183,7 +193,7 @@ __device__ float weight_operand(int slot, int g, int c, int e, const void* w1, c
 
 // Writes operand slots [0, n_slots) to dst (LDS or global memory); this
 // thread handles elements first, first + stride, ...
-template <bool BF, int HID>
+template <bool BF, int HID, bool SH>
 __device__ void stage_weights(unsigned char* dst, int n_slots, const void* w1, const void* w2, const void* w3,
                               int in_dim, int first = threadIdx.x, int stride = kTexThreads) {
   constexpr int per = BF ? 8 : 1;
@@ -192,7 +202,7 @@ __device__ void stage_weights(unsigned char* dst, int n_slots, const void* w1, c
     const int slot = i / (64 * per);
     const int lane = (i / per) % 64;
     const int e = i % per;
-    const float v = weight_operand<BF, HID>(slot, lane >> 4, lane & 15, e, w1, w2, w3, in_dim);
+    const float v = weight_operand<BF, HID, SH>(slot, lane >> 4, lane & 15, e, w1, w2, w3, in_dim);
     if constexpr (BF) {
       reinterpret_cast<short*>(dst)[i] = f2bf(v);
     } else {
@@ -203,16 +213,16 @@ __device__ void stage_weights(unsigned char* dst, int n_slots, const void* w1, c
 
 // The backward's operand slots in global memory, for widths whose slots do
 // not fit in LDS next to the weight-gradient accumulators.
-template <bool BF, int HID>
+template <bool BF, int HID, bool SH>
 __global__ void stage_weight_operands_kernel(unsigned char* wop, const void* w1, const void* w2, const void* w3,
                                              int in_dim) {
-  stage_weights<BF, HID>(wop, WLayout<BF, HID>::nAll, w1, w2, w3, in_dim, blockIdx.x * blockDim.x + threadIdx.x,
+  stage_weights<BF, HID, SH>(wop, WLayout<BF, HID, SH>::nAll, w1, w2, w3, in_dim, blockIdx.x * blockDim.x + threadIdx.x,
                          gridDim.x * blockDim.x);
 }
 
-static_assert(WLayout<false, 128>::nAll * WLayout<false, 128>::slot_bytes <= (int)kWeightOperandBytes,
+static_assert(WLayout<false, 128, true>::nAll * WLayout<false, 128, true>::slot_bytes <= (int)kWeightOperandBytes,
               "operand slots exceed their workspace section");
-static_assert(WLayout<true, 128>::nAll * WLayout<true, 128>::slot_bytes <= (int)kWeightOperandBytes,
+static_assert(WLayout<true, 128, true>::nAll * WLayout<true, 128, true>::slot_bytes <= (int)kWeightOperandBytes,
               "operand slots exceed their workspace section");
 
 template <bool BF>
@@ -246,11 +256,13 @@ __device__ __forceinline__ f4 relu4(f4 x) {
 }
 
 // MLP forward for 16 samples: z[8] are this lane's features; h1/h2 receive
-// the post-ReLU hidden tiles (rows 16 mt + 4 g + r); returns the head tile
-// (rows 4 g + r; logits in rows 0..2 of lane group 0).
-template <bool BF, int HID>
-__device__ __forceinline__ f4 mlp_forward(const unsigned char* lds, int lane, const float z[8], f4* h1, f4* h2) {
-  using LY = WLayout<BF, HID>;
+// the post-ReLU hidden tiles (rows 16 mt + 4 g + r); o receives the head
+// tiles (rows 16 ot + 4 g + r; RGB logits in rows 0..2 of lane group 0, or
+// the 48 SH coefficients).
+template <bool BF, int HID, bool SH>
+__device__ __forceinline__ void mlp_forward(const unsigned char* lds, int lane, const float z[8], f4* h1, f4* h2,
+                                            f4* o) {
+  using LY = WLayout<BF, HID, SH>;
   constexpr int MT = LY::MT;
   const f4 zero = {0.f, 0.f, 0.f, 0.f};
   if constexpr (BF) {
@@ -271,10 +283,13 @@ __device__ __forceinline__ f4 mlp_forward(const unsigned char* lds, int lane, co
     s8 b2[HT];
 #pragma unroll
     for (int h = 0; h < HT; ++h) b2[h] = pack_tiles(h2[2 * h], h2[2 * h + 1]);
-    f4 o = zero;
 #pragma unroll
-    for (int h = 0; h < HT; ++h) o = mfma_bf16_k32(Operand<true>::get(lds, LY::oA3 + h, lane), b2[h], o);
-    return o;
+    for (int ot = 0; ot < LY::OT; ++ot) {
+      f4 acc = zero;
+#pragma unroll
+      for (int h = 0; h < HT; ++h) acc = mfma_bf16_k32(Operand<true>::get(lds, LY::oA3 + ot * HT + h, lane), b2[h], acc);
+      o[ot] = acc;
+    }
   } else {
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
@@ -293,13 +308,94 @@ __device__ __forceinline__ f4 mlp_forward(const unsigned char* lds, int lane, co
           acc = mfma_f32_k4(Operand<false>::get(lds, LY::oA2 + (mt * MT + mi) * 4 + r, lane), h1[mi][r], acc);
       h2[mt] = relu4(acc);
     }
-    f4 o = zero;
 #pragma unroll
-    for (int mi = 0; mi < MT; ++mi)
+    for (int ot = 0; ot < LY::OT; ++ot) {
+      f4 acc = zero;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) o = mfma_f32_k4(Operand<false>::get(lds, LY::oA3 + mi * 4 + r, lane), h2[mi][r], o);
-    return o;
+      for (int mi = 0; mi < MT; ++mi)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          acc = mfma_f32_k4(Operand<false>::get(lds, LY::oA3 + (ot * MT + mi) * 4 + r, lane), h2[mi][r], acc);
+      o[ot] = acc;
+    }
   }
+}
+
+// ------------------------------------------------------------------ SH head
+// Degree-3 real spherical harmonics of a unit direction (Representation,
+// Appearance): the usual Cartesian forms with orthonormal constants.
+__device__ __forceinline__ void sh_basis16(float x, float y, float z, float Y[16]) {
+  const float xx = x * x, yy = y * y, zz = z * z;
+  Y[0] = 0.28209479177387814f;
+  Y[1] = -0.4886025119029199f * y;
+  Y[2] = 0.4886025119029199f * z;
+  Y[3] = -0.4886025119029199f * x;
+  Y[4] = 1.0925484305920792f * (x * y);
+  Y[5] = -1.0925484305920792f * (y * z);
+  Y[6] = 0.31539156525252005f * (2.0f * zz - xx - yy);
+  Y[7] = -1.0925484305920792f * (x * z);
+  Y[8] = 0.5462742152960396f * (xx - yy);
+  Y[9] = -0.5900435899266435f * y * (3.0f * xx - yy);
+  Y[10] = 2.890611442640554f * (x * y) * z;
+  Y[11] = -0.4570457994644658f * y * (4.0f * zz - xx - yy);
+  Y[12] = 0.3731763325901154f * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+  Y[13] = -0.4570457994644658f * x * (4.0f * zz - xx - yy);
+  Y[14] = 1.445305721320277f * z * (xx - yy);
+  Y[15] = -0.5900435899266435f * x * (xx - 3.0f * yy);
+}
+
+// Head row 16 ot + 4 g + r holds coefficient k = row / 3 of channel row % 3
+// ([16][3] layout). For a fixed (ot, r) the lane group g picks one of four
+// rows known at compile time: select Y_k and the channel without indexing a
+// register array at run time.
+template <int OT_, int R>
+__device__ __forceinline__ float sh_row_basis(const float Y[16], int g) {
+  constexpr int r0 = 16 * OT_ + R;
+  return g == 0 ? Y[r0 / 3] : g == 1 ? Y[(r0 + 4) / 3] : g == 2 ? Y[(r0 + 8) / 3] : Y[(r0 + 12) / 3];
+}
+template <int OT_, int R>
+__device__ __forceinline__ int sh_row_channel(int g) {
+  constexpr int r0 = 16 * OT_ + R;
+  return g == 0 ? r0 % 3 : g == 1 ? (r0 + 4) % 3 : g == 2 ? (r0 + 8) % 3 : (r0 + 12) % 3;
+}
+
+// The three channels before the clamp, sum_k Y_k a_{3k+c} + 0.5, for the 16
+// samples of a wave (every lane of a sample's column gets them): each lane
+// sums its 12 head rows, then the four lane groups add up.
+__device__ __forceinline__ void sh_decode(const f4 o[3], const float Y[16], int g, float raw[3]) {
+  float p[3] = {0.f, 0.f, 0.f};
+#define NX_SH_ROW(OT_, R)                                                \
+  {                                                                      \
+    const float v = sh_row_basis<OT_, R>(Y, g) * o[OT_][R];              \
+    const int ch = sh_row_channel<OT_, R>(g);                            \
+    p[0] += ch == 0 ? v : 0.f;                                           \
+    p[1] += ch == 1 ? v : 0.f;                                           \
+    p[2] += ch == 2 ? v : 0.f;                                           \
+  }
+  NX_SH_ROW(0, 0) NX_SH_ROW(0, 1) NX_SH_ROW(0, 2) NX_SH_ROW(0, 3)
+  NX_SH_ROW(1, 0) NX_SH_ROW(1, 1) NX_SH_ROW(1, 2) NX_SH_ROW(1, 3)
+  NX_SH_ROW(2, 0) NX_SH_ROW(2, 1) NX_SH_ROW(2, 2) NX_SH_ROW(2, 3)
+#undef NX_SH_ROW
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    p[ch] += __shfl_xor(p[ch], 16, 64);
+    p[ch] += __shfl_xor(p[ch], 32, 64);
+    raw[ch] = p[ch] + 0.5f;
+  }
+}
+
+// dL/d(head rows) of this lane: Y_k dL/dc for the row's channel c.
+__device__ __forceinline__ void sh_head_grad(const float Y[16], int g, const float dc[3], f4 dlog[3]) {
+#define NX_SH_G(OT_, R)                                                  \
+  {                                                                      \
+    const int ch = sh_row_channel<OT_, R>(g);                            \
+    const float d = ch == 0 ? dc[0] : (ch == 1 ? dc[1] : dc[2]);         \
+    dlog[OT_][R] = sh_row_basis<OT_, R>(Y, g) * d;                       \
+  }
+  NX_SH_G(0, 0) NX_SH_G(0, 1) NX_SH_G(0, 2) NX_SH_G(0, 3)
+  NX_SH_G(1, 0) NX_SH_G(1, 1) NX_SH_G(1, 2) NX_SH_G(1, 3)
+  NX_SH_G(2, 0) NX_SH_G(2, 1) NX_SH_G(2, 2) NX_SH_G(2, 3)
+#undef NX_SH_G
 }
 
 struct SampleInfo {
@@ -513,8 +609,8 @@ __device__ __forceinline__ void gather_lane(const GridDev& gd, const void* table
   }
 }
 
-template <int TDT, bool BF, int HID>
-__global__ __launch_bounds__(kTexThreads, (HID <= 64 && BF && TDT != NX_F32) ? 3 : 1) void texture_forward_kernel(GridDev gd, const void* __restrict__ table,
+template <int TDT, bool BF, int HID, bool SH>
+__global__ __launch_bounds__(kTexThreads, (HID <= 64 && BF && TDT != NX_F32 && !SH) ? 3 : 1) void texture_forward_kernel(GridDev gd, const void* __restrict__ table,
                                                                       const void* w1, const void* w2, const void* w3,
                                                                       int in_dim, int K, int log2K, int64_t n_samples,
                                                                       const int32_t* __restrict__ ids,
@@ -526,10 +622,10 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 && BF && TDT != NX_F32) ? 3
                                                                       int32_t* __restrict__ cells,
                                                                       uint32_t* __restrict__ relu_masks,
                                                                       float* __restrict__ features) {
-  using LY = WLayout<BF, HID>;
+  using LY = WLayout<BF, HID, SH>;
   constexpr int MT = LY::MT;
   __shared__ __attribute__((aligned(16))) unsigned char lds[LY::nFwd * LY::slot_bytes];
-  stage_weights<BF, HID>(lds, LY::nFwd, w1, w2, w3, in_dim);
+  stage_weights<BF, HID, SH>(lds, LY::nFwd, w1, w2, w3, in_dim);
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, c = lane & 15;
@@ -566,8 +662,22 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 && BF && TDT != NX_F32) ? 3
           }
         }
       }
-      f4 h1[MT], h2[MT];
-      const f4 o = mlp_forward<BF, HID>(lds, lane, z, h1, h2);
+      f4 h1[MT], h2[MT], o[LY::OT];
+      mlp_forward<BF, HID, SH>(lds, lane, z, h1, h2, o);
+      // the sample's texture: sigmoid of the RGB head (rows 0..2 of lane
+      // group 0), or the SH coefficients decoded along the unit ray
+      float tv[3];
+      if constexpr (SH) {
+        const float inv = rsqrtf(si.dx * si.dx + si.dy * si.dy + si.dz * si.dz);
+        float Y[16], raw[3];
+        sh_basis16(si.dx * inv, si.dy * inv, si.dz * inv, Y);
+        sh_decode(o, Y, g, raw);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) tv[r] = fmaxf(raw[r], 0.0f);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) tv[r] = rcp(1.0f + __expf(-o[0][r]));
+      }
       if (relu_masks) {
         // Unit 16 mt + 4 g + r of this lane's sample -> word mt / 2, bit 16 (mt % 2) + 4 g + r.
         constexpr int NW = HID / 32;
@@ -604,7 +714,7 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 && BF && TDT != NX_F32) ? 3
       if (g == 0 && si.valid) {
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
-          const float t = si.has ? rcp(1.0f + __expf(-o[r])) : 0.0f;
+          const float t = si.has ? tv[r] : 0.0f;
           tex[si.s * 3 + r] = t;
           contrib[r] = fmaf(si.W, t, contrib[r]);
         }
@@ -679,10 +789,11 @@ __device__ __forceinline__ void weight_grad_accum(const unsigned char* Y, const 
 // [rows][16 samples] in the MLP's storage precision. Rows: Y3 = dL/dlogit
 // (16, rows 0..2 used), X3 = h2, Y2 = dL/dh2, X2 = h1, Y1 = dL/dh1 (HID each),
 // X1 = z (32).
-template <bool BF, int HID>
+template <bool BF, int HID, bool SH>
 struct UnitTiles {
   static constexpr int elem = BF ? 2 : 4;
-  static constexpr int oY3 = 0, oX3 = 16, oY2 = oX3 + HID, oX2 = oY2 + HID, oY1 = oX2 + HID, oX1 = oY1 + HID;
+  static constexpr int oY3 = 0, oX3 = 16 * WLayout<BF, HID, SH>::OT, oY2 = oX3 + HID, oX2 = oY2 + HID,
+                       oY1 = oX2 + HID, oX1 = oY1 + HID;
   static constexpr int rows = oX1 + kInPad;
   static constexpr int bytes = rows * 16 * elem;
 };
@@ -697,16 +808,17 @@ struct UnitTiles {
 // its own quarter of dW1, dW2 and dW3 (row tiles split across the waves),
 // which it keeps in MFMA accumulator registers for the whole launch and adds
 // to global memory once at the end.
-template <int TDT, bool BF, int HID, bool WLDS>
+template <int TDT, bool BF, int HID, bool SH, bool WLDS>
 __global__ __launch_bounds__(kTexThreads, (HID <= 64 || BF) ? 2 : 1) void texture_backward_kernel(
     GridDev gd, const void* __restrict__ table, const void* w1, const void* w2, const void* w3,
     const unsigned char* __restrict__ wop, int in_dim, int K,
     int log2K, int64_t n_samples, const int32_t* __restrict__ ids, const float* __restrict__ depths,
     const float* __restrict__ weights, const float* __restrict__ grad_image, const float* __restrict__ grad_tex,
     float2* __restrict__ feat_grad, float* g_w1, float* g_w2, float* g_w3, float* __restrict__ grad_depth) {
-  using LY = WLayout<BF, HID>;
-  using UT = UnitTiles<BF, HID>;
+  using LY = WLayout<BF, HID, SH>;
+  using UT = UnitTiles<BF, HID, SH>;
   constexpr int MT = LY::MT;
+  constexpr int OT = LY::OT;
   constexpr int RT = MT / kWaves;           // row tiles of dW1 / dW2 per wave
   constexpr int CT3 = MT / kWaves;          // column tiles of dW3 per wave
   static_assert(RT >= 1 && RT * kWaves == MT, "hidden width must be a multiple of 64");
@@ -714,7 +826,7 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 || BF) ? 2 : 1) void textur
   __shared__ __attribute__((aligned(16))) unsigned char tiles[kWaves * UT::bytes];
   const unsigned char* W;
   if constexpr (WLDS) {
-    stage_weights<BF, HID>(lds, LY::nAll, w1, w2, w3, in_dim);
+    stage_weights<BF, HID, SH>(lds, LY::nAll, w1, w2, w3, in_dim);
     W = lds;
   } else {
     W = wop;
@@ -728,9 +840,9 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 || BF) ? 2 : 1) void textur
   const int64_t n_q = n_patches(gd);
   const int64_t n_units = n_q * K;
   const f4 zero = {0.f, 0.f, 0.f, 0.f};
-  f4 accW3[CT3], accW2[RT * MT], accW1[RT * 2];
+  f4 accW3[OT * CT3], accW2[RT * MT], accW1[RT * 2];
 #pragma unroll
-  for (int i = 0; i < CT3; ++i) accW3[i] = zero;
+  for (int i = 0; i < OT * CT3; ++i) accW3[i] = zero;
 #pragma unroll
   for (int i = 0; i < RT * MT; ++i) accW2[i] = zero;
 #pragma unroll
@@ -758,36 +870,60 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 || BF) ? 2 : 1) void textur
         z[2 * i + 1] = fraw[2 * i + 1] * delta[i];
       }
       // ---- MLP forward, keeping activations
-      f4 h1[MT], h2[MT];
-      const f4 o = mlp_forward<BF, HID>(W, lane, z, h1, h2);
-      // ---- head: dL/dlogit for rows 0..2 of lane group 0
-      f4 dlog = zero;
-      if (g == 0 && si.has) {
-        const float g0 = grad_image[si.p * 3], g1 = grad_image[si.p * 3 + 1], g2 = grad_image[si.p * 3 + 2];
-        const float gi[3] = {g0, g1, g2};
+      f4 h1[MT], h2[MT], o[OT];
+      mlp_forward<BF, HID, SH>(W, lane, z, h1, h2, o);
+      // ---- head: dL/d(head rows): RGB logits in rows 0..2 of lane group 0,
+      // or the 48 SH coefficients (every lane group holds 12 of them)
+      f4 dlog[OT];
 #pragma unroll
-        for (int r = 0; r < 3; ++r) {
-          const float t = rcp(1.0f + __expf(-o[r]));
-          float dt = si.W * gi[r];
-          if (grad_tex) dt += grad_tex[si.s * 3 + r];
-          dlog[r] = dt * t * (1.0f - t);
+      for (int ot = 0; ot < OT; ++ot) dlog[ot] = zero;
+      if constexpr (SH) {
+        const float inv = rsqrtf(si.dx * si.dx + si.dy * si.dy + si.dz * si.dz);
+        float Y[16], raw[3];
+        sh_basis16(si.dx * inv, si.dy * inv, si.dz * inv, Y);
+        sh_decode(o, Y, g, raw);
+        if (si.has) {
+          float dc[3];
+#pragma unroll
+          for (int r = 0; r < 3; ++r) {
+            float dt = si.W * grad_image[si.p * 3 + r];
+            if (grad_tex) dt += grad_tex[si.s * 3 + r];
+            dc[r] = raw[r] > 0.0f ? dt : 0.0f;
+          }
+          sh_head_grad(Y, g, dc, dlog);
+        }
+      } else {
+        if (g == 0 && si.has) {
+          const float g0 = grad_image[si.p * 3], g1 = grad_image[si.p * 3 + 1], g2 = grad_image[si.p * 3 + 2];
+          const float gi[3] = {g0, g1, g2};
+#pragma unroll
+          for (int r = 0; r < 3; ++r) {
+            const float t = rcp(1.0f + __expf(-o[0][r]));
+            float dt = si.W * gi[r];
+            if (grad_tex) dt += grad_tex[si.s * 3 + r];
+            dlog[0][r] = dt * t * (1.0f - t);
+          }
         }
       }
       // ---- MLP backward, layer by layer; each layer's two weight-gradient
       // factors go to this wave's tiles as soon as they exist, so the
       // activations die early (h2 after layer 3, dH2 and h1 after layer 2).
       f4 dzt[2];
-      put_rows4<BF>(T, UT::oY3 + 4 * g, c, dlog);
+#pragma unroll
+      for (int ot = 0; ot < OT; ++ot) put_rows4<BF>(T, UT::oY3 + 16 * ot + 4 * g, c, dlog[ot]);
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) put_rows4<BF>(T, UT::oX3 + 16 * mt + 4 * g, c, h2[mt]);
       f4 dh2[MT];
       if constexpr (BF) {
-        s8 bd;
+        constexpr int HO = LY::HO;
+        s8 bd[HO];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) bd[e] = e < 4 ? f2bf(dlog[e]) : (short)0;
+        for (int ho = 0; ho < HO; ++ho) bd[ho] = pack_tiles(dlog[2 * ho], 2 * ho + 1 < OT ? dlog[2 * ho + 1] : zero);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-          f4 a = mfma_bf16_k32(Operand<true>::get(W, LY::oA3T + mt, lane), bd, zero);
+          f4 a = zero;
+#pragma unroll
+          for (int ho = 0; ho < HO; ++ho) a = mfma_bf16_k32(Operand<true>::get(W, LY::oA3T + mt * HO + ho, lane), bd[ho], a);
 #pragma unroll
           for (int r = 0; r < 4; ++r) a[r] = h2[mt][r] > 0.f ? a[r] : 0.f;
           dh2[mt] = a;
@@ -797,7 +933,10 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 || BF) ? 2 : 1) void textur
         for (int mt = 0; mt < MT; ++mt) {
           f4 a = zero;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) a = mfma_f32_k4(Operand<false>::get(W, LY::oA3T + mt * 4 + r, lane), dlog[r], a);
+          for (int ot = 0; ot < OT; ++ot)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              a = mfma_f32_k4(Operand<false>::get(W, LY::oA3T + (mt * OT + ot) * 4 + r, lane), dlog[ot][r], a);
 #pragma unroll
           for (int r = 0; r < 4; ++r) a[r] = h2[mt][r] > 0.f ? a[r] : 0.f;
           dh2[mt] = a;
@@ -891,7 +1030,7 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 || BF) ? 2 : 1) void textur
 #pragma unroll 1
     for (int u = 0; u < kWaves; ++u) {
       const unsigned char* U = tiles + u * UT::bytes;
-      weight_grad_accum<BF, 1, CT3>(row_ptr(U, UT::oY3), row_ptr(U, UT::oX3 + 16 * CT3 * wave), accW3, lane);
+      weight_grad_accum<BF, OT, CT3>(row_ptr(U, UT::oY3), row_ptr(U, UT::oX3 + 16 * CT3 * wave), accW3, lane);
       weight_grad_accum<BF, RT, MT>(row_ptr(U, UT::oY2 + 16 * RT * wave), row_ptr(U, UT::oX2), accW2, lane);
       weight_grad_accum<BF, RT, 2>(row_ptr(U, UT::oY1 + 16 * RT * wave), row_ptr(U, UT::oX1), accW1, lane);
     }
@@ -899,13 +1038,15 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 || BF) ? 2 : 1) void textur
   }
   // ---- add this wave's weight-gradient tiles to global memory
 #pragma unroll
-  for (int mi = 0; mi < CT3; ++mi)
+  for (int ot = 0; ot < OT; ++ot)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = 4 * g + r, col = 16 * (CT3 * wave + mi) + c;
-      const float v = accW3[mi][r];
-      if (g_w3 && row < 3 && v != 0.0f) unsafeAtomicAdd(&g_w3[row * HID + col], v);
-    }
+    for (int mi = 0; mi < CT3; ++mi)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * ot + 4 * g + r, col = 16 * (CT3 * wave + mi) + c;
+        const float v = accW3[ot * CT3 + mi][r];
+        if (g_w3 && row < LY::NOUT && v != 0.0f) unsafeAtomicAdd(&g_w3[row * HID + col], v);
+      }
 #pragma unroll
   for (int mo = 0; mo < RT; ++mo) {
 #pragma unroll
@@ -934,17 +1075,18 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 || BF) ? 2 : 1) void textur
 // use no floating-point global atomics.
 //
 // scatter_bin: one task is one level over a block of 4x4-pixel patches (all
-// K slots). Each corner contribution becomes a record (entry, 2 features)
-// filed under its bucket, a fixed range of 2^bucket_log2 table entries: the
-// block counts its records per bucket in LDS, reserves space in every bucket
-// it touches with one global cursor add, and writes the records there. Where
-// all samples of a 16-lane row lie in one cell, the row's contributions are
-// summed first, leaving 8 records instead of 128.
+// K slots). Each wave sorts its 128 samples by cell (unless no neighbouring
+// samples share one) and sums runs of equal cells; every run files 8 corner
+// records (entry, 2 values) under their buckets, fixed ranges of
+// 2^bucket_log2 table entries. The block ranks its records per bucket with
+// LDS counters, groups them by bucket in LDS and appends them to the
+// workgroup's own slab of each bucket (slab cursors stay in LDS for the whole
+// launch, so filing needs no global atomics); at the end the workgroup writes
+// its (slab start, count) per bucket into the slab table.
 //
-// scatter_reduce: one workgroup per bucket sums the bucket's records into a
-// dense LDS array and adds it to its range of the gradient table, which no
-// other workgroup writes; it also clears the bucket's cursor for the next
-// level.
+// scatter_reduce: one workgroup per bucket walks the bucket's column of the
+// slab table, sums the records into a dense LDS array and adds it to its
+// range of the gradient table, which no other workgroup writes.
 //
 // Measured on this chip: LDS float atomics (ds_add_f32) retire about one lane
 // every three clocks per CU, integer LDS atomics about ten lanes per clock and
@@ -955,7 +1097,7 @@ constexpr int kReduceThreads = 1024;
 constexpr int kReduceMaxLog2 = 13;  // LDS pairs per bucket in scatter_reduce
 constexpr int kUnitsPerRow = kScatUnits / (kScatThreads / 16);
 static_assert(kUnitsPerRow * (kScatThreads / 16) == kScatUnits, "units per task must fill the rows evenly");
-constexpr int kMaxCasRounds = 256;
+constexpr int kMaxCasRounds = 256;  // default bound of lds_add_pair's retries
 
 __device__ __forceinline__ unsigned long long pair_plus(unsigned long long old, float a, float b) {
   const float lo = __uint_as_float((uint32_t)old) + a;
@@ -964,11 +1106,11 @@ __device__ __forceinline__ unsigned long long pair_plus(unsigned long long old, 
 }
 
 // Adds (a, b) to the pair at p with a compare-and-swap loop; false if it lost
-// kMaxCasRounds races in a row (the caller then adds to global memory).
-__device__ __forceinline__ bool lds_add_pair(unsigned long long* p, float a, float b) {
+// `rounds` races in a row (the caller then adds to global memory).
+__device__ __forceinline__ bool lds_add_pair(unsigned long long* p, float a, float b, int rounds) {
   unsigned long long old = *p;
 #pragma unroll 1
-  for (int r = 0; r < kMaxCasRounds; ++r) {
+  for (int r = 0; r < rounds; ++r) {
     const unsigned long long prev = atomicCAS(p, old, pair_plus(old, a, b));
     if (prev == old) return true;
     old = prev;
@@ -1005,6 +1147,8 @@ constexpr int kDppQuadXor1 = 0xB1;   // quad_perm [1,0,3,2]
 constexpr int kDppQuadXor2 = 0x4E;   // quad_perm [2,3,0,1]
 constexpr int kDppRowRor8 = 0x128;   // rotate by 8 within 16 lanes = xor 8
 constexpr int kDppRowShr1 = 0x111;
+constexpr int kDppRowShl2 = 0x102;   // lane i reads lane i + 2 within its row of 16
+constexpr int kDppRowShl8 = 0x108;   // lane i reads lane i + 8 within its row of 16
 constexpr int kDppWaveShr1 = 0x138;  // lane i reads lane i - 1
 constexpr int kDppWaveShl1 = 0x130;  // lane i reads lane i + 1
 constexpr int kDppRowBcast15 = 0x142;
@@ -1164,9 +1308,22 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
     __syncthreads();
     // 2. bitonic sort of (key, sample) over each wave's 128 samples (the
     // wave's two patches, all slots); equal cells in different waves stay
-    // separate records, which only costs a few duplicates at coarse levels
+    // separate records, which only costs a few duplicates at coarse levels.
+    // In pixel order a lane holds two horizontally adjacent pixels of one
+    // slot, lane + 2 the pixels below them and lane + 8 the same pixels at the
+    // next slot. When no such pair shares a cell (fine levels: a pixel spans
+    // a cell or more), sorting would gather next to nothing, and the wave
+    // keeps pixel order: runs of equal cells are still summed where they are
+    // adjacent, and the others file separate records, which the reduction
+    // adds up like any others.
     uint32_t key[2] = {skey[p0], skey[p0 + 1]};
-    bitonic_sort_regs<2>(key, p0);
+    {
+      const uint32_t h0 = key[0] >> 7, h1 = key[1] >> 7;
+      const uint32_t below = dpp_u<kDppRowShl2>(h0), next_slot = dpp_u<kDppRowShl8>(h0);
+      const bool live0 = h0 != kInactiveKey;
+      const bool shared = live0 && (h0 == h1 || ((lane & 15) < 14 && h0 == below) || ((lane & 15) < 8 && h0 == next_slot));
+      if (__any(shared)) bitonic_sort_regs<2>(key, p0);
+    }
     // 3. segments of equal cells along the sorted order, summed within each wave
     bool live[2];
     int cx[2], cy[2], cz[2];
@@ -1337,7 +1494,8 @@ __device__ __forceinline__ void wave_sort_by_key(uint32_t& key, float& a, float&
 #undef NX_WS_STAGE
 }
 
-__global__ __launch_bounds__(kReduceThreads) void scatter_reduce_kernel(int bucket_log2, int coarse, int64_t n_rows,
+__global__ __launch_bounds__(kReduceThreads) void scatter_reduce_kernel(int bucket_log2, int coarse, int cas_rounds,
+                                                                       int64_t n_rows,
                                                                        const uint2* __restrict__ slab_table,
                                                                        const uint16_t* __restrict__ rec_key,
                                                                        const float2* __restrict__ rec_val,
@@ -1372,7 +1530,7 @@ __global__ __launch_bounds__(kReduceThreads) void scatter_reduce_kernel(int buck
         const uint32_t prev = dpp_u<kDppWaveShr1>(key), next = dpp_u<kDppWaveShl1>(key);
         float s2[2] = {v.x, v.y};
         segmented_scan<2>(s2, lane == 0 || prev != key);
-        if (key != 0xFFFFFFFFu && (lane == 63 || next != key) && !lds_add_pair(&acc[key], s2[0], s2[1])) {
+        if (key != 0xFFFFFFFFu && (lane == 63 || next != key) && !lds_add_pair(&acc[key], s2[0], s2[1], cas_rounds)) {
           unsafeAtomicAdd(&out[key].x, s2[0]);
           unsafeAtomicAdd(&out[key].y, s2[1]);
         }
@@ -1396,7 +1554,7 @@ __global__ __launch_bounds__(kReduceThreads) void scatter_reduce_kernel(int buck
       }
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
-        if (i0 + 16 * u < sl.y && !lds_add_pair(&acc[k[u]], v[u].x, v[u].y)) {
+        if (i0 + 16 * u < sl.y && !lds_add_pair(&acc[k[u]], v[u].x, v[u].y, cas_rounds)) {
           unsafeAtomicAdd(&out[k[u]].x, v[u].x);
           unsafeAtomicAdd(&out[k[u]].y, v[u].y);
         }
@@ -1427,7 +1585,7 @@ int ilog2(int k) {
   return r;
 }
 
-template <int TDT, bool BF, int HID>
+template <int TDT, bool BF, int HID, bool SH>
 hipError_t fwd_inst(const GridDev& gd, const void* table, const MlpDev& mlp, int K, int64_t n_samples,
                     const int32_t* ids, const float* depths, const float* weights, const float* plain, float* tex,
                     float* image, int32_t* cells, uint32_t* masks, float* feats, hipStream_t s) {
@@ -1435,75 +1593,92 @@ hipError_t fwd_inst(const GridDev& gd, const void* table, const MlpDev& mlp, int
   int64_t grid = (n_q + kWaves - 1) / kWaves;
   if (grid > 4096) grid = 4096;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL((texture_forward_kernel<TDT, BF, HID>), dim3((unsigned)grid), dim3(kTexThreads), 0, s, gd, table,
-                     mlp.w[0], mlp.w[1], mlp.w[2], mlp.in_dim, K, ilog2(K), n_samples, ids, depths, weights, plain,
-                     tex, image, cells, masks, feats);
+  hipLaunchKernelGGL((texture_forward_kernel<TDT, BF, HID, SH>), dim3((unsigned)grid), dim3(kTexThreads), 0, s, gd,
+                     table, mlp.w[0], mlp.w[1], mlp.w[2], mlp.in_dim, K, ilog2(K), n_samples, ids, depths, weights,
+                     plain, tex, image, cells, masks, feats);
   return hipGetLastError();
 }
 
-template <int TDT, bool BF, int HID>
+template <int TDT, bool BF, int HID, bool SH>
 hipError_t bwd_inst(const GridDev& gd, const void* table, const MlpDev& mlp, int K, int64_t n_samples,
                     const int32_t* ids, const float* depths, const float* weights, const float* grad_image,
                     const float* grad_tex, float2* feat_grad, float* g0, float* g1, float* g2, float* grad_depth,
                     unsigned char* wop, hipStream_t s) {
-  constexpr bool kWlds = HID <= 64 && BF;
+  // operand slots in LDS for the BF16 hidden-64 RGB form; the others read them
+  // from the workspace (L2-resident), leaving LDS to the activation tiles
+  constexpr bool kWlds = HID <= 64 && BF && !SH;
   const int64_t n_q = n_patches(gd) * K;
   int64_t grid = (n_q + kWaves - 1) / kWaves;
   if (grid > 1024) grid = 1024;
   if (grid < 1) grid = 1;
   if constexpr (!kWlds) {
-    hipLaunchKernelGGL((stage_weight_operands_kernel<BF, HID>), dim3(64), dim3(256), 0, s, wop, mlp.w[0], mlp.w[1],
-                       mlp.w[2], mlp.in_dim);
+    hipLaunchKernelGGL((stage_weight_operands_kernel<BF, HID, SH>), dim3(64), dim3(256), 0, s, wop, mlp.w[0],
+                       mlp.w[1], mlp.w[2], mlp.in_dim);
   }
-  hipLaunchKernelGGL((texture_backward_kernel<TDT, BF, HID, kWlds>), dim3((unsigned)grid), dim3(kTexThreads), 0, s,
-                     gd, table, mlp.w[0], mlp.w[1], mlp.w[2], wop, mlp.in_dim, K, ilog2(K), n_samples, ids, depths,
+  hipLaunchKernelGGL((texture_backward_kernel<TDT, BF, HID, SH, kWlds>), dim3((unsigned)grid), dim3(kTexThreads), 0,
+                     s, gd, table, mlp.w[0], mlp.w[1], mlp.w[2], wop, mlp.in_dim, K, ilog2(K), n_samples, ids, depths,
                      weights, grad_image, grad_tex, feat_grad, g0, g1, g2, grad_depth);
   return hipGetLastError();
 }
 
-template <bool BF, int HID>
-hipError_t fwd_by_table(int tdt, const GridDev& gd, const void* table, const MlpDev& mlp, int K, int64_t n,
-                        const int32_t* ids, const float* depths, const float* weights, const float* plain,
-                        float* tex, float* image, int32_t* cells, uint32_t* masks, float* feats, hipStream_t s) {
+// Arguments of one texturing-pass launch, forwarded to the instantiation the
+// storage types, hidden width and head select.
+struct TexArgs {
+  GridDev gd;
+  const void* table;
+  MlpDev mlp;
+  int K;
+  int64_t n;
+  const int32_t* ids;
+  const float *depths, *weights;
+  // forward
+  const float* plain;
+  float *tex, *image;
+  int32_t* cells;
+  uint32_t* masks;
+  float* feats;
+  // backward
+  const float *grad_image, *grad_tex;
+  float2* feat_grad;
+  float *g0, *g1, *g2, *grad_depth;
+  unsigned char* wop;
+};
+
+template <int TDT, bool BF, int HID, bool SH>
+hipError_t run_tex(bool backward, const TexArgs& a, hipStream_t s) {
+  if (backward)
+    return bwd_inst<TDT, BF, HID, SH>(a.gd, a.table, a.mlp, a.K, a.n, a.ids, a.depths, a.weights, a.grad_image,
+                                      a.grad_tex, a.feat_grad, a.g0, a.g1, a.g2, a.grad_depth, a.wop, s);
+  return fwd_inst<TDT, BF, HID, SH>(a.gd, a.table, a.mlp, a.K, a.n, a.ids, a.depths, a.weights, a.plain, a.tex,
+                                    a.image, a.cells, a.masks, a.feats, s);
+}
+
+template <bool BF, int HID, bool SH>
+hipError_t by_table(int tdt, bool backward, const TexArgs& a, hipStream_t s) {
   switch (tdt) {
-    case NX_F32:
-      return fwd_inst<NX_F32, BF, HID>(gd, table, mlp, K, n, ids, depths, weights, plain, tex, image, cells, masks,
-                                       feats, s);
-    case NX_F16:
-      return fwd_inst<NX_F16, BF, HID>(gd, table, mlp, K, n, ids, depths, weights, plain, tex, image, cells, masks,
-                                       feats, s);
-    case NX_BF16:
-      return fwd_inst<NX_BF16, BF, HID>(gd, table, mlp, K, n, ids, depths, weights, plain, tex, image, cells, masks,
-                                        feats, s);
+    case NX_F32: return run_tex<NX_F32, BF, HID, SH>(backward, a, s);
+    case NX_F16: return run_tex<NX_F16, BF, HID, SH>(backward, a, s);
+    case NX_BF16: return run_tex<NX_BF16, BF, HID, SH>(backward, a, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <bool BF, int HID>
-hipError_t bwd_by_table(int tdt, const GridDev& gd, const void* table, const MlpDev& mlp, int K, int64_t n,
-                        const int32_t* ids, const float* depths, const float* weights, const float* gi,
-                        const float* gt, float2* fg, float* g0, float* g1, float* g2, float* gd_out,
-                        unsigned char* wop, hipStream_t s) {
-  switch (tdt) {
-    case NX_F32:
-      return bwd_inst<NX_F32, BF, HID>(gd, table, mlp, K, n, ids, depths, weights, gi, gt, fg, g0, g1, g2, gd_out, wop,
-                                       s);
-    case NX_F16:
-      return bwd_inst<NX_F16, BF, HID>(gd, table, mlp, K, n, ids, depths, weights, gi, gt, fg, g0, g1, g2, gd_out, wop,
-                                       s);
-    case NX_BF16:
-      return bwd_inst<NX_BF16, BF, HID>(gd, table, mlp, K, n, ids, depths, weights, gi, gt, fg, g0, g1, g2, gd_out,
-                                        wop, s);
-    default: return hipErrorInvalidValue;
-  }
+template <bool SH>
+hipError_t by_mlp(int tdt, int mlp_dtype, bool backward, const TexArgs& a, hipStream_t s) {
+  const bool bf = mlp_dtype == NX_BF16;
+  if (a.mlp.hidden == 64)
+    return bf ? by_table<true, 64, SH>(tdt, backward, a, s) : by_table<false, 64, SH>(tdt, backward, a, s);
+  if (a.mlp.hidden == 128)
+    return bf ? by_table<true, 128, SH>(tdt, backward, a, s) : by_table<false, 128, SH>(tdt, backward, a, s);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-hipError_t launch_texture_forward(int K, int feat_dtype, int mlp_dtype, const GridDev& grid, const void* table,
-                                  const MlpDev& mlp, const int32_t* ids, const float* depths, const float* weights,
-                                  const float* plain, float* tex, float* image, int32_t* cells, uint32_t* masks,
-                                  float* feats, hipStream_t s) {
+hipError_t launch_texture_forward(int K, int feat_dtype, int mlp_dtype, int sh, const GridDev& grid,
+                                  const void* table, const MlpDev& mlp, const int32_t* ids, const float* depths,
+                                  const float* weights, const float* plain, float* tex, float* image, int32_t* cells,
+                                  uint32_t* masks, float* feats, hipStream_t s) {
   const int64_t P = (int64_t)grid.width * grid.height;
   if (K == 0) {
     if (P == 0) return hipSuccess;
@@ -1512,41 +1687,51 @@ hipError_t launch_texture_forward(int K, int feat_dtype, int mlp_dtype, const Gr
   }
   const int64_t n = P * K;
   if (n == 0) return hipSuccess;
-  const bool bf = mlp_dtype == NX_BF16;
-  if (mlp.hidden == 64)
-    return bf ? fwd_by_table<true, 64>(feat_dtype, grid, table, mlp, K, n, ids, depths, weights, plain, tex, image,
-                                       cells, masks, feats, s)
-              : fwd_by_table<false, 64>(feat_dtype, grid, table, mlp, K, n, ids, depths, weights, plain, tex, image,
-                                        cells, masks, feats, s);
-  if (mlp.hidden == 128)
-    return bf ? fwd_by_table<true, 128>(feat_dtype, grid, table, mlp, K, n, ids, depths, weights, plain, tex, image,
-                                        cells, masks, feats, s)
-              : fwd_by_table<false, 128>(feat_dtype, grid, table, mlp, K, n, ids, depths, weights, plain, tex, image,
-                                         cells, masks, feats, s);
-  return hipErrorInvalidValue;
+  TexArgs a{};
+  a.gd = grid;
+  a.table = table;
+  a.mlp = mlp;
+  a.K = K;
+  a.n = n;
+  a.ids = ids;
+  a.depths = depths;
+  a.weights = weights;
+  a.plain = plain;
+  a.tex = tex;
+  a.image = image;
+  a.cells = cells;
+  a.masks = masks;
+  a.feats = feats;
+  return sh ? by_mlp<true>(feat_dtype, mlp_dtype, false, a, s) : by_mlp<false>(feat_dtype, mlp_dtype, false, a, s);
 }
 
-hipError_t launch_texture_backward(int K, int feat_dtype, int mlp_dtype, const GridDev& grid, const void* table,
-                                   const MlpDev& mlp, const int32_t* ids, const float* depths, const float* weights,
-                                   const float* grad_image, const float* grad_tex, float2* feat_grad, float* g_mlp0,
-                                   float* g_mlp1, float* g_mlp2, float* grad_depth, unsigned char* weight_ops,
-                                   hipStream_t s) {
+hipError_t launch_texture_backward(int K, int feat_dtype, int mlp_dtype, int sh, const GridDev& grid,
+                                   const void* table, const MlpDev& mlp, const int32_t* ids, const float* depths,
+                                   const float* weights, const float* grad_image, const float* grad_tex,
+                                   float2* feat_grad, float* g_mlp0, float* g_mlp1, float* g_mlp2, float* grad_depth,
+                                   unsigned char* weight_ops, hipStream_t s) {
   const int64_t P = (int64_t)grid.width * grid.height;
   if (K == 0) return hipSuccess;
   const int64_t n = P * K;
   if (n == 0) return hipSuccess;
-  const bool bf = mlp_dtype == NX_BF16;
-  if (mlp.hidden == 64)
-    return bf ? bwd_by_table<true, 64>(feat_dtype, grid, table, mlp, K, n, ids, depths, weights, grad_image, grad_tex,
-                                       feat_grad, g_mlp0, g_mlp1, g_mlp2, grad_depth, weight_ops, s)
-              : bwd_by_table<false, 64>(feat_dtype, grid, table, mlp, K, n, ids, depths, weights, grad_image, grad_tex,
-                                        feat_grad, g_mlp0, g_mlp1, g_mlp2, grad_depth, weight_ops, s);
-  if (mlp.hidden == 128)
-    return bf ? bwd_by_table<true, 128>(feat_dtype, grid, table, mlp, K, n, ids, depths, weights, grad_image,
-                                        grad_tex, feat_grad, g_mlp0, g_mlp1, g_mlp2, grad_depth, weight_ops, s)
-              : bwd_by_table<false, 128>(feat_dtype, grid, table, mlp, K, n, ids, depths, weights, grad_image,
-                                         grad_tex, feat_grad, g_mlp0, g_mlp1, g_mlp2, grad_depth, weight_ops, s);
-  return hipErrorInvalidValue;
+  TexArgs a{};
+  a.gd = grid;
+  a.table = table;
+  a.mlp = mlp;
+  a.K = K;
+  a.n = n;
+  a.ids = ids;
+  a.depths = depths;
+  a.weights = weights;
+  a.grad_image = grad_image;
+  a.grad_tex = grad_tex;
+  a.feat_grad = feat_grad;
+  a.g0 = g_mlp0;
+  a.g1 = g_mlp1;
+  a.g2 = g_mlp2;
+  a.grad_depth = grad_depth;
+  a.wop = weight_ops;
+  return sh ? by_mlp<true>(feat_dtype, mlp_dtype, true, a, s) : by_mlp<false>(feat_dtype, mlp_dtype, true, a, s);
 }
 
 namespace {
@@ -1563,7 +1748,7 @@ bool scatter_launch(const GridDev& grid, ScatterLaunch* o) {
 hipError_t launch_hash_scatter_bin(int K, const GridDev& grid, int level, const float* depths,
                                    const float2* feat_grad, float* g_table, uint32_t slab0, int64_t row0,
                                    int64_t n_rows, uint2* slab_table, uint16_t* rec_key, float2* rec_val,
-                                   hipStream_t s) {
+                                   int64_t slab_cap, hipStream_t s) {
   if (K == 0 || grid.width == 0 || grid.height == 0 || level < 0 || level >= grid.levels) return hipSuccess;
   ScatterLaunch sl;
   if (!scatter_launch(grid, &sl)) return hipErrorInvalidValue;
@@ -1573,15 +1758,17 @@ hipError_t launch_hash_scatter_bin(int K, const GridDev& grid, int level, const 
   if (row0 < 0 || row0 + sb.wgs > n_rows || (int64_t)slab0 + sb.wgs * sl.nb * sb.slab > 0xFFFFFFFFll)
     return hipErrorInvalidValue;
   const size_t lds = kScatStageBytes + 3 * sizeof(uint32_t) * sl.nb;
+  // a smaller slab (diagnostics) stays inside the records laid out for the full one
+  const int64_t slab = slab_cap > 0 && slab_cap < sb.slab ? slab_cap : sb.slab;
   hipLaunchKernelGGL(scatter_bin_kernel, dim3((unsigned)sb.wgs), dim3(kScatThreads), lds, s, grid, grid.lv[level], K,
                      ilog2(K), level, depths, feat_grad, g_table, sg.bw, sg.bh, sg.nbx, sg.nby, sl.bl, slab0,
-                     (uint32_t)sb.slab, row0, n_rows, slab_table, rec_key, rec_val);
+                     (uint32_t)slab, row0, n_rows, slab_table, rec_key, rec_val);
   return hipGetLastError();
 }
 
 hipError_t launch_hash_scatter_reduce(const GridDev& grid, int level, float* g_table, int64_t n_rows,
                                       const uint2* slab_table, const uint16_t* rec_key, const float2* rec_val,
-                                      hipStream_t s) {
+                                      int cas_rounds, hipStream_t s) {
   if (level < 0 || level >= grid.levels || n_rows <= 0) return hipSuccess;
   ScatterLaunch sl;
   if (!scatter_launch(grid, &sl)) return hipErrorInvalidValue;
@@ -1590,8 +1777,9 @@ hipError_t launch_hash_scatter_reduce(const GridDev& grid, int level, float* g_t
   const float corners = (grid.lv[level].scale + 2.0f) * (grid.lv[level].scale + 2.0f) * (grid.lv[level].scale + 2.0f);
   const int coarse = corners < 65536.0f ? 1 : 0;
   const size_t lds = sizeof(unsigned long long) << sl.bl;
-  hipLaunchKernelGGL(scatter_reduce_kernel, dim3((unsigned)sl.nb), dim3(kReduceThreads), lds, s, sl.bl, coarse, n_rows,
-                     slab_table, rec_key, rec_val, g_table + 2 * ((size_t)level << grid.log2_size));
+  const int rounds = cas_rounds > 0 ? cas_rounds : kMaxCasRounds;
+  hipLaunchKernelGGL(scatter_reduce_kernel, dim3((unsigned)sl.nb), dim3(kReduceThreads), lds, s, sl.bl, coarse, rounds,
+                     n_rows, slab_table, rec_key, rec_val, g_table + 2 * ((size_t)level << grid.log2_size));
   return hipGetLastError();
 }
 

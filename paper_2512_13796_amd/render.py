@@ -49,17 +49,32 @@ def camera_struct(cam, near=0.2):
 
 
 class Context:
-    """Owns one nx_ctx (K, tile size, storage dtypes)."""
+    """Owns one nx_ctx (K, tile size, storage dtypes, appearance).
 
-    def __init__(self, K, feat_dtype=torch.float32, mlp_dtype=torch.float32):
+    sh_degree=3 selects the spherical-harmonics appearance: surfel colours are
+    [n, 48] coefficients ([16][3]) and the MLP head has 48 outputs; None keeps
+    RGB colours and a sigmoid head of 3."""
+
+    def __init__(self, K, feat_dtype=torch.float32, mlp_dtype=torch.float32, sh_degree=None):
         self.lib = L.load()
         self.K = int(K)
         self.feat_dtype = feat_dtype
         self.mlp_dtype = mlp_dtype
+        self.sh_degree = sh_degree
         h = ctypes.c_void_p()
         L.check(self.lib.nx_create(ctypes.byref(h), self.K, 16, _DTYPE[feat_dtype], _DTYPE[mlp_dtype]))
         self.handle = h
+        if sh_degree is not None:
+            L.check(self.lib.nx_set_sh_degree(h, int(sh_degree)))
         self.ws_hint = 0
+
+    def debug_limits(self, slab_records=0, cas_rounds=0):
+        """nx_debug_limits: force the hash-grid gradient's slab-overflow and lost-CAS fallbacks (0 = default)."""
+        L.check(self.lib.nx_debug_limits(self.handle, int(slab_records), int(cas_rounds)))
+
+    @property
+    def n_color(self):
+        return 3 if self.sh_degree is None else 3 * (self.sh_degree + 1) ** 2
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
@@ -120,13 +135,17 @@ class ForwardResult:
     features: torch.Tensor = None
 
 
-def _structs(ctx, surfels, table, level_scales, weights, device):
+def _surfel_struct(ctx, surfels, device):
     means, quats, scales, opac, gammas, colors = surfels
     n = means.shape[0]
     for nm, t, shp in (("means", means, (n, 3)), ("quats", quats, (n, 4)), ("scales", scales, (n, 2)),
-                       ("opacities", opac, (n,)), ("gammas", gammas, (n, 2)), ("colors", colors, (n, 3))):
+                       ("opacities", opac, (n,)), ("gammas", gammas, (n, 2)), ("colors", colors, (n, ctx.n_color))):
         _check_dev(nm, t, device, torch.float32, shp)
-    s = L.NxSurfels(_ptr(means), _ptr(quats), _ptr(scales), _ptr(opac), _ptr(gammas), _ptr(colors), n)
+    return L.NxSurfels(_ptr(means), _ptr(quats), _ptr(scales), _ptr(opac), _ptr(gammas), _ptr(colors), n)
+
+
+def _structs(ctx, surfels, table, level_scales, weights, device):
+    s = _surfel_struct(ctx, surfels, device)
     g = L.NxHashGrid()
     m = L.NxMLP()
     keep = []
@@ -163,6 +182,23 @@ def workspace_size(ctx: Context, n_surfels, cam, max_instances, near=0.2):
     L.check(ctx.lib.nx_workspace_size(ctx.handle, int(n_surfels), cs, len(cams), int(max_instances),
                                       ctypes.byref(size)))
     return int(size.value)
+
+
+def workspace_size_exact(ctx: Context, surfels, cam, near=0.2):
+    """nx_workspace_size_exact: (bytes nx_render_forward needs, per-camera pair counts) for these surfels and
+    cameras (one synchronisation per camera)."""
+    device = surfels[0].device
+    s = _surfel_struct(ctx, surfels, device)
+    cams = _cameras(cam)
+    cs = (L.NxCamera * len(cams))(*[camera_struct(c, near) for c in cams])
+    need = max(workspace_size(ctx, surfels[0].shape[0], c, 0, near) for c in cams)
+    ws = torch.empty(need, device=device, dtype=torch.uint8)
+    size = ctypes.c_size_t()
+    counts = (ctypes.c_int64 * len(cams))()
+    stream = ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+    L.check(ctx.lib.nx_workspace_size_exact(ctx.handle, ctypes.byref(s), cs, len(cams), _ptr(ws), ws.numel(),
+                                            ctypes.byref(size), counts, stream))
+    return int(size.value), [int(v) for v in counts]
 
 
 def instance_counts(ctx: Context, n_surfels, res: ForwardResult):
@@ -326,6 +362,91 @@ def render_backward(ctx: Context, surfels, fwd: ForwardResult, table=None, level
                                        stream))
     del keep
     return grads
+
+
+def aux_losses(ctx: Context, weights, tex, target, opacities, table=None, level_scales=None,
+               lambdas=(1.0, 1.0, 1.0, 1.0), grads=None):
+    """nx_aux_losses: the losses L_alpha, L_texture, L_opacity, L_grid (unweighted, a float32 [4] device
+    tensor) of a forward's weights [P,K] and tex [P,K,3] against target [P,3], of the opacities [n] and of the
+    table (optional); the gradient of their lambda-weighted sum is added to the float32 tensors in ``grads``
+    (keys "weights", "tex", "opacities", "table"; missing keys are skipped)."""
+    device = opacities.device
+    P = target.shape[0]
+    K = ctx.K
+    _check_dev("target", target, device, torch.float32, (P, 3))
+    _check_dev("opacities", opacities, device, torch.float32)
+    if K > 0:
+        _check_dev("weights", weights, device, torch.float32, (P, K))
+        _check_dev("tex", tex, device, torch.float32, (P, K, 3))
+    grads = grads or {}
+    for k, t in grads.items():
+        _check_dev(f"grads[{k}]", t, device, torch.float32)
+    g = None
+    keep = []
+    if table is not None:
+        _check_dev("table", table, device, ctx.feat_dtype)
+        ls = level_scales.detach().to("cpu", torch.float32).contiguous()
+        keep.append(ls)
+        g = L.NxHashGrid()
+        g.table = _ptr(table)
+        g.dtype = _DTYPE[table.dtype]
+        g.levels, g.log2_size, g.feat = table.shape[0], int(table.shape[1]).bit_length() - 1, table.shape[2]
+        g.level_scales = ctypes.c_void_p(ls.data_ptr())
+    lam = L.NxAuxLambdas(*[float(v) for v in lambdas])
+    losses = torch.empty(4, device=device, dtype=torch.float32)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+    L.check(ctx.lib.nx_aux_losses(ctx.handle, P, _ptr(weights if K > 0 else None), _ptr(tex if K > 0 else None),
+                                  _ptr(target), opacities.shape[0], _ptr(opacities),
+                                  None if g is None else ctypes.byref(g), ctypes.byref(lam),
+                                  _ptr(grads.get("weights")), _ptr(grads.get("tex")), _ptr(grads.get("opacities")),
+                                  _ptr(grads.get("table")), _ptr(losses), stream))
+    del keep
+    return losses
+
+
+def fps(ctx: Context, points, m):
+    """nx_fps: the first m points of the farthest-point-sampling order of points [n,3] (device float32), from
+    point 0, and each one's squared distance to the nearest earlier one. Returns (order int32 [m],
+    dist2 float32 [m]); the initial scale of point order[i] is sqrt(dist2[i])."""
+    device = points.device
+    _check_dev("points", points, device, torch.float32)
+    n = points.shape[0]
+    size = ctypes.c_size_t()
+    L.check(ctx.lib.nx_fps_workspace_size(n, ctypes.byref(size)))
+    ws = torch.empty(int(size.value), device=device, dtype=torch.uint8)
+    order = torch.empty(int(m), device=device, dtype=torch.int32)
+    d2 = torch.empty(int(m), device=device, dtype=torch.float32)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+    L.check(ctx.lib.nx_fps(ctx.handle, _ptr(points), n, int(m), _ptr(order), _ptr(d2), _ptr(ws), ws.numel(), stream))
+    return order, d2
+
+
+def densify(ctx: Context, surfels, blended_error, exp_draws, n_split, min_opacity=0.005):
+    """nx_densify: split n_split surfels drawn in proportion to blended_error (exponential clocks exp_draws [n]),
+    then prune opacities below min_opacity. Returns (the six surfel tensors, parent int32) of the new set
+    (synchronises the stream once for its size)."""
+    device = surfels[0].device
+    n = surfels[0].shape[0]
+    for nm, t, shp in (("means", surfels[0], (n, 3)), ("quats", surfels[1], (n, 4)), ("scales", surfels[2], (n, 2)),
+                       ("opacities", surfels[3], (n,)), ("gammas", surfels[4], (n, 2)), ("colors", surfels[5], (n, 3)),
+                       ("blended_error", blended_error, (n,)), ("exp_draws", exp_draws, (n,))):
+        _check_dev(nm, t, device, torch.float32, shp)
+    s = L.NxSurfels(*[_ptr(t) for t in surfels], n)
+    cap = n + max(int(n_split), 0)
+    f32 = dict(device=device, dtype=torch.float32)
+    outs = [torch.empty(cap, 3, **f32), torch.empty(cap, 4, **f32), torch.empty(cap, 2, **f32),
+            torch.empty(cap, **f32), torch.empty(cap, 2, **f32), torch.empty(cap, 3, **f32)]
+    parent = torch.empty(cap, device=device, dtype=torch.int32)
+    o = L.NxSurfelsOut(*[_ptr(t) for t in outs], _ptr(parent), cap)
+    size = ctypes.c_size_t()
+    L.check(ctx.lib.nx_densify_workspace_size(n, ctypes.byref(size)))
+    ws = torch.empty(int(size.value), device=device, dtype=torch.uint8)
+    n_out = ctypes.c_int64()
+    stream = ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+    L.check(ctx.lib.nx_densify(ctx.handle, ctypes.byref(s), _ptr(blended_error), _ptr(exp_draws), int(n_split),
+                               float(min_opacity), ctypes.byref(o), ctypes.byref(n_out), _ptr(ws), ws.numel(), stream))
+    k = int(n_out.value)
+    return tuple(t[:k] for t in outs), parent[:k]
 
 
 class RenderFunction(torch.autograd.Function):

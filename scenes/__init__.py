@@ -104,6 +104,7 @@ class Workload:
     mlp: MLP
     K: int
     target: list  # per camera: [H, W, 3] float32 target image (or None)
+    sh_degree: int = None  # 3: colours are [N,48] SH coefficients and the MLP head has 48 outputs
 
 
 CONFIG_NAMES = {
@@ -332,6 +333,24 @@ def _target_images(rng, cams):
     return [torch.from_numpy(rng.uniform(0.0, 1.0, (c.height, c.width, 3)).astype(np.float32)) for c in cams]
 
 
+def with_sh(wl: Workload, seed: int = 0, ac_sd: float = 0.2) -> Workload:
+    """The same workload with the spherical-harmonics appearance (degree 3): per-surfel coefficients [N,48]
+    whose DC term reproduces the RGB colour (a_0 = (c - 0.5) / Y_0, Y_0 = 0.5 / sqrt(pi)) and whose higher
+    terms are N(0, ac_sd^2), and a 48-output head (Xavier-uniform) in the MLP's dtype. Drawn from a generator
+    of its own (PCG64(seed + 7919)), so the base workload is unchanged."""
+    rng = np.random.Generator(np.random.PCG64(seed + 7919))
+    rgb = wl.scene.colors.double().numpy()
+    n = rgb.shape[0]
+    coef = rng.normal(0.0, ac_sd, (n, 16, 3))
+    coef[:, 0, :] = (rgb - 0.5) / (0.5 / math.sqrt(math.pi))
+    scene = Scene(*wl.scene.tensors()[:5], torch.from_numpy(coef.reshape(n, 48).astype(np.float32)))
+    w = wl.mlp.weights
+    hid = w[2].shape[1]
+    b = math.sqrt(6.0 / (hid + 48))
+    head = torch.from_numpy(rng.uniform(-b, b, (48, hid)).astype(np.float32)).to(w[2].dtype)
+    return Workload(wl.name + "_sh3", scene, wl.cameras, wl.grid, MLP([w[0], w[1], head]), wl.K, wl.target, 3)
+
+
 def make_workload(config: int, seed: int = 0, *, n_surfels=None, width=None, height=None,
                   feat_dtype=None, mlp_dtype=None, K=None, grid_amp=1e-2) -> Workload:
     """Build one of the five synthetic workloads.
@@ -419,10 +438,11 @@ class TrainWorkload:
     init_grid: HashGrid
     init_mlp: MLP
     K: int
+    init_gammas: torch.Tensor = None  # the students' starting exponents (None: the scene's own)
 
 
 def make_train_workload(seed: int = 0, n_surfels: int = 3000, n_views: int = 7, width: int = 64,
-                        height: int = 64, K: int = 4) -> TrainWorkload:
+                        height: int = 64, K: int = 4, teacher_gamma: float = None) -> TrainWorkload:
     """A small textured scene for the training check.
 
     Surfels on 6 planes through [-2,2]^3 (no clutter) with scales around 0.15;
@@ -434,6 +454,11 @@ def make_train_workload(seed: int = 0, n_surfels: int = 3000, n_views: int = 7, 
     heights U(0.5, 1.5) looking at the origin; the held-out view lies between
     two training views. The student starts from fresh colours U[0,1], a grid
     U(-1e-2, 1e-2) with the same level scales, and a fresh MLP.
+
+    teacher_gamma: the teacher's surfels use this kernel exponent on both
+    axes (flat-topped, near-rectangular footprints) while the students start
+    from gamma = 1 (Gaussians); set after every random draw, so the rest of
+    the workload is unchanged.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     scene = _planes_scene(rng, n_surfels, 0, n_planes=6, half=2.0, scale_mean=0.15)
@@ -448,4 +473,8 @@ def make_train_workload(seed: int = 0, n_surfels: int = 3000, n_views: int = 7, 
     init_colors = torch.from_numpy(rng.uniform(0.0, 1.0, (scene.n, 3)).astype(np.float32))
     init_grid = _grid(rng, 8, 14, 2, torch.float32, amp=1e-2, base=2.0)
     init_mlp = _mlp(rng, [16, 64, 64, 3], torch.float32)
-    return TrainWorkload(scene, cams, teacher_grid, teacher_mlp, init_colors, init_grid, init_mlp, K)
+    init_gammas = None
+    if teacher_gamma is not None:
+        init_gammas = torch.ones_like(scene.gammas)
+        scene.gammas = torch.full_like(scene.gammas, float(teacher_gamma))
+    return TrainWorkload(scene, cams, teacher_grid, teacher_mlp, init_colors, init_grid, init_mlp, K, init_gammas)

@@ -23,6 +23,11 @@ from tests.gpu_helpers import device_inputs, log
 pytestmark = pytest.mark.gpu
 
 FWD_FIELDS = ("image", "plain", "ids", "weights", "depths", "t_final", "tex", "n_iter")
+# Two backward calls on identical inputs differ only in the order of their float32 atomic additions. With a
+# random upstream gradient the per-surfel sums cancel heavily (the result is much smaller than the partial sums
+# that are reordered), so the difference relative to the gradient's norm reaches ~1e-5 (measured 1.4e-5 for the
+# quaternion gradient of four cameras).
+ATOMIC_ORDER_TOL = 1e-4
 
 
 @pytest.fixture(scope="module")
@@ -64,7 +69,9 @@ def test_async_forward_equals_synced_forward(nx, views):
     torch.cuda.synchronize()
     for nm in ("means", "quats", "scales", "opacities", "gammas", "colors", "table"):
         a, b = ga[nm].double(), gb[nm].double()
-        assert float((a - b).norm()) <= 1e-5 * max(float(a.norm()), 1e-30), nm
+        rel = float((a - b).norm()) / max(float(a.norm()), 1e-30)
+        log(f"async vs synced backward: {nm} relative difference {rel:.2e}")
+        assert rel <= ATOMIC_ORDER_TOL, nm
 
 
 def test_async_forward_reports_overflow(nx, views):
@@ -132,6 +139,24 @@ def test_captured_training_step_replays_exactly(nx, views):
             assert torch.equal(getattr(res_g, nm), eager[nm]), f"replay {rep}: {nm}"
         for k, v in grads.items():
             for a, b in zip(v if k == "mlp" else [v], eager_g[k] if k == "mlp" else [eager_g[k]]):
-                d = float((a.double() - b.double()).norm())
-                assert d <= 1e-5 * max(float(b.double().norm()), 1e-30), f"replay {rep}: {k} differs by {d:.3e}"
+                d = float((a.double() - b.double()).norm()) / max(float(b.double().norm()), 1e-30)
+                assert d <= ATOMIC_ORDER_TOL, f"replay {rep}: {k} differs by {d:.3e} (relative)"
     log("graph replays match the eager step:", [c.width * c.height for c in cams], "pixels per camera")
+
+
+def test_exact_workspace_size(nx, views):
+    """nx_workspace_size_exact returns the pair counts the synced forward finds and a size that lets a single
+    nx_render_forward call succeed (and no smaller one: the synced forward's own requirement)."""
+    wl, cams = views
+    surf, table, weights = device_inputs(wl)
+    ctx = nx.Context(wl.K, table.dtype, weights[0].dtype)
+    size, counts = nx.workspace_size_exact(ctx, surf, cams)
+    ref = nx.render_forward(ctx, surf, cams, table, wl.grid.level_scales, weights)
+    log("exact workspace:", size, "bytes, counts", counts, "synced", ref.n_instances_cam)
+    assert counts == ref.n_instances_cam
+    ws = torch.empty(size, device="cuda", dtype=torch.uint8)
+    ctx2 = nx.Context(wl.K, table.dtype, weights[0].dtype)
+    res = nx.render_forward(ctx2, surf, cams, table, wl.grid.level_scales, weights, workspace=ws)
+    assert res.workspace.data_ptr() == ws.data_ptr(), "the exact size was not enough for one call"
+    for nm in FWD_FIELDS:
+        assert torch.equal(getattr(res, nm), getattr(ref, nm)), nm

@@ -20,14 +20,15 @@ import torch
 import oracle
 import scenes
 from oracle.binning import bin_surfels
-from tests.gpu_helpers import (SAFETY, TOL_IMAGE, check_forced_decisions, compare_forward, device_inputs,
+from tests.gpu_helpers import (BF16_ELEM, SAFETY, TOL_IMAGE, check_forced_decisions, compare_forward, device_inputs,
                                fmt_grad_report, grad_errors, log, psnr, run_forward, to_np)
 
 pytestmark = pytest.mark.gpu
 
-# BF16 form, per element: |g_gpu - g| <= BF16_ELEM max(|g|, rms(g)) (activations rounded to BF16, unit roundoff
-# 2^-9, at three layers of the forward and three of the backward)
-BF16_ELEM = 0.25
+# BF16 form, per element: |g_gpu - g| <= BF16_ELEM max(|g|, rms(g)) (tests.gpu_helpers: 2^-5 from sixteen BF16
+# roundings of 2^-9); at most this fraction of a tensor's elements may exceed it, for the elements whose
+# gradient is a sum of contributions that cancel (their error follows the contributions, not the sum).
+BF16_VIOL = 1e-3
 
 
 @pytest.fixture(scope="module")
@@ -103,12 +104,13 @@ def _forward_case(nx, wl, K=None, label="", max_nd=1e-3, feat_dtype=None, mlp_dt
         cells = res.cells[sel].cpu().numpy()
         masks = res.relu_masks[sel].cpu().numpy().view(np.uint32)
         feats = res.features[sel].cpu().numpy()
-        nat = oracle.render(wl.scene, cam, grid, mlp, K, pixels=pixels, want_decisions=True)
+        nat = oracle.render(wl.scene, cam, grid, mlp, K, pixels=pixels, want_decisions=True, sh_degree=wl.sh_degree)
         form = "bf16" if weights[0].dtype == torch.bfloat16 else "f32"
         dstats = check_forced_decisions(nat, cells, masks, feats, gpu["depths"][pixels], cam, wl.grid.level_scales,
-                                        weights, form, label=label)
+                                        weights, form, label=label, table_absmax=float(table.float().abs().max()))
         log(label, "decisions:", dstats)
-    orc = oracle.render(wl.scene, cam, grid, mlp, K, pixels=pixels, force_cells=cells, force_relu=masks)
+    orc = oracle.render(wl.scene, cam, grid, mlp, K, pixels=pixels, force_cells=cells, force_relu=masks,
+                        sh_degree=wl.sh_degree)
     stats = compare_forward(gpu, orc, pixels, K, tol=tol, tol_tex=tol, max_nondecisive=max_nd, label=label)
     log(label, stats)
     return ctx, surf, table, weights, res, gpu, orc, (cells, masks)
@@ -212,7 +214,7 @@ def _grad_case(nx, wl, K=None, label="", feat_dtype=None, mlp_dtype=None, pixels
     og = oracle.render_and_grad(wl.scene, cam, grid, mlp, K, pixels=pixels, grad_image=gi[pixels],
                                 grad_weights=None if gw is None else gw[pixels],
                                 grad_tex=None if gt is None else gt[pixels], force_cells=forced[0],
-                                force_relu=forced[1], pixel_error=perr[pixels])
+                                force_relu=forced[1], pixel_error=perr[pixels], sh_degree=wl.sh_degree)
     blended = og.blended_error
     og = og.grads
     report = {}
@@ -231,9 +233,9 @@ def _grad_case(nx, wl, K=None, label="", feat_dtype=None, mlp_dtype=None, pixels
         if bf16_bound is None:
             assert r["viol_coarse"] <= viol_tol, f"{label}: {k} per-element violations {r['viol_coarse']:.3e}"
         else:
-            # BF16 activations: every element within bf16_bound max(|g|, rms(g))
-            assert r["max_abs"] <= bf16_bound * max(r["rms"], 1e-30) or r["viol"] == 0.0, \
-                f"{label}: {k} max abs error {r['max_abs']:.3e} > {bf16_bound} rms {r['rms']:.3e}"
+            # BF16 operands: elements within BF16_ELEM max(|g|, rms(g)), but for a fraction bf16_bound
+            assert r["viol_bf16"] <= bf16_bound, \
+                f"{label}: {k}: {r['viol_bf16']:.2e} of the elements beyond {BF16_ELEM} max(|g|, rms)"
     return report
 
 
@@ -266,7 +268,7 @@ def test_backward_hidden128_bf16(nx):
     three layers, so gradients carry a relative error of a few 2^-8; bound 5e-2 on the relative L2."""
     wl = scenes.make_workload(5, seed=10, n_surfels=40_000, width=160, height=90)
     pix = _sample_pixels(wl.cameras[0], 4, per_block=16, full_tiles=2)
-    _grad_case(nx, wl, label="h128 bf16", pixels=pix, rel_tol=5e-2, bf16_bound=BF16_ELEM, tol_fwd=1e-3)
+    _grad_case(nx, wl, label="h128 bf16", pixels=pix, rel_tol=5e-2, bf16_bound=BF16_VIOL, tol_fwd=1e-3)
 
 
 def test_autograd_function_matches_direct_call(nx):
@@ -332,7 +334,7 @@ def test_outdoor_bf16_form_gradients_sampled(nx):
     wl = scenes.make_workload(3)
     pix = _sample_pixels(wl.cameras[0], 7, per_block=64, full_tiles=2)
     # a pixel sample of ~1500: one pixel within the decision margins is 7e-4 of it
-    rep = _grad_case(nx, wl, label="c3 bf16", pixels=pix, rel_tol=5e-2, bf16_bound=BF16_ELEM, tol_fwd=1e-3,
+    rep = _grad_case(nx, wl, label="c3 bf16", pixels=pix, rel_tol=5e-2, bf16_bound=BF16_VIOL, tol_fwd=1e-3,
                      max_nd=3e-3)
     for nm in ("means", "quats", "scales", "opacities", "gammas", "colors"):
         assert rep[nm]["rel_l2"] <= 1e-3, f"{nm}: {rep[nm]['rel_l2']:.2e}"
@@ -345,7 +347,7 @@ def test_large_hidden128_bf16_gradients_sampled(nx):
     wl = scenes.make_workload(5)
     pix = _sample_pixels(wl.cameras[0], 13, per_block=96, full_tiles=1)
     log(f"c5 sampled pixels: {pix.shape[0]}")
-    rep = _grad_case(nx, wl, label="c5 bf16", pixels=pix, rel_tol=5e-2, bf16_bound=BF16_ELEM, tol_fwd=1e-3,
+    rep = _grad_case(nx, wl, label="c5 bf16", pixels=pix, rel_tol=5e-2, bf16_bound=BF16_VIOL, tol_fwd=1e-3,
                      max_nd=1e-2)
     for nm in ("means", "quats", "scales", "opacities", "gammas", "colors"):
         assert rep[nm]["rel_l2"] <= 1e-3, f"{nm}: {rep[nm]['rel_l2']:.2e}"
@@ -385,7 +387,7 @@ def test_outdoor_bf16_form_unit_features(nx):
     oracle >= 45 dB; max and mean absolute errors of the image, the textures and every gradient are reported."""
     wl = scenes.make_workload(3, grid_amp=1.0)
     pix = _sample_pixels(wl.cameras[0], 9, per_block=64, full_tiles=2)
-    rep = _grad_case(nx, wl, label="c3 bf16 unit", pixels=pix, rel_tol=5e-2, bf16_bound=BF16_ELEM, tol_fwd=2e-2,
+    rep = _grad_case(nx, wl, label="c3 bf16 unit", pixels=pix, rel_tol=5e-2, bf16_bound=BF16_VIOL, tol_fwd=2e-2,
                      max_nd=3e-3)
     ctx, surf, table, weights, res = run_forward(nx, wl)
     gpu = to_np(res, wl.K)
@@ -406,14 +408,17 @@ def test_stop_rule_and_clamp_scenes(nx):
     """The hand-built stop-rule stack (five alpha = 0.95 surfels on one ray) and the opacity-1 clamp case, through
     the HIP path against the oracle: three composited, T_final = 0.05^3; alpha clamped at 0.99."""
     from tests.oracle_cases import identity_camera, random_grid, random_mlp, scene_from
-    cam = identity_camera(16, 16, 20.0)
+    # 32x32: the stack (around pixel (8, 8), reaching 9.3 px from it) and the clamp surfel (around pixel
+    # (26, 26), 6.2 px) do not overlap
+    cam = identity_camera(32, 32, 20.0)
     dx = (8 + 0.5 - cam.cx) / cam.fx
     zs = [2.0, 2.5, 3.0, 3.5, 4.0, 5.0]
     means = [[z * dx, z * dx, z] for z in zs]
     opac = [0.95] * 5 + [1.0]
-    means[5] = [5.0 * (3 + 0.5 - cam.cx) / cam.fx, 5.0 * (3 + 0.5 - cam.cy) / cam.fy, 5.0]
+    means[5] = [5.0 * (26 + 0.5 - cam.cx) / cam.fx, 5.0 * (26 + 0.5 - cam.cy) / cam.fy, 5.0]
     rng = np.random.default_rng(40)
-    sc = scene_from(means, [[1, 0, 0, 0]] * 6, [[0.3, 0.3]] * 5 + [[0.5, 0.5]], opac, [[1, 1]] * 6,
+    # scales chosen so that no pixel centre falls exactly on a support edge |u| = 3 (a tie of the support test)
+    sc = scene_from(means, [[1, 0, 0, 0]] * 6, [[0.31, 0.31]] * 5 + [[0.52, 0.52]], opac, [[1, 1]] * 6,
                     rng.uniform(0, 1, (6, 3)), dtype=torch.float32)
     grid = random_grid(rng, levels=8, log2_size=10, scale=0.01)
     grid = scenes.HashGrid(grid.table.float(), grid.level_scales)
@@ -421,8 +426,33 @@ def test_stop_rule_and_clamp_scenes(nx):
     mlp = scenes.MLP([w.float() for w in mlp.weights])
     wl = scenes.Workload("stack", sc, [cam], grid, mlp, 4, [None])
     ctx, surf, table, weights, res, gpu, orc, _ = _forward_case(nx, wl, label="stack")
-    p = 8 * 16 + 8
+    p = 8 * 32 + 8
     assert orc.n_comp[p] == 3 and list(gpu["ids"][p]) == [0, 1, 2, -1]
     np.testing.assert_allclose(gpu["t_final"][p], (1.0 - np.float32(0.95)) ** 3, rtol=1e-5)
-    q = 3 * 16 + 3
+    q = 26 * 32 + 26
+    assert list(gpu["ids"][q]) == [5, -1, -1, -1]
     np.testing.assert_allclose(gpu["t_final"][q], 0.01, rtol=1e-5)
+
+
+def test_hash_scatter_fallback_paths(nx):
+    """The hash-grid gradient's fallbacks, forced with nx_debug_limits: slabs of 4 records (every further record
+    of a bucket goes to the table with a float atomic) and one LDS compare-and-swap attempt (a lost race goes to a
+    global atomic). The table gradient equals the default path's (itself checked against the oracle by the other
+    tests) up to float32 summation order."""
+    wl = scenes.make_workload(1, seed=12)
+    surf, table, weights = device_inputs(wl)
+    ctx = nx.Context(wl.K, table.dtype, weights[0].dtype)
+    res = nx.render_forward(ctx, surf, wl.cameras[0], table, wl.grid.level_scales, weights)
+    P = res.image.shape[0]
+    gi = torch.randn(P, 3, device="cuda", generator=torch.Generator(device="cuda").manual_seed(3))
+    out = []
+    for limits in ((0, 0), (4, 1)):
+        c = nx.Context(wl.K, table.dtype, weights[0].dtype)
+        c.debug_limits(*limits)
+        g = {"table": torch.zeros(table.shape, device="cuda", dtype=torch.float32)}
+        nx.render_backward(c, surf, res, table, wl.grid.level_scales, weights, gi, None, None, g)
+        torch.cuda.synchronize()
+        out.append(g["table"].double())
+    rel = float((out[1] - out[0]).norm() / out[0].norm())
+    log(f"fallback paths: table gradient relative difference {rel:.2e}")
+    assert rel <= 1e-5
