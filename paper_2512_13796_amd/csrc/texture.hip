@@ -727,12 +727,23 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 && BF && TDT != NX_F32 && !
   }
 }
 
+// Row r of a BF16 activation tile starts at element 16 tile_row(r): after
+// every 4 rows of 16 samples (32 dwords) the tile skips 8 dwords, so that the
+// four lane groups of a wave, which write rows 4 g + r of one column, reach
+// four different bank groups instead of the same one. (The FP32 tiles are not
+// padded: their 16-lane row writes use half the banks anyway, and padding
+// would take a workgroup's place on the CU.)
+template <bool BF>
+__device__ __forceinline__ int tile_row(int r) {
+  return BF ? r + (r >> 2) : r;
+}
+
 // Write a register tile set (rows 16 mt + 4 g + r, column c) into an LDS
 // [rows][16] matrix.
 template <bool BF>
 __device__ __forceinline__ void put_rows(unsigned char* buf, int row, int c, float v) {
   if constexpr (BF) {
-    reinterpret_cast<short*>(buf)[row * 16 + c] = f2bf(v);
+    reinterpret_cast<short*>(buf)[tile_row<BF>(row) * 16 + c] = f2bf(v);
   } else {
     reinterpret_cast<float*>(buf)[row * 16 + c] = v;
   }
@@ -744,7 +755,7 @@ template <bool BF>
 __device__ __forceinline__ void put_rows4(unsigned char* buf, int row0, int c, f4 v) {
   if constexpr (BF) {
     const uint32_t w01 = pack_bf16x2(v[0], v[1]), w23 = pack_bf16x2(v[2], v[3]);
-    short* p = reinterpret_cast<short*>(buf) + row0 * 16 + c;
+    short* p = reinterpret_cast<short*>(buf) + tile_row<BF>(row0) * 16 + c;  // row0 % 4 == 0
     p[0] = (short)(w01 & 0xFFFFu);
     p[16] = (short)(w01 >> 16);
     p[32] = (short)(w23 & 0xFFFFu);
@@ -770,8 +781,11 @@ __device__ __forceinline__ void weight_grad_accum(const unsigned char* Y, const 
     for (int mi = 0; mi < NMI; ++mi) {
       f4& d = acc[mo * NMI + mi];
       if constexpr (BF) {
-        const s4 a = *reinterpret_cast<const s4*>(reinterpret_cast<const short*>(Y) + (16 * mo + c) * 16 + 4 * g);
-        const s4 b = *reinterpret_cast<const s4*>(reinterpret_cast<const short*>(X) + (16 * mi + c) * 16 + 4 * g);
+        // Y and X start at a row that is a multiple of 4, so relative rows pad alike
+        const s4 a = *reinterpret_cast<const s4*>(reinterpret_cast<const short*>(Y) + tile_row<BF>(16 * mo + c) * 16 +
+                                                  4 * g);
+        const s4 b = *reinterpret_cast<const s4*>(reinterpret_cast<const short*>(X) + tile_row<BF>(16 * mi + c) * 16 +
+                                                  4 * g);
         d = mfma_bf16_k16(a, b, d);
       } else {
 #pragma unroll
@@ -795,7 +809,7 @@ struct UnitTiles {
   static constexpr int oY3 = 0, oX3 = 16 * WLayout<BF, HID, SH>::OT, oY2 = oX3 + HID, oX2 = oY2 + HID,
                        oY1 = oX2 + HID, oX1 = oY1 + HID;
   static constexpr int rows = oX1 + kInPad;
-  static constexpr int bytes = rows * 16 * elem;
+  static constexpr int bytes = (BF ? rows + rows / 4 : rows) * 16 * elem;
 };
 
 // WLDS: operand slots staged in LDS by every workgroup (hidden width 64), or
@@ -835,7 +849,7 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 || BF) ? 2 : 1) void textur
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, c = lane & 15;
   unsigned char* T = tiles + wave * UT::bytes;  // this wave's unit
-  auto row_ptr = [&](const unsigned char* base, int row) { return base + row * 16 * UT::elem; };
+  auto row_ptr = [&](const unsigned char* base, int row) { return base + tile_row<BF>(row) * 16 * UT::elem; };
   const uint32_t mask = (1u << gd.log2_size) - 1u;
   const int64_t n_q = n_patches(gd);
   const int64_t n_units = n_q * K;
