@@ -126,6 +126,10 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2512_13796_amd/build.py`")
+    # torch ships its own HIP runtime. Loaded first, it is the runtime the library binds to (same soname);
+    # loaded after the library, a second HIP and HSA runtime would enter the process, and whichever opens the
+    # device second finds none.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     for name, (args, res) in SIGNATURES.items():
         fn = getattr(lib, name)

@@ -70,3 +70,18 @@ def test_struct_sizes_match_the_header():
     assert ctypes.sizeof(L.NxFwdOut) == 12 * 8
     assert ctypes.sizeof(L.NxSurfels) == 7 * 8
     assert ctypes.sizeof(L.NxGrads) == 12 * 8
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """Importing the package before torch must not map a second HIP runtime next to torch's own copy (the
+    second one to open the device finds none)."""
+    import subprocess
+    import sys
+    code = ("import paper_2512_13796_amd, torch\n"
+            "print(sorted({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    import ast
+    mapped = ast.literal_eval(out.stdout.strip().splitlines()[-1])
+    assert len(mapped) == 1, mapped
