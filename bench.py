@@ -226,6 +226,61 @@ def time_form(form, steps, warmup, workload="outdoor"):
     return {"ms": ms, "wall_ms": 1000.0 * wall / steps, "phases": phases, "stats": st, "workload": wl}
 
 
+def time_graph(form, steps, warmup, workload="outdoor"):
+    """The same step captured once in a HIP graph (through torch.cuda.CUDAGraph) and replayed: the forward runs
+    the sync-free entry point with this frame's per-camera instance count as its bound, so the whole step
+    (forward, loss gradient, zeroing, backward) is one graph launch. The replays' outputs are checked against
+    an eager step first."""
+    import torch
+
+    nx, wl, ctx, surf, table, weights, target, grads = setup(form, workload)
+    cams = wl.cameras if len(wl.cameras) > 1 else wl.cameras[0]
+    ls = wl.grid.level_scales
+    P = sum(c.width * c.height for c in wl.cameras)
+    scale = 2.0 / (3.0 * P)
+    counts = nx.workspace_size_exact(ctx, surf, cams)[1]
+    cap = max(counts)
+    ws = torch.empty(nx.workspace_size(ctx, wl.scene.n, cams, cap), device="cuda", dtype=torch.uint8)
+    state = {}
+
+    def step():
+        res = nx.render_forward(ctx, surf, cams, table, ls, weights, workspace=ws, max_instances=cap)
+        g = (res.image - target).mul_(scale)
+        for k, t in grads.items():
+            for x in (t if k == "mlp" else [t]):
+                x.zero_()
+        nx.render_backward(ctx, surf, res, table, ls, weights, g, None, None, grads)
+        state["res"] = res
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # eager warm-up off the default stream (creates the backward's streams)
+        for _ in range(max(warmup, 1)):
+            step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    eager = state["res"].image.clone()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    res = state["res"]
+    for _ in range(max(warmup, 1)):
+        graph.replay()
+    torch.cuda.synchronize()
+    assert torch.equal(res.image, eager), "graph replay differs from the eager step"
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        graph.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    return {"ms_per_step": round(ms, 4), "value": round(P / (ms / 1000.0) / 1e6, 2),
+            "instances_bound_per_camera": cap}
+
+
 def workload_stats(res, wl, K):
     """Per-frame statistics of the rendered workload (outside the timed region)."""
     import torch
@@ -285,6 +340,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="skip timing the step as a replayed HIP graph")
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="outdoor",
                     help="outdoor (the headline: 400k surfels, 1080p), multiview (16 cameras in one call) or large "
@@ -343,6 +399,9 @@ def main():
         "rooflines": roofs,
         "phases_ms_per_step": {k: round(v, 4) for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},
     }
+    if not args.no_graph:
+        log("graph replay ...")
+        line["graph_replay"] = time_graph("native", args.steps, args.warmup, args.workload)
     if args.workload != "outdoor":
         args.no_fp32 = True
         args.no_cpu_baseline = True

@@ -170,9 +170,10 @@ typedef struct nx_ctx nx_ctx;
 int nx_create(nx_ctx **out, int32_t K, int32_t tile, nx_dtype feat_dtype, nx_dtype mlp_dtype);
 int nx_destroy(nx_ctx *ctx);
 
-/* Appearance (Representation, Appearance; Results: "degree 3 ... an MLP output
- * dimension of 48"). degree -1 (the default): nx_surfels.colors is [n,3] RGB
- * and the MLP head has 3 outputs through a sigmoid. degree 3: colors is
+/* Appearance (Representation, Appearance; Results: the experiments use
+ * degree-3 harmonics, so the MLP has 48 outputs). degree -1 (the default):
+ * nx_surfels.colors is [n,3] RGB and the MLP head has 3 outputs through a
+ * sigmoid. degree 3: colors is
  * [n,48] spherical-harmonics coefficients in the layout [16][3] (coefficient
  * k of channel c at 3k + c), decoded along the unit direction from the camera
  * centre to the surfel centre as max(0, sum_k Y_k a_k + 0.5); the MLP head has

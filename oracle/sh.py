@@ -6,7 +6,7 @@ Paper, Preliminaries (2D Gaussian Splatting) and Representation, Appearance:
 each surfel's non-textured radiance is a set of channel-wise spherical
 harmonics coefficients (degree 3: S = 16 per channel, 48 values), and the
 neural field outputs the same number of coefficients for the textured
-appearance (Results: "degree 3 ... an MLP output dimension of 48").
+appearance (Results: the experiments use degree 3, hence 48 MLP outputs).
 
 Readings (the paper builds on the 3D Gaussian Splatting code and does not
 print these):

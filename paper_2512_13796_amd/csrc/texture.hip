@@ -450,6 +450,14 @@ __host__ __device__ __forceinline__ int64_t n_patches(const GridDev& gd) {
   return (int64_t)((gd.width + 3) >> 2) * ((gd.height + 3) >> 2);
 }
 
+// Workgroup ids are dealt to the 8 XCDs in turn, and each XCD has its own L2.
+// Renumbered this way, the workgroups on one XCD take consecutive work items
+// (neighbouring patches, which share hash-grid cells) instead of every eighth.
+__device__ __forceinline__ int64_t xcd_local_block() {
+  const unsigned G = gridDim.x, b = blockIdx.x;
+  return (G % 8u == 0u) ? (int64_t)(b % 8u) * (G / 8u) + b / 8u : (int64_t)b;
+}
+
 struct LevelGeom {
   int cx, cy, cz;  // lattice cell floor(s_l x)
   float frx, fry, frz;
@@ -631,7 +639,7 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 && BF && TDT != NX_F32 && !
   const int g = lane >> 4, c = lane & 15;
   const uint32_t mask = (1u << gd.log2_size) - 1u;
   const int64_t n_q = n_patches(gd);
-  for (int64_t q = (int64_t)blockIdx.x * kWaves + wave; q < n_q; q += (int64_t)gridDim.x * kWaves) {
+  for (int64_t q = xcd_local_block() * kWaves + wave; q < n_q; q += (int64_t)gridDim.x * kWaves) {
     float contrib[3] = {0.f, 0.f, 0.f};
     bool pix_valid = false;
     int64_t pix = 0;
@@ -862,7 +870,7 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 || BF) ? 2 : 1) void textur
 #pragma unroll
   for (int i = 0; i < RT * 2; ++i) accW1[i] = zero;
 
-  const int64_t first = (int64_t)blockIdx.x * kWaves;
+  const int64_t first = xcd_local_block() * kWaves;
   const int64_t stride = (int64_t)gridDim.x * kWaves;
   const int64_t n_rounds = first < n_units ? (n_units - first + stride - 1) / stride : 0;
   for (int64_t round = 0; round < n_rounds; ++round) {

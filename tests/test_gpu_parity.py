@@ -231,7 +231,12 @@ def _grad_case(nx, wl, K=None, label="", feat_dtype=None, mlp_dtype=None, pixels
     for k, r in report.items():
         assert r["rel_l2"] <= rel_tol, f"{label}: {k} rel L2 {r['rel_l2']:.3e} > {rel_tol}"
         if bf16_bound is None:
-            assert r["viol_coarse"] <= viol_tol, f"{label}: {k} per-element violations {r['viol_coarse']:.3e}"
+            # FP32 form: every element within 1e-3 max(|g|, 1e-2 rms) but for a fraction viol_tol. An MLP
+            # weight-gradient element sums one term per sample (thousands), and with random upstream gradients
+            # the terms cancel (the sum is about n^-1/2 of their magnitudes), so FP32 accumulation leaves every
+            # element an absolute error of 1e-5 to 1e-4 rms whatever its size: for them the floor is 1e-1 rms.
+            viol = r["viol_coarse"] if k.startswith("mlp") else r["viol"]
+            assert viol <= viol_tol, f"{label}: {k} per-element violations {viol:.3e}"
         else:
             # BF16 operands: elements within BF16_ELEM max(|g|, rms(g)), but for a fraction bf16_bound
             assert r["viol_bf16"] <= bf16_bound, \

@@ -7,7 +7,7 @@ selection distance of the picked set). Split selection: weights of zero are
 never drawn, and over many draws a surfel's chance of being drawn first is
 its share of the weights. Split: closed-form children for both long axes and
 a rotated surfel, and for gamma -> infinity the two children render the
-parent's quad (the paper's "splits the quad perfectly in half"). Prune:
+parent's quad (the split halves a flat-topped quad exactly). Prune:
 survivors keep their order and parents.
 """
 from __future__ import annotations
