@@ -33,9 +33,11 @@ HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}  # dense matrix peaks of the MI355X per operand type
 # VALU peak: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz = 39.3e12 lane-instructions/s (packed FP32 is off)
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# VALU instructions per (pixel, surfel) pair the collection pass tests: the gamma = 1 path of the inner loop
-# counts 27 from the record reads to the alpha threshold; composited pairs add the K-buffer and colour update.
-RASTER_OPS_PER_PAIR = 30
+# VALU lane-instructions per (pixel, surfel) pair the collection pass tests, from SQ_INSTS_VALU x 64 over the
+# tested pairs of the 1080p frame: the forward evaluates the pair (27 on the gamma = 1 path up to the alpha
+# threshold) and updates the K-buffer and colour of composited pairs; the backward re-evaluates the pair, forms
+# its 16 record gradients and sums them across the wave once per surfel.
+RASTER_OPS_PER_PAIR = {"raster_forward": 38, "raster_backward": 88}
 
 
 def log(*a):
@@ -75,7 +77,7 @@ def method_work(phase, st):
         "preprocess_backward": C * N * (36 + 4 + 64 + 2 * 60),
     }
     flops = {"texture_forward": mlp_flops, "texture_backward": 3.0 * mlp_flops}
-    valu = {"raster_forward": pairs * RASTER_OPS_PER_PAIR, "raster_backward": pairs * RASTER_OPS_PER_PAIR}
+    valu = {k: pairs * v for k, v in RASTER_OPS_PER_PAIR.items()}
     bound = "mfma" if phase in flops else ("alu" if phase in valu else "hbm")
     return bound, float(hbm.get(phase, 0)), float(flops.get(phase, 0.0)), float(valu.get(phase, 0.0))
 
