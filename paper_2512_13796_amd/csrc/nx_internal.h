@@ -222,7 +222,7 @@ inline int scatter_buckets(int log2_size) { return 1 << (log2_size - scatter_buc
 // Slabs of one camera's bin launch: workgroups and records per (workgroup,
 // bucket) slab, sized for 5/4 of the worst case (every corner of every
 // sample a record) spread evenly over the buckets.
-constexpr int kScatWorkgroups = 1024;
+constexpr int kScatWorkgroups = 2048;
 constexpr int kBlockRecords = 4096;  // at most 8 corner records per sample
 struct ScatterSlabs {
   int64_t wgs, slab;

@@ -738,20 +738,24 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 && BF && TDT != NX_F32 && !
 // Row r of a BF16 activation tile starts at element 16 tile_row(r): after
 // every 4 rows of 16 samples (32 dwords) the tile skips 8 dwords, so that the
 // four lane groups of a wave, which write rows 4 g + r of one column, reach
-// four different bank groups instead of the same one. (The FP32 tiles are not
-// padded: their 16-lane row writes use half the banks anyway, and padding
-// would take a workgroup's place on the CU.)
-template <bool BF>
+// four different bank groups instead of the same one. Only the BF16 tiles of
+// hidden width 64 are padded: the FP32 tiles' 16-lane row writes use half the
+// banks anyway, and at hidden width 128 the padding would cost a workgroup's
+// place on the CU (the padded tiles need more than half its LDS).
+template <bool BF, int HID>
+constexpr bool kPadTiles = BF && HID <= 64;
+
+template <bool PAD>
 __device__ __forceinline__ int tile_row(int r) {
-  return BF ? r + (r >> 2) : r;
+  return PAD ? r + (r >> 2) : r;
 }
 
 // Write a register tile set (rows 16 mt + 4 g + r, column c) into an LDS
 // [rows][16] matrix.
-template <bool BF>
+template <bool BF, bool PAD>
 __device__ __forceinline__ void put_rows(unsigned char* buf, int row, int c, float v) {
   if constexpr (BF) {
-    reinterpret_cast<short*>(buf)[tile_row<BF>(row) * 16 + c] = f2bf(v);
+    reinterpret_cast<short*>(buf)[tile_row<PAD>(row) * 16 + c] = f2bf(v);
   } else {
     reinterpret_cast<float*>(buf)[row * 16 + c] = v;
   }
@@ -759,11 +763,11 @@ __device__ __forceinline__ void put_rows(unsigned char* buf, int row, int c, flo
 
 // Rows row0 .. row0 + 3 of column c from a register tile (rows 4 g + r):
 // two values per conversion for BF16.
-template <bool BF>
+template <bool BF, bool PAD>
 __device__ __forceinline__ void put_rows4(unsigned char* buf, int row0, int c, f4 v) {
   if constexpr (BF) {
     const uint32_t w01 = pack_bf16x2(v[0], v[1]), w23 = pack_bf16x2(v[2], v[3]);
-    short* p = reinterpret_cast<short*>(buf) + tile_row<BF>(row0) * 16 + c;  // row0 % 4 == 0
+    short* p = reinterpret_cast<short*>(buf) + tile_row<PAD>(row0) * 16 + c;  // row0 % 4 == 0
     p[0] = (short)(w01 & 0xFFFFu);
     p[16] = (short)(w01 >> 16);
     p[32] = (short)(w23 & 0xFFFFu);
@@ -779,7 +783,7 @@ __device__ __forceinline__ void put_rows4(unsigned char* buf, int row0, int c, f
 // tiles mo < NMO and column tiles mi < NMI: acc[mo * NMI + mi] += the
 // 16-sample contribution (samples are the K index of the product), reading
 // Y and X from LDS [rows][16] tiles.
-template <bool BF, int NMO, int NMI>
+template <bool BF, bool PAD, int NMO, int NMI>
 __device__ __forceinline__ void weight_grad_accum(const unsigned char* Y, const unsigned char* X,
                                                   f4 (&acc)[NMO * NMI], int lane) {
   const int g = lane >> 4, c = lane & 15;
@@ -790,9 +794,9 @@ __device__ __forceinline__ void weight_grad_accum(const unsigned char* Y, const 
       f4& d = acc[mo * NMI + mi];
       if constexpr (BF) {
         // Y and X start at a row that is a multiple of 4, so relative rows pad alike
-        const s4 a = *reinterpret_cast<const s4*>(reinterpret_cast<const short*>(Y) + tile_row<BF>(16 * mo + c) * 16 +
+        const s4 a = *reinterpret_cast<const s4*>(reinterpret_cast<const short*>(Y) + tile_row<PAD>(16 * mo + c) * 16 +
                                                   4 * g);
-        const s4 b = *reinterpret_cast<const s4*>(reinterpret_cast<const short*>(X) + tile_row<BF>(16 * mi + c) * 16 +
+        const s4 b = *reinterpret_cast<const s4*>(reinterpret_cast<const short*>(X) + tile_row<PAD>(16 * mi + c) * 16 +
                                                   4 * g);
         d = mfma_bf16_k16(a, b, d);
       } else {
@@ -817,7 +821,7 @@ struct UnitTiles {
   static constexpr int oY3 = 0, oX3 = 16 * WLayout<BF, HID, SH>::OT, oY2 = oX3 + HID, oX2 = oY2 + HID,
                        oY1 = oX2 + HID, oX1 = oY1 + HID;
   static constexpr int rows = oX1 + kInPad;
-  static constexpr int bytes = (BF ? rows + rows / 4 : rows) * 16 * elem;
+  static constexpr int bytes = (kPadTiles<BF, HID> ? rows + rows / 4 : rows) * 16 * elem;
 };
 
 // WLDS: operand slots staged in LDS by every workgroup (hidden width 64), or
@@ -857,7 +861,8 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 || BF) ? 2 : 1) void textur
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, c = lane & 15;
   unsigned char* T = tiles + wave * UT::bytes;  // this wave's unit
-  auto row_ptr = [&](const unsigned char* base, int row) { return base + tile_row<BF>(row) * 16 * UT::elem; };
+  constexpr bool PAD = kPadTiles<BF, HID>;
+  auto row_ptr = [&](const unsigned char* base, int row) { return base + tile_row<PAD>(row) * 16 * UT::elem; };
   const uint32_t mask = (1u << gd.log2_size) - 1u;
   const int64_t n_q = n_patches(gd);
   const int64_t n_units = n_q * K;
@@ -932,9 +937,9 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 || BF) ? 2 : 1) void textur
       // activations die early (h2 after layer 3, dH2 and h1 after layer 2).
       f4 dzt[2];
 #pragma unroll
-      for (int ot = 0; ot < OT; ++ot) put_rows4<BF>(T, UT::oY3 + 16 * ot + 4 * g, c, dlog[ot]);
+      for (int ot = 0; ot < OT; ++ot) put_rows4<BF, PAD>(T, UT::oY3 + 16 * ot + 4 * g, c, dlog[ot]);
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) put_rows4<BF>(T, UT::oX3 + 16 * mt + 4 * g, c, h2[mt]);
+      for (int mt = 0; mt < MT; ++mt) put_rows4<BF, PAD>(T, UT::oX3 + 16 * mt + 4 * g, c, h2[mt]);
       f4 dh2[MT];
       if constexpr (BF) {
         constexpr int HO = LY::HO;
@@ -966,8 +971,8 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 || BF) ? 2 : 1) void textur
       }
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
-        put_rows4<BF>(T, UT::oY2 + 16 * mt + 4 * g, c, dh2[mt]);
-        put_rows4<BF>(T, UT::oX2 + 16 * mt + 4 * g, c, h1[mt]);
+        put_rows4<BF, PAD>(T, UT::oY2 + 16 * mt + 4 * g, c, dh2[mt]);
+        put_rows4<BF, PAD>(T, UT::oX2 + 16 * mt + 4 * g, c, h1[mt]);
       }
       f4 dh1[MT];
       if constexpr (BF) {
@@ -999,9 +1004,9 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 || BF) ? 2 : 1) void textur
         }
       }
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) put_rows4<BF>(T, UT::oY1 + 16 * mt + 4 * g, c, dh1[mt]);
+      for (int mt = 0; mt < MT; ++mt) put_rows4<BF, PAD>(T, UT::oY1 + 16 * mt + 4 * g, c, dh1[mt]);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) put_rows<BF>(T, UT::oX1 + feat_index(g, e), c, z[e]);
+      for (int e = 0; e < 8; ++e) put_rows<BF, PAD>(T, UT::oX1 + feat_index(g, e), c, z[e]);
       if constexpr (BF) {
         constexpr int HT = LY::HT;
         s8 b1[HT];
@@ -1052,9 +1057,9 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 || BF) ? 2 : 1) void textur
 #pragma unroll 1
     for (int u = 0; u < kWaves; ++u) {
       const unsigned char* U = tiles + u * UT::bytes;
-      weight_grad_accum<BF, OT, CT3>(row_ptr(U, UT::oY3), row_ptr(U, UT::oX3 + 16 * CT3 * wave), accW3, lane);
-      weight_grad_accum<BF, RT, MT>(row_ptr(U, UT::oY2 + 16 * RT * wave), row_ptr(U, UT::oX2), accW2, lane);
-      weight_grad_accum<BF, RT, 2>(row_ptr(U, UT::oY1 + 16 * RT * wave), row_ptr(U, UT::oX1), accW1, lane);
+      weight_grad_accum<BF, PAD, OT, CT3>(row_ptr(U, UT::oY3), row_ptr(U, UT::oX3 + 16 * CT3 * wave), accW3, lane);
+      weight_grad_accum<BF, PAD, RT, MT>(row_ptr(U, UT::oY2 + 16 * RT * wave), row_ptr(U, UT::oX2), accW2, lane);
+      weight_grad_accum<BF, PAD, RT, 2>(row_ptr(U, UT::oY1 + 16 * RT * wave), row_ptr(U, UT::oX1), accW1, lane);
     }
     __syncthreads();
   }
