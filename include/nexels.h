@@ -269,6 +269,22 @@ int nx_instance_counts(nx_ctx *ctx, int64_t n_surfels, const nx_camera *cams, in
                        const int64_t *n_instances, const void *workspace, size_t workspace_bytes, int64_t *counts,
                        void *stream);
 
+/* Launch-shape tuning of the collection pass (the tiled rasteriser of the
+ * Preliminaries section): each 16x16-pixel tile stages the records of its
+ * surfels in LDS in rounds of `batch` records (64, 128 or 256; 256 unless
+ * tuned). nx_autotune_raster times the collection-pass forward kernel of every
+ * camera with each batch size, `reps` times after one warm-up (1 <= reps <=
+ * 100), on the sorted tile lists a finished nx_render_forward (or _async)
+ * left in `workspace` for these surfels and cameras (`out` as that call
+ * returned it), and keeps the fastest for this context, keyed by K and the
+ * cameras' sizes: later forward and backward calls over cameras of those
+ * sizes use it. The kernel rewrites the collection pass's outputs in `out`
+ * with the same values (the batch size does not change any result).
+ * Synchronises the stream; *batch (host) receives the choice. */
+int nx_autotune_raster(nx_ctx *ctx, const nx_surfels *surfels, const nx_camera *cams, int32_t n_cams,
+                       const nx_fwd_out *out, const void *workspace, size_t workspace_bytes, int32_t reps,
+                       int32_t *batch, void *stream);
+
 /* Gradients of L through both passes given dL/dimage [P,3] (device) and the
  * optional dL/dweights [P,K] and dL/dtex [P,K,3] (device, NULL = zero), all
  * cameras concatenated as in the forward; the cameras' gradients add up in

@@ -8,11 +8,10 @@ from . import _lib
 
 _lib.load()
 
-from .render import (Context, ForwardResult, RenderFunction, aux_losses, camera_struct, densify, fps,  # noqa: E402,F401
-                     instance_counts, render, render_backward, render_forward, render_forward_noalloc, workspace_size,
-                     workspace_size_exact)
+from .render import (Context, ForwardResult, RenderFunction, autotune_raster, aux_losses,  # noqa: E402,F401
+                     camera_struct, densify, fps, instance_counts, render, render_backward, render_forward,
+                     render_forward_noalloc, workspace_size, workspace_size_exact)
 
-__all__ = ["Context", "ForwardResult", "RenderFunction", "aux_losses", "camera_struct", "densify", "fps",
-           "instance_counts", "render",
-           "render_backward", "render_forward", "render_forward_noalloc", "workspace_size",
-           "workspace_size_exact"]
+__all__ = ["Context", "ForwardResult", "RenderFunction", "autotune_raster", "aux_losses", "camera_struct", "densify",
+           "fps", "instance_counts", "render", "render_backward", "render_forward", "render_forward_noalloc",
+           "workspace_size", "workspace_size_exact"]

@@ -107,6 +107,9 @@ SIGNATURES = {
     "nx_densify": ([c_void_p, ctypes.POINTER(NxSurfels), c_void_p, c_void_p, ctypes.c_int64, ctypes.c_float,
                     ctypes.POINTER(NxSurfelsOut), ctypes.POINTER(ctypes.c_int64), c_void_p, ctypes.c_size_t,
                     c_void_p], ctypes.c_int),
+    "nx_autotune_raster": ([c_void_p, ctypes.POINTER(NxSurfels), ctypes.POINTER(NxCamera), ctypes.c_int32,
+                            ctypes.POINTER(NxFwdOut), c_void_p, ctypes.c_size_t, ctypes.c_int32,
+                            ctypes.POINTER(ctypes.c_int32), c_void_p], ctypes.c_int),
     "nx_instance_counts": ([c_void_p, ctypes.c_int64, ctypes.POINTER(NxCamera), ctypes.c_int32,
                             ctypes.POINTER(ctypes.c_int64), c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int64),
                             c_void_p], ctypes.c_int),

@@ -3,6 +3,8 @@
 #include <math.h>
 #include <stdio.h>
 
+#include <map>
+
 #include <mutex>
 #include <string>
 #include <vector>
@@ -29,6 +31,12 @@ struct nx_ctx {
   int debug_cas = 0;       // > 0: LDS compare-and-swap retries before a global atomic
   uint32_t* pinned;  // one host word for the instance-count readback
   bool timing;
+  // Collection-pass records staged in LDS per round, chosen by
+  // nx_autotune_raster per camera configuration (key: K and every camera's
+  // size); configurations not tuned use the default. `batch` is the value
+  // for the call in progress.
+  std::map<std::string, int> tuned_batch;
+  int batch = nx::kRasterBatchDefault;
   // The backward's extra streams (default priority) and the events that
   // order them with the call's stream: `side` runs each level's hash-scatter
   // reduction while the next level is binned, `side2` the collection-pass
@@ -50,6 +58,18 @@ thread_local std::string g_last_error;
 int fail(int code, const std::string& msg) {
   g_last_error = msg;
   return code;
+}
+
+std::string camera_key(int K, const nx_camera* cams, int32_t n_cams) {
+  std::string k = std::to_string(K);
+  for (int32_t c = 0; c < n_cams; ++c) k += ":" + std::to_string(cams[c].width) + "x" + std::to_string(cams[c].height);
+  return k;
+}
+
+// Selects the collection pass's LDS batch for a call over these cameras.
+void select_batch(nx_ctx* ctx, const nx_camera* cams, int32_t n_cams) {
+  const auto it = ctx->tuned_batch.find(camera_key(ctx->K, cams, n_cams));
+  ctx->batch = it == ctx->tuned_batch.end() ? nx::kRasterBatchDefault : it->second;
 }
 
 #define NX_CHECK_HIP(expr)                                                                 \
@@ -115,16 +135,18 @@ Layout make_layout(int64_t n, const nx::CamDev& cd, int K, int64_t n_inst, bool 
 // at the start of the workspace, before the per-camera sections.
 struct SharedLayout {
   // two arenas: level l files into arena l % 2 while level l - 1 is reduced
-  size_t rec_key[2], rec_val[2], slab_table[2], total;
+  size_t rec_key[2], rec_val[2], slab_table[2], cams, total;
   int64_t capacity;  // records per arena
-  int64_t rows;      // slab-table rows (bin workgroups over all cameras)
+  int64_t rows;      // slab-table rows (workgroups of the joint bin launch)
+  int64_t blocks;    // bin blocks over all cameras
 };
 
 SharedLayout make_shared_layout(const nx_camera* cams, int32_t n_cams, int K) {
   SharedLayout S{};
-  for (int32_t c = 0; c < n_cams && K > 0; ++c) {
-    S.capacity += nx::scatter_record_capacity(cams[c].width, cams[c].height, K);
-    S.rows += nx::scatter_slabs(cams[c].width, cams[c].height, K, 1).wgs;
+  for (int32_t c = 0; c < n_cams && K > 0; ++c) S.blocks += nx::scatter_blocks(cams[c].width, cams[c].height, K);
+  if (S.blocks > 0) {
+    S.capacity = nx::scatter_record_capacity_blocks(S.blocks);
+    S.rows = nx::scatter_slabs_blocks(S.blocks, 1).wgs;
   }
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -137,6 +159,7 @@ SharedLayout make_shared_layout(const nx_camera* cams, int32_t n_cams, int K) {
     S.rec_val[a] = take(sizeof(float2) * (size_t)S.capacity);
     S.slab_table[a] = take(sizeof(uint2) * (size_t)S.rows * nx::kScatMaxBuckets);
   }
+  S.cams = take(S.blocks > 0 ? sizeof(nx::ScatterCam) * (size_t)n_cams : 0);
   S.total = o;
   return S;
 }
@@ -439,7 +462,7 @@ int forward_one(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera& cam, co
   {
   PhaseTimer pt(ctx, "raster_forward", s);
   NX_CHECK_HIP(nx::launch_raster_forward(K, records, iid, ranges, cd, out->plain, out->ids, out->weights,
-                                         out->depths, out->t_final, out->n_iter, s));
+                                         out->depths, out->t_final, out->n_iter, ctx->batch, s));
   }
   nx::GridDev gd = make_grid(cam, grid);
   nx::MlpDev md{};
@@ -480,7 +503,7 @@ int backward_one(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera& cam, c
       NX_CHECK_HIP(nx::launch_raster_backward(K, at<float4>(ws, L.records), at<uint32_t>(ws, L.inst_ids),
                                               at<uint2>(ws, L.tile_ranges), cd, saved->plain, saved->ids,
                                               saved->weights, saved->tex, saved->n_iter, grad_image, grad_weights,
-                                              K > 0 ? gdepth : nullptr, pixel_error, rec_grad, s));
+                                              K > 0 ? gdepth : nullptr, pixel_error, rec_grad, ctx->batch, s));
     }
     PhaseTimer pt(ctx, "preprocess_backward", s);
     NX_CHECK_HIP(nx::launch_preprocess_backward(surfels->means, surfels->quats, surfels->scales, surfels->colors,
@@ -751,6 +774,7 @@ int nx_render_forward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* c
   if (ctx->K > 0 && (!out->ids || !out->weights || !out->depths || !out->tex))
     return fail(NX_ERR_INVALID, "an output pointer is NULL");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  select_batch(ctx, cams, n_cams);
   NX_CHECK_HIP(hipGetLastError());
   size_t off = make_shared_layout(cams, n_cams, ctx->K).total;
   int64_t pix = 0;
@@ -802,6 +826,7 @@ int nx_render_forward_async(nx_ctx* ctx, const nx_surfels* surfels, const nx_cam
   if (!workspace || workspace_bytes < total)
     return fail(NX_ERR_WORKSPACE, "workspace smaller than nx_workspace_size(..., max_instances)");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  select_batch(ctx, cams, n_cams);
   NX_CHECK_HIP(hipGetLastError());
   size_t off = SH.total;
   int64_t pix = 0;
@@ -845,6 +870,7 @@ int nx_render_forward_noalloc(nx_ctx* ctx, const nx_surfels* surfels, const nx_c
   void* ws = nullptr;
   if ((r = scratch_address(&ws)) != NX_OK) return r;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  select_batch(ctx, cams, n_cams);
   NX_CHECK_HIP(hipGetLastError());
   TimingOff no_events(ctx);
   size_t off = 0;
@@ -1033,6 +1059,76 @@ int nx_instance_counts(nx_ctx* ctx, int64_t n_surfels, const nx_camera* cams, in
   return NX_OK;
 }
 
+int nx_autotune_raster(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* cams, int32_t n_cams,
+                       const nx_fwd_out* out, const void* workspace, size_t workspace_bytes, int32_t reps,
+                       int32_t* batch, void* stream) {
+  int r;
+  if ((r = check_ctx(ctx)) != NX_OK) return r;
+  if ((r = check_surfels(surfels)) != NX_OK) return r;
+  if ((r = check_camera(cams, n_cams)) != NX_OK) return r;
+  if (!out || !out->plain || !out->t_final || !out->n_iter || !out->n_instances)
+    return fail(NX_ERR_INVALID, "an output pointer is NULL");
+  if (ctx->K > 0 && (!out->ids || !out->weights || !out->depths))
+    return fail(NX_ERR_INVALID, "an output pointer is NULL");
+  if (reps < 1 || reps > 100) return fail(NX_ERR_INVALID, "reps must be in [1, 100]");
+  if (!batch) return fail(NX_ERR_INVALID, "batch is NULL");
+  size_t total = make_shared_layout(cams, n_cams, ctx->K).total;
+  for (int32_t c = 0; c < n_cams; ++c) {
+    if (out->n_instances[c] < 0) return fail(NX_ERR_INVALID, "n_instances is negative");
+    total += make_layout(surfels->n, make_cam(cams[c]), ctx->K, out->n_instances[c]).total;
+  }
+  if (!workspace || workspace_bytes < total) return fail(NX_ERR_INVALID, "workspace does not match the forward");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  NX_CHECK_HIP(hipGetLastError());
+  struct Events {
+    hipEvent_t e[2] = {nullptr, nullptr};
+    ~Events() {
+      for (hipEvent_t x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } ev;
+  NX_CHECK_HIP(hipEventCreate(&ev.e[0]));
+  NX_CHECK_HIP(hipEventCreate(&ev.e[1]));
+  const int64_t K = ctx->K;
+  // the collection pass of every camera with LDS batch b
+  auto run = [&](int b) -> hipError_t {
+    size_t off = make_shared_layout(cams, n_cams, ctx->K).total;
+    int64_t pix = 0;
+    for (int32_t c = 0; c < n_cams; ++c) {
+      const nx::CamDev cd = make_cam(cams[c]);
+      const Layout L = make_layout(surfels->n, cd, ctx->K, out->n_instances[c]);
+      char* ws = const_cast<char*>(static_cast<const char*>(workspace)) + off;
+      const hipError_t e = nx::launch_raster_forward(
+          ctx->K, at<float4>(ws, L.records), at<uint32_t>(ws, L.inst_ids), at<uint2>(ws, L.tile_ranges), cd,
+          out->plain + 3 * pix, K > 0 ? out->ids + K * pix : nullptr, K > 0 ? out->weights + K * pix : nullptr,
+          K > 0 ? out->depths + K * pix : nullptr, out->t_final + pix, out->n_iter + pix, b, s);
+      if (e != hipSuccess) return e;
+      off += L.total;
+      pix += (int64_t)cams[c].width * cams[c].height;
+    }
+    return hipSuccess;
+  };
+  int best_b = nx::kRasterBatchDefault;
+  float best_ms = 0.0f;
+  for (int b : nx::kRasterBatches) {
+    NX_CHECK_HIP(run(b));  // warm-up
+    NX_CHECK_HIP(hipEventRecord(ev.e[0], s));
+    for (int32_t k = 0; k < reps; ++k) NX_CHECK_HIP(run(b));
+    NX_CHECK_HIP(hipEventRecord(ev.e[1], s));
+    NX_CHECK_HIP(hipEventSynchronize(ev.e[1]));
+    float ms = 0.0f;
+    NX_CHECK_HIP(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
+    if (b == nx::kRasterBatches[0] || ms < best_ms) {
+      best_ms = ms;
+      best_b = b;
+    }
+  }
+  ctx->tuned_batch[camera_key(ctx->K, cams, n_cams)] = best_b;
+  *batch = best_b;
+  g_last_error.clear();
+  return NX_OK;
+}
+
 int nx_render_backward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* cams, int32_t n_cams,
                        const nx_hashgrid* grid, const nx_mlp* mlp, const nx_fwd_out* saved, const void* workspace,
                        size_t workspace_bytes, const float* grad_image, const float* grad_weights,
@@ -1058,6 +1154,7 @@ int nx_render_backward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* 
   }
   if (!workspace || workspace_bytes < total) return fail(NX_ERR_INVALID, "workspace does not match the forward");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  select_batch(ctx, cams, n_cams);
   NX_CHECK_HIP(hipGetLastError());
   void* ws = const_cast<void*>(workspace);
   const int64_t K = ctx->K > 0 ? ctx->K : 0;
@@ -1088,11 +1185,35 @@ int nx_render_backward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* 
       pix += (int64_t)cams[c].width * cams[c].height;
     }
   }
-  // 2. hash-grid gradient, level by level: every camera files its records,
-  //    then one reduction per level for all of them
-  if (K > 0 && grads->table) {
+  // 2. hash-grid gradient, level by level: one joint bin launch files the
+  //    records of every camera, then one reduction per level
+  if (K > 0 && grads->table && SH.blocks > 0) {
     const nx::GridDev gd0 = make_grid(cams[0], grid);
-    const int nb = nx::scatter_buckets(gd0.log2_size);
+    nx::ScatterCam* dcams = at<nx::ScatterCam>(ws, SH.cams);
+    nx::ScatterCam cam0{};
+    {
+      size_t coff = SH.total;
+      int64_t cpix = 0, blk0 = 0;
+      for (int32_t c = 0; c < n_cams; ++c) {
+        const nx::CamDev cd = make_cam(cams[c]);
+        const Layout L = make_layout(surfels->n, cd, ctx->K, saved->n_instances[c]);
+        const nx::ScatterGeom sg = nx::scatter_geom(cams[c].width, cams[c].height, ctx->K);
+        nx::ScatterCam sc;
+        sc.gd = make_grid(cams[c], grid);
+        sc.depths = saved->depths + K * cpix;
+        sc.feat_grad = at<float2>(ws, coff + L.feat_grad);
+        sc.bw = sg.bw;
+        sc.bh = sg.bh;
+        sc.nbx = sg.nbx;
+        sc.nby = sg.nby;
+        sc.blk0 = blk0;
+        if (c == 0) cam0 = sc;
+        if (n_cams > 1) NX_CHECK_HIP(nx::launch_write_scatter_cam(sc, dcams + c, s));
+        blk0 += (int64_t)sg.nbx * sg.nby;
+        coff += L.total;
+        cpix += (int64_t)cams[c].width * cams[c].height;
+      }
+    }
     // Level l: bin on the call's stream into arena l % 2, reduce on the side
     // stream; the bin of level l + 2 waits for the reduce of level l (same
     // arena), the reduce of level l for its own bin; the call's stream waits
@@ -1105,21 +1226,10 @@ int nx_render_backward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* 
       float2* rv = at<float2>(ws, SH.rec_val[a]);
       uint2* tab = at<uint2>(ws, SH.slab_table[a]);
       if (l >= 2) NX_CHECK_HIP(hipStreamWaitEvent(s, ctx->ev_red[a], 0));
-      size_t coff = SH.total;
-      int64_t cpix = 0, row0 = 0, slab0 = 0;
-      for (int32_t c = 0; c < n_cams; ++c) {
-        const nx::CamDev cd = make_cam(cams[c]);
-        const Layout L = make_layout(surfels->n, cd, ctx->K, saved->n_instances[c]);
-        const nx::GridDev gd = make_grid(cams[c], grid);
+      {
         PhaseTimer pt(ctx, "scatter_bin", s);
-        NX_CHECK_HIP(nx::launch_hash_scatter_bin(ctx->K, gd, l, saved->depths + K * cpix,
-                                                 at<float2>(ws, coff + L.feat_grad), grads->table,
-                                                 (uint32_t)slab0, row0, SH.rows, tab, rk, rv, ctx->debug_slab, s));
-        const nx::ScatterSlabs sb = nx::scatter_slabs(cams[c].width, cams[c].height, ctx->K, nb);
-        row0 += sb.wgs;
-        slab0 += sb.wgs * nb * sb.slab;
-        coff += L.total;
-        cpix += (int64_t)cams[c].width * cams[c].height;
+        NX_CHECK_HIP(nx::launch_hash_scatter_bin(ctx->K, cam0, dcams, n_cams, SH.blocks, gd0, l, grads->table,
+                                                 SH.rows, tab, rk, rv, ctx->debug_slab, s));
       }
       NX_CHECK_HIP(hipEventRecord(ctx->ev_bin[a], s));
       NX_CHECK_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_bin[a], 0));

@@ -62,6 +62,8 @@ struct GridDev {
   int width, height;
 };
 
+struct ScatterCam;  // one camera's share of a joint hash-scatter launch (below)
+
 // ---------------------------------------------------------------- launchers
 // sh: colors holds 48 spherical-harmonics coefficients per surfel ([16][3])
 // decoded along the direction from the camera centre, instead of RGB.
@@ -100,15 +102,19 @@ hipError_t launch_duplicate(const uint32_t* order, const uint32_t* offsets, cons
 hipError_t launch_tile_ranges(const uint32_t* tile_keys, int64_t n_inst, uint2* ranges, int n_tiles,
                               hipStream_t s, const uint32_t* n_dev = nullptr);
 
+// Collection pass (one 16x16 tile per workgroup). batch: records staged in
+// LDS per round, one of kRasterBatches.
+constexpr int kRasterBatches[3] = {64, 128, 256};
+constexpr int kRasterBatchDefault = 256;
 hipError_t launch_raster_forward(int K, const float4* records, const uint32_t* sorted_ids, const uint2* ranges,
                                  const CamDev& cam, float* plain, int32_t* ids, float* weights, float* depths,
-                                 float* t_final, uint32_t* n_iter, hipStream_t s);
+                                 float* t_final, uint32_t* n_iter, int batch, hipStream_t s);
 
 hipError_t launch_raster_backward(int K, const float4* records, const uint32_t* sorted_ids, const uint2* ranges,
                                   const CamDev& cam, const float* plain, const int32_t* ids,
                                   const float* weights, const float* tex, const uint32_t* n_iter,
                                   const float* grad_image, const float* grad_weights, const float* grad_depth,
-                                  const float* pixel_error, float* rec_grad, hipStream_t s);
+                                  const float* pixel_error, float* rec_grad, int batch, hipStream_t s);
 
 struct MlpDev {
   const void* w[3];
@@ -142,23 +148,24 @@ constexpr size_t kWeightOperandBytes = 256 * 1024;
 // corner contributions are filed as records under buckets (fixed ranges of
 // table entries), then one workgroup per bucket sums its records and updates
 // that range of g_table (no floating-point global atomics).
-// bin runs once per camera and level, then reduce once per level.
-// Records are filed in slabs: the bin launch for a camera runs `wgs`
-// persistent workgroups, and workgroup w keeps the records of bucket b in
-// its own slab of `slab` records at arena offset slab0 + (w nb + b) slab; it
-// ends by writing (slab start, records in it) to row row0 + w of the bucket's
-// slab-table column (slab_table[b * n_rows + row]). A slab that fills up
-// sends further records straight to the table with atomics (correct,
-// slower). slab_cap > 0 shrinks the slabs and cas_rounds > 0 bounds the
-// reduction's LDS compare-and-swap retries (then a global atomic), to
-// exercise both fallbacks in tests; 0 keeps the defaults. The arena (rec_key, rec_val) and the slab table are shared by all
-// cameras of a call: camera c takes the next wgs rows and the next
-// wgs * nb * slab records.
-hipError_t launch_hash_scatter_bin(int K, const GridDev& grid, int level, const float* depths,
-                                   const float2* feat_grad, float* g_table, uint32_t slab0, int64_t row0,
-                                   int64_t n_rows, uint2* slab_table, uint16_t* rec_key, float2* rec_val,
-                                   int64_t slab_cap,
-                                   hipStream_t s);
+// bin runs once per level over the blocks of every camera of the call (one
+// joint launch), then reduce once per level. Records are filed in slabs: the
+// bin launch runs `wgs` workgroups, each with a fixed share of the blocks,
+// and workgroup w keeps the records of bucket b in its own slab of `slab`
+// records at arena offset (w nb + b) slab; it ends by writing (slab start,
+// records in it) to row w of the bucket's slab-table column
+// (slab_table[b * n_rows + w]). A slab that fills up sends further records
+// straight to the table with atomics (correct, slower). slab_cap > 0 shrinks
+// the slabs and cas_rounds > 0 bounds the reduction's LDS compare-and-swap
+// retries (then a global atomic), to exercise both fallbacks in tests; 0
+// keeps the defaults. The n_cams cameras' n_blocks blocks are numbered camera
+// after camera. One camera: cam0 (host) describes it and travels as the
+// kernel's argument. Several: cams [n_cams] (device, written with
+// launch_write_scatter_cam before the first level's launch) describe them.
+hipError_t launch_write_scatter_cam(const ScatterCam& cam, ScatterCam* dst, hipStream_t s);
+hipError_t launch_hash_scatter_bin(int K, const ScatterCam& cam0, const ScatterCam* cams, int n_cams, int64_t n_blocks,
+                                   const GridDev& grid0, int level, float* g_table, int64_t n_rows, uint2* slab_table,
+                                   uint16_t* rec_key, float2* rec_val, int64_t slab_cap, hipStream_t s);
 hipError_t launch_hash_scatter_reduce(const GridDev& grid, int level, float* g_table, int64_t n_rows,
                                       const uint2* slab_table, const uint16_t* rec_key, const float2* rec_val,
                                       int cas_rounds,
@@ -219,29 +226,46 @@ inline int scatter_bucket_log2(int log2_size) {
   return b < 0 ? 0 : (b > 13 ? 13 : b);
 }
 inline int scatter_buckets(int log2_size) { return 1 << (log2_size - scatter_bucket_log2(log2_size)); }
-// Slabs of one camera's bin launch: workgroups and records per (workgroup,
-// bucket) slab, sized for 5/4 of the worst case (every corner of every
-// sample a record) spread evenly over the buckets.
+// Slabs of a bin launch: workgroups and records per (workgroup, bucket) slab,
+// sized for 5/4 of the worst case (every corner of every sample a record)
+// spread evenly over the buckets.
 constexpr int kScatWorkgroups = 2048;
 constexpr int kBlockRecords = 4096;  // at most 8 corner records per sample
 struct ScatterSlabs {
   int64_t wgs, slab;
 };
-inline ScatterSlabs scatter_slabs(int width, int height, int K, int nb) {
-  ScatterSlabs r{0, 0};
+// Blocks of one camera (0 without texture slots).
+inline int64_t scatter_blocks(int width, int height, int K) {
   const ScatterGeom g = scatter_geom(width, height, K);
-  const int64_t nblk = (int64_t)g.nbx * g.nby;
-  if (K <= 0 || nblk <= 0) return r;
+  return K > 0 ? (int64_t)g.nbx * g.nby : 0;
+}
+// The same for a joint launch over nblk blocks of several cameras.
+inline ScatterSlabs scatter_slabs_blocks(int64_t nblk, int nb) {
+  ScatterSlabs r{0, 0};
+  if (nblk <= 0) return r;
   r.wgs = nblk < kScatWorkgroups ? nblk : kScatWorkgroups;
   const int64_t per_wg = (nblk + r.wgs - 1) / r.wgs;
   r.slab = (per_wg * kBlockRecords * 5 / 4 + nb - 1) / nb;
   return r;
 }
-// Arena records one camera needs under any bucket count up to kScatMaxBuckets.
-inline int64_t scatter_record_capacity(int width, int height, int K) {
-  const ScatterSlabs r = scatter_slabs(width, height, K, 1);
+// Arena records a joint launch over nblk blocks needs under any bucket count
+// up to kScatMaxBuckets.
+inline int64_t scatter_record_capacity_blocks(int64_t nblk) {
+  const ScatterSlabs r = scatter_slabs_blocks(nblk, 1);
   return r.wgs * (r.slab + kScatMaxBuckets);
 }
+
+// One camera's share of a joint binning launch over all cameras of a call
+// (device memory): its grid geometry, its depths [P,K] and per-level feature
+// gradients, its block layout, and the index of its first block among the
+// blocks of all cameras (cameras in call order).
+struct ScatterCam {
+  GridDev gd;
+  const float* depths;
+  const float2* feat_grad;
+  int bw, bh, nbx, nby;
+  int64_t blk0;
+};
 
 // The per-level feature gradients are stored for 4x4 pixel patches (row-major
 // over the image, ragged at the right and bottom edges): element

@@ -28,7 +28,8 @@
 namespace nx {
 namespace {
 
-constexpr int kBatch = 256;
+// Records staged in LDS per batch: B of them, one per thread of the first B
+// (B in {64, 128, 256}; chosen per context, see launch_raster_forward).
 constexpr float kNegHalfLog2e = -0.72134752044448170368f;
 constexpr float kLn2 = 0.69314718055994530942f;
 
@@ -85,7 +86,7 @@ __device__ __forceinline__ TileCoords tile_pixel(int tile, int ntx, int width, i
   return c;
 }
 
-template <int K>
+template <int K, int B>
 __global__ __launch_bounds__(256) void raster_forward_kernel(const float4* __restrict__ records,
                                                              const uint32_t* __restrict__ sorted_ids,
                                                              const uint2* __restrict__ ranges, int ntx, int width,
@@ -94,8 +95,8 @@ __global__ __launch_bounds__(256) void raster_forward_kernel(const float4* __res
                                                              float* __restrict__ out_w, float* __restrict__ out_d,
                                                              float* __restrict__ t_final,
                                                              uint32_t* __restrict__ n_iter) {
-  __shared__ float4 s_rec[kBatch * kRecF4];
-  __shared__ uint32_t s_id[kBatch];
+  __shared__ float4 s_rec[B * kRecF4];
+  __shared__ uint32_t s_id[B];
   const int tile = blockIdx.x;
   const TileCoords pc = tile_pixel(tile, ntx, width, height);
   const uint2 range = ranges[tile];
@@ -115,17 +116,17 @@ __global__ __launch_bounds__(256) void raster_forward_kernel(const float4* __res
   uint32_t last = 0;
   bool done = !pc.inside;
 
-  for (uint32_t start = range.x; start < range.y; start += kBatch) {
+  for (uint32_t start = range.x; start < range.y; start += B) {
     if (__syncthreads_and(done)) break;
     const uint32_t idx = start + threadIdx.x;
-    if (idx < range.y) {
+    if (threadIdx.x < B && idx < range.y) {
       const uint32_t id = sorted_ids[idx];
       s_id[threadIdx.x] = id;
 #pragma unroll
       for (int f = 0; f < kRecF4; ++f) s_rec[threadIdx.x * kRecF4 + f] = records[(int64_t)id * kRecF4 + f];
     }
     __syncthreads();
-    const int cnt = (int)min((uint32_t)kBatch, range.y - start);
+    const int cnt = (int)min((uint32_t)B, range.y - start);
     for (int j = 0; j < cnt; ++j) {
       if (done) continue;
       const float4 r0 = s_rec[j * kRecF4 + 0], r1 = s_rec[j * kRecF4 + 1], r2 = s_rec[j * kRecF4 + 2],
@@ -246,15 +247,15 @@ __device__ __forceinline__ float wave_transpose_sum16(float v[16], int lane, int
   return x;
 }
 
-template <int K>
+template <int K, int B>
 __global__ __launch_bounds__(256) void raster_backward_kernel(
     const float4* __restrict__ records, const uint32_t* __restrict__ sorted_ids, const uint2* __restrict__ ranges,
     int ntx, int width, int height, float near_z, const float* __restrict__ plain, const int32_t* __restrict__ ids,
     const float* __restrict__ weights, const float* __restrict__ tex, const uint32_t* __restrict__ n_iter,
     const float* __restrict__ grad_image, const float* __restrict__ grad_weights,
     const float* __restrict__ grad_depth, const float* __restrict__ pixel_error, float* __restrict__ rec_grad) {
-  __shared__ float4 s_rec[kBatch * kRecF4];
-  __shared__ uint32_t s_id[kBatch];
+  __shared__ float4 s_rec[B * kRecF4];
+  __shared__ uint32_t s_id[B];
   const int tile = blockIdx.x;
   const TileCoords pc = tile_pixel(tile, ntx, width, height);
   const uint2 range = ranges[tile];
@@ -298,17 +299,17 @@ __global__ __launch_bounds__(256) void raster_backward_kernel(
   float T = 1.0f;
   bool done = my_n == 0;
 
-  for (uint32_t start = range.x; start < range.y; start += kBatch) {
+  for (uint32_t start = range.x; start < range.y; start += B) {
     if (__syncthreads_and(done)) break;
     const uint32_t idx = start + threadIdx.x;
-    if (idx < range.y) {
+    if (threadIdx.x < B && idx < range.y) {
       const uint32_t id = sorted_ids[idx];
       s_id[threadIdx.x] = id;
 #pragma unroll
       for (int f = 0; f < kRecF4; ++f) s_rec[threadIdx.x * kRecF4 + f] = records[(int64_t)id * kRecF4 + f];
     }
     __syncthreads();
-    const int cnt = (int)min((uint32_t)kBatch, range.y - start);
+    const int cnt = (int)min((uint32_t)B, range.y - start);
     for (int j = 0; j < cnt; ++j) {
       const uint32_t rel = start - range.x + (uint32_t)j;
       if (rel >= my_n) done = true;
@@ -379,53 +380,88 @@ __global__ __launch_bounds__(256) void raster_backward_kernel(
   }
 }
 
-template <int K>
-hipError_t launch_fwd_k(const float4* records, const uint32_t* sorted_ids, const uint2* ranges, const CamDev& cam,
+template <int K, int B>
+hipError_t launch_fwd_k1(const float4* records, const uint32_t* sorted_ids, const uint2* ranges, const CamDev& cam,
                         float* plain, int32_t* ids, float* weights, float* depths, float* t_final, uint32_t* n_iter,
                         hipStream_t s) {
   const int n_tiles = cam.ntx * cam.nty;
-  hipLaunchKernelGGL(raster_forward_kernel<K>, dim3(n_tiles), dim3(256), 0, s, records, sorted_ids, ranges, cam.ntx,
+  hipLaunchKernelGGL((raster_forward_kernel<K, B>), dim3(n_tiles), dim3(256), 0, s, records, sorted_ids, ranges, cam.ntx,
                      cam.width, cam.height, (float)cam.near_z, plain, ids, weights, depths, t_final, n_iter);
   return hipGetLastError();
+}
+
+template <int K, int B>
+hipError_t launch_bwd_k1(const float4* records, const uint32_t* sorted_ids, const uint2* ranges, const CamDev& cam,
+                        const float* plain, const int32_t* ids, const float* weights, const float* tex,
+                        const uint32_t* n_iter, const float* grad_image, const float* grad_weights,
+                        const float* grad_depth, const float* pixel_error, float* rec_grad, hipStream_t s) {
+  const int n_tiles = cam.ntx * cam.nty;
+  hipLaunchKernelGGL((raster_backward_kernel<K, B>), dim3(n_tiles), dim3(256), 0, s, records, sorted_ids, ranges,
+                     cam.ntx, cam.width, cam.height, (float)cam.near_z, plain, ids, weights, tex, n_iter, grad_image,
+                     grad_weights, grad_depth, pixel_error, rec_grad);
+  return hipGetLastError();
+}
+
+template <int K>
+hipError_t launch_fwd_k(const float4* records, const uint32_t* sorted_ids, const uint2* ranges, const CamDev& cam,
+                        float* plain, int32_t* ids, float* weights, float* depths, float* t_final, uint32_t* n_iter,
+                        int batch, hipStream_t s) {
+#define NX_FWD(BB) \
+  return launch_fwd_k1<K, BB>(records, sorted_ids, ranges, cam, plain, ids, weights, depths, t_final, n_iter, s)
+  switch (batch) {
+    case 64: NX_FWD(64);
+    case 128: NX_FWD(128);
+    case 256: NX_FWD(256);
+    default: return hipErrorInvalidValue;
+  }
+#undef NX_FWD
 }
 
 template <int K>
 hipError_t launch_bwd_k(const float4* records, const uint32_t* sorted_ids, const uint2* ranges, const CamDev& cam,
                         const float* plain, const int32_t* ids, const float* weights, const float* tex,
                         const uint32_t* n_iter, const float* grad_image, const float* grad_weights,
-                        const float* grad_depth, const float* pixel_error, float* rec_grad, hipStream_t s) {
-  const int n_tiles = cam.ntx * cam.nty;
-  hipLaunchKernelGGL(raster_backward_kernel<K>, dim3(n_tiles), dim3(256), 0, s, records, sorted_ids, ranges,
-                     cam.ntx, cam.width, cam.height, (float)cam.near_z, plain, ids, weights, tex, n_iter, grad_image,
-                     grad_weights, grad_depth, pixel_error, rec_grad);
-  return hipGetLastError();
+                        const float* grad_depth, const float* pixel_error, float* rec_grad, int batch,
+                        hipStream_t s) {
+#define NX_BWD1(BB)                                                                                             \
+  return launch_bwd_k1<K, BB>(records, sorted_ids, ranges, cam, plain, ids, weights, tex, n_iter, grad_image, \
+                              grad_weights, grad_depth, pixel_error, rec_grad, s)
+  switch (batch) {
+    case 64: NX_BWD1(64);
+    case 128: NX_BWD1(128);
+    case 256: NX_BWD1(256);
+    default: return hipErrorInvalidValue;
+  }
+#undef NX_BWD1
 }
 
 }  // namespace
 
 hipError_t launch_raster_forward(int K, const float4* records, const uint32_t* sorted_ids, const uint2* ranges,
                                  const CamDev& cam, float* plain, int32_t* ids, float* weights, float* depths,
-                                 float* t_final, uint32_t* n_iter, hipStream_t s) {
+                                 float* t_final, uint32_t* n_iter, int batch, hipStream_t s) {
+#define NX_FWD(KK) \
+  return launch_fwd_k<KK>(records, sorted_ids, ranges, cam, plain, ids, weights, depths, t_final, n_iter, batch, s)
   switch (K) {
-    case 0: return launch_fwd_k<0>(records, sorted_ids, ranges, cam, plain, ids, weights, depths, t_final, n_iter, s);
-    case 1: return launch_fwd_k<1>(records, sorted_ids, ranges, cam, plain, ids, weights, depths, t_final, n_iter, s);
-    case 2: return launch_fwd_k<2>(records, sorted_ids, ranges, cam, plain, ids, weights, depths, t_final, n_iter, s);
-    case 4: return launch_fwd_k<4>(records, sorted_ids, ranges, cam, plain, ids, weights, depths, t_final, n_iter, s);
-    case 8: return launch_fwd_k<8>(records, sorted_ids, ranges, cam, plain, ids, weights, depths, t_final, n_iter, s);
-    case 16:
-      return launch_fwd_k<16>(records, sorted_ids, ranges, cam, plain, ids, weights, depths, t_final, n_iter, s);
+    case 0: NX_FWD(0);
+    case 1: NX_FWD(1);
+    case 2: NX_FWD(2);
+    case 4: NX_FWD(4);
+    case 8: NX_FWD(8);
+    case 16: NX_FWD(16);
     default: return hipErrorInvalidValue;
   }
+#undef NX_FWD
 }
 
 hipError_t launch_raster_backward(int K, const float4* records, const uint32_t* sorted_ids, const uint2* ranges,
                                   const CamDev& cam, const float* plain, const int32_t* ids, const float* weights,
                                   const float* tex, const uint32_t* n_iter, const float* grad_image,
                                   const float* grad_weights, const float* grad_depth, const float* pixel_error,
-                                  float* rec_grad, hipStream_t s) {
+                                  float* rec_grad, int batch, hipStream_t s) {
 #define NX_BWD(KK)                                                                                             \
   return launch_bwd_k<KK>(records, sorted_ids, ranges, cam, plain, ids, weights, tex, n_iter, grad_image, \
-                          grad_weights, grad_depth, pixel_error, rec_grad, s)
+                          grad_weights, grad_depth, pixel_error, rec_grad, batch, s)
   switch (K) {
     case 0: NX_BWD(0);
     case 1: NX_BWD(1);

@@ -1264,11 +1264,23 @@ __device__ __forceinline__ void segmented_scan(float (&v)[N], bool head) {
 #undef NX_SEG_STEP
 }
 
+// The camera of a block: with JOINT the cameras' descriptors are read from
+// device memory, otherwise the single camera's descriptor is the kernel
+// argument itself (no loads beyond the argument segment).
+template <bool JOINT>
+__device__ __forceinline__ const ScatterCam& scatter_cam(const ScatterCam& cam0, const ScatterCam* cams, int i) {
+  if constexpr (JOINT) {
+    return cams[i];
+  } else {
+    return cam0;
+  }
+}
+
+template <bool JOINT>
 __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
-    GridDev gd, GridLevel L, int K, int log2K, int level, const float* __restrict__ depths,
-    const float2* __restrict__ feat_grad, float* __restrict__ g_table, int bw, int bh, int nbx, int nby,
-    int bucket_log2, uint32_t slab0, uint32_t slab, int64_t row0, int64_t n_rows, uint2* __restrict__ slab_table,
-    uint16_t* __restrict__ rec_key, float2* __restrict__ rec_val) {
+    ScatterCam cam0, const ScatterCam* __restrict__ cams, int n_cams, int64_t n_blocks, int K, int log2K, int level,
+    float* __restrict__ g_table, int log2_size, int bucket_log2, uint32_t slab, int64_t n_rows,
+    uint2* __restrict__ slab_table, uint16_t* __restrict__ rec_key, float2* __restrict__ rec_val) {
   // LDS: the per-sample stage (corner values, cells, sort keys) and, once
   // those are in registers, the block's records grouped by bucket share one
   // region; per-bucket counters follow it (dynamic size: 3 nb words).
@@ -1279,31 +1291,40 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
   uint32_t* skey = reinterpret_cast<uint32_t*>(scat_lds + sizeof(float) * 8 * kBlockSamples);
   uint32_t* st_h = reinterpret_cast<uint32_t*>(scat_lds);                          // record: entry index
   float2* st_v = reinterpret_cast<float2*>(scat_lds + sizeof(uint32_t) * kBlockRecords);  // record: 2 values
-  const int nb = 1 << (gd.log2_size - bucket_log2);
+  const int nb = 1 << (log2_size - bucket_log2);
   uint32_t* hist = reinterpret_cast<uint32_t*>(scat_lds + kScatStageBytes);  // count, then local offset
   uint32_t* gdelta = hist + nb;  // slab slot minus local position
   uint32_t* wcur = gdelta + nb;  // records this workgroup has filed per bucket
   __shared__ uint32_t wsum[kScatThreads / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, c = lane & 15;
   const int row = threadIdx.x >> 4;
-  const uint32_t mask = (1u << gd.log2_size) - 1u;
+  const uint32_t mask = (1u << log2_size) - 1u;
   const uint32_t emask = (1u << bucket_log2) - 1u;
-  const int npx = (gd.width + 3) >> 2, npy = (gd.height + 3) >> 2;
-  const int64_t n_q = (int64_t)npx * npy;
-  const int64_t nqK = n_q * K;
-  const int n_blocks = nbx * nby;
-  float* g_level = g_table + 2 * ((size_t)level << gd.log2_size);
+  float* g_level = g_table + 2 * ((size_t)level << log2_size);
   const int p0 = 128 * wave + 2 * lane;  // sorted positions p0, p0 + 1 belong to this lane
-  const int log2bw = __builtin_ctz((unsigned)bw);  // bw is a power of two
   // Consecutive workgroup ids go to different XCDs; renumber so that each XCD
   // walks neighbouring blocks.
   const int G = gridDim.x;
   const int wg = (G % 8 == 0) ? (int)(blockIdx.x % 8) * (G / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
-  const size_t slab_base = slab0 + (size_t)wg * nb * slab;  // this workgroup's slab of bucket 0
+  const size_t slab_base = (size_t)wg * nb * slab;  // this workgroup's slab of bucket 0
   for (int i = threadIdx.x; i < nb; i += kScatThreads) wcur[i] = 0u;
-  for (int blk = wg; blk < n_blocks; blk += G) {
+  int cam = 0;  // blocks ascend, so the camera only moves forward
+  for (int64_t blk = wg; blk < n_blocks; blk += G) {
+    if constexpr (JOINT) {
+      while (cam + 1 < n_cams && cams[cam + 1].blk0 <= blk) ++cam;
+    }
+    const ScatterCam& sc = scatter_cam<JOINT>(cam0, cams, cam);
+    const GridDev& gd = sc.gd;
+    const GridLevel L = gd.lv[level];
+    const float* __restrict__ depths = sc.depths;
+    const float2* __restrict__ feat_grad = sc.feat_grad;
+    const int bw = sc.bw, bh = sc.bh, nbx = sc.nbx;
+    const int log2bw = __builtin_ctz((unsigned)bw);  // bw is a power of two
+    const int npx = (gd.width + 3) >> 2, npy = (gd.height + 3) >> 2;
+    const int64_t nqK = (int64_t)npx * npy * K;
+    const int64_t lb = blk - sc.blk0;
     for (int i = threadIdx.x; i < nb; i += kScatThreads) hist[i] = 0u;
-    const int bx = blk % nbx, by = blk / nbx;
+    const int bx = (int)(lb % nbx), by = (int)(lb / nbx);
     // 1. per sample: cell, position in it, feature gradient and sort key
 #pragma unroll
     for (int it = 0; it < kUnitsPerRow; ++it) {
@@ -1492,7 +1513,7 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
   __syncthreads();
   for (int i = threadIdx.x; i < nb; i += kScatThreads) {
     const uint32_t n = wcur[i];
-    slab_table[(size_t)i * n_rows + row0 + wg] = make_uint2((uint32_t)(slab_base + (size_t)i * slab), n < slab ? n : slab);
+    slab_table[(size_t)i * n_rows + wg] = make_uint2((uint32_t)(slab_base + (size_t)i * slab), n < slab ? n : slab);
   }
 }
 
@@ -1770,26 +1791,42 @@ bool scatter_launch(const GridDev& grid, ScatterLaunch* o) {
   o->nb = scatter_buckets(grid.log2_size);
   return o->bl <= kReduceMaxLog2 && o->nb <= kScatMaxBuckets;
 }
+
+__global__ void write_scatter_cam_kernel(ScatterCam cam, ScatterCam* dst) {
+  // a plain copy of the argument, one dword per lane
+  static_assert(sizeof(ScatterCam) % 4 == 0, "copied in dwords");
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(&cam);
+  uint32_t* out = reinterpret_cast<uint32_t*>(dst);
+  for (int i = threadIdx.x; i < (int)(sizeof(ScatterCam) / 4); i += blockDim.x) out[i] = src[i];
+}
 }  // namespace
 
-hipError_t launch_hash_scatter_bin(int K, const GridDev& grid, int level, const float* depths,
-                                   const float2* feat_grad, float* g_table, uint32_t slab0, int64_t row0,
-                                   int64_t n_rows, uint2* slab_table, uint16_t* rec_key, float2* rec_val,
-                                   int64_t slab_cap, hipStream_t s) {
-  if (K == 0 || grid.width == 0 || grid.height == 0 || level < 0 || level >= grid.levels) return hipSuccess;
+hipError_t launch_write_scatter_cam(const ScatterCam& cam, ScatterCam* dst, hipStream_t s) {
+  hipLaunchKernelGGL(write_scatter_cam_kernel, dim3(1), dim3(256), 0, s, cam, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_hash_scatter_bin(int K, const ScatterCam& cam0, const ScatterCam* cams, int n_cams, int64_t n_blocks,
+                                   const GridDev& grid0, int level, float* g_table, int64_t n_rows, uint2* slab_table,
+                                   uint16_t* rec_key, float2* rec_val, int64_t slab_cap, hipStream_t s) {
+  if (K == 0 || n_blocks <= 0 || n_cams <= 0 || level < 0 || level >= grid0.levels) return hipSuccess;
   ScatterLaunch sl;
-  if (!scatter_launch(grid, &sl)) return hipErrorInvalidValue;
-  const ScatterGeom sg = scatter_geom(grid.width, grid.height, K);
-  const ScatterSlabs sb = scatter_slabs(grid.width, grid.height, K, sl.nb);
-  if (sb.wgs <= 0) return hipSuccess;
-  if (row0 < 0 || row0 + sb.wgs > n_rows || (int64_t)slab0 + sb.wgs * sl.nb * sb.slab > 0xFFFFFFFFll)
-    return hipErrorInvalidValue;
+  if (!scatter_launch(grid0, &sl)) return hipErrorInvalidValue;
+  const ScatterSlabs sb = scatter_slabs_blocks(n_blocks, sl.nb);
+  if (sb.wgs > n_rows || sb.wgs * sl.nb * sb.slab > 0xFFFFFFFFll) return hipErrorInvalidValue;
   const size_t lds = kScatStageBytes + 3 * sizeof(uint32_t) * sl.nb;
   // a smaller slab (diagnostics) stays inside the records laid out for the full one
   const int64_t slab = slab_cap > 0 && slab_cap < sb.slab ? slab_cap : sb.slab;
-  hipLaunchKernelGGL(scatter_bin_kernel, dim3((unsigned)sb.wgs), dim3(kScatThreads), lds, s, grid, grid.lv[level], K,
-                     ilog2(K), level, depths, feat_grad, g_table, sg.bw, sg.bh, sg.nbx, sg.nby, sl.bl, slab0,
-                     (uint32_t)slab, row0, n_rows, slab_table, rec_key, rec_val);
+  if (n_cams == 1) {
+    hipLaunchKernelGGL(scatter_bin_kernel<false>, dim3((unsigned)sb.wgs), dim3(kScatThreads), lds, s, cam0, cams,
+                       n_cams, n_blocks, K, ilog2(K), level, g_table, grid0.log2_size, sl.bl, (uint32_t)slab, n_rows,
+                       slab_table, rec_key, rec_val);
+  } else {
+    if (!cams) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(scatter_bin_kernel<true>, dim3((unsigned)sb.wgs), dim3(kScatThreads), lds, s, cam0, cams, n_cams,
+                       n_blocks, K, ilog2(K), level, g_table, grid0.log2_size, sl.bl, (uint32_t)slab, n_rows,
+                       slab_table, rec_key, rec_val);
+  }
   return hipGetLastError();
 }
 

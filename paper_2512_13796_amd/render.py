@@ -214,6 +214,25 @@ def instance_counts(ctx: Context, n_surfels, res: ForwardResult):
     return [int(v) for v in out]
 
 
+def autotune_raster(ctx: Context, surfels, res: ForwardResult, reps=5):
+    """nx_autotune_raster: choose the collection pass's LDS batch for the cameras of res (the result of a
+    finished forward with these surfels), keep it in ctx for later calls over cameras of the same sizes, and
+    return it. Synchronises the current stream."""
+    device = surfels[0].device
+    s = _surfel_struct(ctx, surfels, device)
+    cams = _cameras(res.camera)
+    cs = (L.NxCamera * len(cams))(*[camera_struct(c, res.near) for c in cams])
+    n_inst = (ctypes.c_int64 * len(cams))(*res.n_instances_cam)
+    out = L.NxFwdOut(_ptr(res.image), _ptr(res.plain), _ptr(res.ids), _ptr(res.weights), _ptr(res.depths),
+                     _ptr(res.t_final), _ptr(res.tex), _ptr(res.n_iter), None, None, None, n_inst)
+    batch = ctypes.c_int32()
+    stream = ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+    L.check(ctx.lib.nx_autotune_raster(ctx.handle, ctypes.byref(s), cs, len(cams), ctypes.byref(out),
+                                       _ptr(res.workspace), res.workspace.numel(), int(reps), ctypes.byref(batch),
+                                       stream))
+    return int(batch.value)
+
+
 def render_forward(ctx: Context, surfels, cam, table=None, level_scales=None, weights=None, near=0.2,
                    workspace=None, want_cells=False, max_instances=None) -> ForwardResult:
     """Collection and texturing passes (nx_render_forward) for one camera or a

@@ -9,7 +9,9 @@ HIP graph of a whole multi-camera training step (needs an MI355X).
     several cameras of mixed resolution, captured once in a HIP graph and
     replayed several times with eager work in between: every replay's
     outputs equal the eager call's bit for bit, and its gradients equal the
-    eager gradients up to float32 atomic summation order.
+    eager gradients up to float32 atomic summation order;
+  * the collection pass's LDS batch autotuned per camera configuration
+    (nx_autotune_raster) changes no result.
 """
 from __future__ import annotations
 
@@ -160,3 +162,35 @@ def test_exact_workspace_size(nx, views):
     assert res.workspace.data_ptr() == ws.data_ptr(), "the exact size was not enough for one call"
     for nm in FWD_FIELDS:
         assert torch.equal(getattr(res, nm), getattr(ref, nm)), nm
+
+
+def test_raster_batch_autotune(nx, views):
+    """nx_autotune_raster picks one of the LDS batch sizes for this camera configuration; rerunning the
+    collection pass with every candidate leaves the forward outputs bit-identical, a later forward with the
+    tuned batch equals the default one bit for bit, and its backward matches the default one up to float32
+    atomic order."""
+    wl, cams = views
+    surf, table, weights = device_inputs(wl)
+    ctx = nx.Context(wl.K, table.dtype, weights[0].dtype)
+    ref = nx.render_forward(ctx, surf, cams, table, wl.grid.level_scales, weights)
+    torch.cuda.synchronize()
+    before = {nm: getattr(ref, nm).clone() for nm in FWD_FIELDS}
+    P = sum(c.width * c.height for c in cams)
+    gi = torch.randn(P, 3, device="cuda", generator=torch.Generator(device="cuda").manual_seed(5))
+    g_ref = _zero_grads(surf, table, weights)
+    nx.render_backward(ctx, surf, ref, table, wl.grid.level_scales, weights, gi, None, None, g_ref)
+    batch = nx.autotune_raster(ctx, surf, ref, reps=3)
+    log("raster LDS batch chosen:", batch)
+    assert batch in (64, 128, 256)
+    for nm in FWD_FIELDS:
+        assert torch.equal(getattr(ref, nm), before[nm]), f"autotuning changed {nm}"
+    tuned = nx.render_forward(ctx, surf, cams, table, wl.grid.level_scales, weights)
+    g_tuned = _zero_grads(surf, table, weights)
+    nx.render_backward(ctx, surf, tuned, table, wl.grid.level_scales, weights, gi, None, None, g_tuned)
+    torch.cuda.synchronize()
+    for nm in FWD_FIELDS:
+        assert torch.equal(getattr(tuned, nm), before[nm]), nm
+    for k, v in g_ref.items():
+        for a, b in zip(v if k == "mlp" else [v], g_tuned[k] if k == "mlp" else [g_tuned[k]]):
+            d = float((a.double() - b.double()).norm()) / max(float(a.double().norm()), 1e-30)
+            assert d <= ATOMIC_ORDER_TOL, f"{k} differs by {d:.3e} (relative)"
