@@ -192,7 +192,7 @@ int nx_set_sh_degree(nx_ctx *ctx, int32_t degree);
  * nx_render_forward to count the pairs (it then
  * returns NX_ERR_WORKSPACE with the exact size in *workspace_required, after
  * one synchronisation per camera). The workspace starts with
- * the backward's hash-scatter scratch shared by the cameras (two record
+ * the backward's hash-scatter scratch shared by the cameras (three record
  * arenas of about 10 records per sample, and their slab tables), then holds
  * one section per camera, one after another; the sections carry the
  * forward's sorted tile lists and per-surfel records to the backward. */

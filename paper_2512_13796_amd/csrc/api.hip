@@ -22,6 +22,11 @@ struct nx_pending {
   hipEvent_t a, b;
 };
 
+// Record arenas of the hash-grid gradient: level l is binned into arena
+// l % kScatArenas while earlier levels are reduced on the side stream, so a
+// bin waits only for the reduction of the level kScatArenas before it.
+constexpr int kScatArenas = 3;
+
 struct nx_ctx {
   int32_t K;
   int32_t tile;
@@ -44,7 +49,7 @@ struct nx_ctx {
   // at the first backward, on the device current then (a context serves one
   // device).
   hipStream_t side = nullptr, side2 = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_bin[2] = {}, ev_red[2] = {}, ev_tex = nullptr,
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_bin[kScatArenas] = {}, ev_red[kScatArenas] = {}, ev_tex = nullptr,
              ev_join2 = nullptr;
   std::vector<nx_phase> phases;
   std::vector<nx_pending> pending;
@@ -134,8 +139,8 @@ Layout make_layout(int64_t n, const nx::CamDev& cd, int K, int64_t n_inst, bool 
 // cameras of a call (every level is reduced once for all of them); they sit
 // at the start of the workspace, before the per-camera sections.
 struct SharedLayout {
-  // two arenas: level l files into arena l % 2 while level l - 1 is reduced
-  size_t rec_key[2], rec_val[2], slab_table[2], cams, total;
+  // kScatArenas arenas: level l files into arena l % kScatArenas while earlier levels are reduced
+  size_t rec_key[kScatArenas], rec_val[kScatArenas], slab_table[kScatArenas], cams, total;
   int64_t capacity;  // records per arena
   int64_t rows;      // slab-table rows (workgroups of the joint bin launch)
   int64_t blocks;    // bin blocks over all cameras
@@ -154,7 +159,7 @@ SharedLayout make_shared_layout(const nx_camera* cams, int32_t n_cams, int K) {
     o = align_up(o + bytes);
     return at;
   };
-  for (int a = 0; a < 2; ++a) {
+  for (int a = 0; a < kScatArenas; ++a) {
     S.rec_key[a] = take(sizeof(uint16_t) * (size_t)S.capacity);
     S.rec_val[a] = take(sizeof(float2) * (size_t)S.capacity);
     S.slab_table[a] = take(sizeof(uint2) * (size_t)S.rows * nx::kScatMaxBuckets);
@@ -323,8 +328,11 @@ int side_streams(nx_ctx* c) {
       return fail(NX_ERR_HIP, std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(err));
     }
   }
-  hipEvent_t* evs[8] = {&c->ev_fork, &c->ev_join, &c->ev_bin[0], &c->ev_bin[1],
-                        &c->ev_red[0], &c->ev_red[1], &c->ev_tex, &c->ev_join2};
+  std::vector<hipEvent_t*> evs = {&c->ev_fork, &c->ev_join, &c->ev_tex, &c->ev_join2};
+  for (int a = 0; a < kScatArenas; ++a) {
+    evs.push_back(&c->ev_bin[a]);
+    evs.push_back(&c->ev_red[a]);
+  }
   for (hipEvent_t* e : evs) {
     // ordering between streams of one device: a device-scope release is enough
     const hipError_t err = hipEventCreateWithFlags(e, hipEventDisableTiming | hipEventReleaseToDevice);
@@ -640,9 +648,12 @@ int nx_destroy(nx_ctx* ctx) {
     (void)hipEventDestroy(p.b);
   }
   for (auto e : ctx->pool) (void)hipEventDestroy(e);
-  for (hipEvent_t e : {ctx->ev_fork, ctx->ev_join, ctx->ev_bin[0], ctx->ev_bin[1], ctx->ev_red[0], ctx->ev_red[1],
-                       ctx->ev_tex, ctx->ev_join2})
+  for (hipEvent_t e : {ctx->ev_fork, ctx->ev_join, ctx->ev_tex, ctx->ev_join2})
     if (e) (void)hipEventDestroy(e);
+  for (int a = 0; a < kScatArenas; ++a) {
+    if (ctx->ev_bin[a]) (void)hipEventDestroy(ctx->ev_bin[a]);
+    if (ctx->ev_red[a]) (void)hipEventDestroy(ctx->ev_red[a]);
+  }
   if (ctx->side) (void)hipStreamDestroy(ctx->side);
   if (ctx->side2) (void)hipStreamDestroy(ctx->side2);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -979,7 +990,7 @@ int nx_fps(nx_ctx* ctx, const float* points, int64_t n, int64_t m, int32_t* orde
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   NX_CHECK_HIP(hipGetLastError());
   float* best = static_cast<float*>(workspace);
-  auto* slots = at<unsigned long long>(workspace, align_up(sizeof(float) * (size_t)n));
+  void* slots = at<char>(workspace, align_up(sizeof(float) * (size_t)n));
   NX_CHECK_HIP(nx::launch_fps(points, n, m, best, slots, grid, order, dist2, s));
   g_last_error.clear();
   return NX_OK;
@@ -1214,18 +1225,18 @@ int nx_render_backward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* 
         cpix += (int64_t)cams[c].width * cams[c].height;
       }
     }
-    // Level l: bin on the call's stream into arena l % 2, reduce on the side
-    // stream; the bin of level l + 2 waits for the reduce of level l (same
-    // arena), the reduce of level l for its own bin; the call's stream waits
-    // for the last reduce at the end.
+    // Level l: bin on the call's stream into arena l % kScatArenas, reduce on
+    // the side stream; the bin of level l + kScatArenas waits for the reduce
+    // of level l (same arena), the reduce of level l for its own bin; the
+    // call's stream waits for the last reduce at the end.
     NX_CHECK_HIP(hipEventRecord(ctx->ev_fork, s));
     NX_CHECK_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
     for (int l = 0; l < gd0.levels; ++l) {
-      const int a = l & 1;
+      const int a = l % kScatArenas;
       uint16_t* rk = at<uint16_t>(ws, SH.rec_key[a]);
       float2* rv = at<float2>(ws, SH.rec_val[a]);
       uint2* tab = at<uint2>(ws, SH.slab_table[a]);
-      if (l >= 2) NX_CHECK_HIP(hipStreamWaitEvent(s, ctx->ev_red[a], 0));
+      if (l >= kScatArenas) NX_CHECK_HIP(hipStreamWaitEvent(s, ctx->ev_red[a], 0));
       {
         PhaseTimer pt(ctx, "scatter_bin", s);
         NX_CHECK_HIP(nx::launch_hash_scatter_bin(ctx->K, cam0, dcams, n_cams, SH.blocks, gd0, l, grads->table,
