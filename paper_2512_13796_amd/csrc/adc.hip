@@ -43,63 +43,127 @@ __device__ __forceinline__ unsigned long long fps_key(float d2, uint32_t i) {
   return ((unsigned long long)bits << 32) | (unsigned long long)(0xFFFFFFFFu - i);
 }
 
-__device__ __forceinline__ unsigned long long max_u64(unsigned long long a, unsigned long long b) {
-  return a > b ? a : b;
+// A workgroup's candidate: its key and the point's coordinates, so that the
+// winner's position needs no further load after the barrier.
+struct alignas(16) FpsSlot {
+  unsigned long long key;
+  float x, y, z, pad;
+};
+
+struct FpsCand {
+  unsigned long long key;
+  float x, y, z;
+};
+
+__device__ __forceinline__ void take_max(FpsCand& a, unsigned long long k, float x, float y, float z) {
+  if (k > a.key) {
+    a.key = k;
+    a.x = x;
+    a.y = y;
+    a.z = z;
+  }
 }
 
-__device__ unsigned long long block_max(unsigned long long v) {
-  __shared__ unsigned long long part[kFpsThreads / 64];
-  for (int o = 32; o > 0; o >>= 1) v = max_u64(v, __shfl_xor(v, o, 64));
+// The candidate with the largest key over the workgroup (every thread
+// receives it).
+__device__ FpsCand block_max(FpsCand v) {
+  __shared__ FpsCand part[kFpsThreads / 64];
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long k = __shfl_xor(v.key, o, 64);
+    const float x = __shfl_xor(v.x, o, 64), y = __shfl_xor(v.y, o, 64), z = __shfl_xor(v.z, o, 64);
+    take_max(v, k, x, y, z);
+  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) part[wave] = v;
   __syncthreads();
-  unsigned long long r = part[0];
-  for (int w = 1; w < kFpsThreads / 64; ++w) r = max_u64(r, part[w]);
+  FpsCand r = part[0];
+  for (int w = 1; w < kFpsThreads / 64; ++w) take_max(r, part[w].key, part[w].x, part[w].y, part[w].z);
   __syncthreads();
   return r;
 }
 
+// Points held in registers per thread when n <= grid * kFpsThreads * this;
+// larger inputs keep their distances in `best` (global memory) instead.
+constexpr int kFpsRegPoints = 4;
+
 // One cooperative launch runs all m iterations: every workgroup updates the
 // nearest-taken distances of its points against the point taken last, finds
-// its best candidate, and posts it to a slot; after a grid barrier every
-// workgroup reads all slots and takes the same winner. Slots alternate
-// between two banks, so a bank is rewritten only after the barrier that
-// follows its last read.
+// its best candidate, and posts it with its coordinates to a slot; after a
+// grid barrier every workgroup reads all slots and takes the same winner.
+// Slots alternate between two banks, so a bank is rewritten only after the
+// barrier that follows its last read.
 __global__ __launch_bounds__(kFpsThreads) void fps_kernel(const float* __restrict__ pts, int64_t n, int64_t m,
-                                                          float* __restrict__ best, unsigned long long* slots,
+                                                          float* __restrict__ best, FpsSlot* slots,
                                                           int32_t* __restrict__ order, float* __restrict__ d2out) {
   namespace cg = cooperative_groups;
   cg::grid_group grid = cg::this_grid();
   const int G = gridDim.x;
   const int64_t stride = (int64_t)G * kFpsThreads;
-  for (int64_t k = (int64_t)blockIdx.x * kFpsThreads + threadIdx.x; k < n; k += stride) best[k] = __int_as_float(0x7F800000);
+  const int64_t first = (int64_t)blockIdx.x * kFpsThreads + threadIdx.x;
+  const bool in_regs = n <= stride * kFpsRegPoints;
+  float px[kFpsRegPoints], py[kFpsRegPoints], pz[kFpsRegPoints], pb[kFpsRegPoints];
+  if (in_regs) {
+#pragma unroll
+    for (int r = 0; r < kFpsRegPoints; ++r) {
+      const int64_t k = first + r * stride;
+      const bool ok = k < n;
+      px[r] = ok ? pts[3 * k] : 0.0f;
+      py[r] = ok ? pts[3 * k + 1] : 0.0f;
+      pz[r] = ok ? pts[3 * k + 2] : 0.0f;
+      pb[r] = ok ? __int_as_float(0x7F800000) : kTaken;
+    }
+  } else {
+    for (int64_t k = first; k < n; k += stride) best[k] = __int_as_float(0x7F800000);
+  }
   uint32_t cur = 0;
+  float cx = pts[0], cy = pts[1], cz = pts[2];
   if (blockIdx.x == 0 && threadIdx.x == 0) order[0] = 0;
   for (int64_t it = 0; it + 1 < m; ++it) {
-    const float cx = pts[3 * (int64_t)cur], cy = pts[3 * (int64_t)cur + 1], cz = pts[3 * (int64_t)cur + 2];
-    unsigned long long mine = 0ull;
-    for (int64_t k = (int64_t)blockIdx.x * kFpsThreads + threadIdx.x; k < n; k += stride) {
-      float b = best[k];
-      if (k == (int64_t)cur) {
-        b = kTaken;
-      } else if (b != kTaken) {
-        b = fminf(b, dist2_rn(pts[3 * k], pts[3 * k + 1], pts[3 * k + 2], cx, cy, cz));
+    FpsCand mine{0ull, 0.0f, 0.0f, 0.0f};
+    if (in_regs) {
+#pragma unroll
+      for (int r = 0; r < kFpsRegPoints; ++r) {
+        const int64_t k = first + r * stride;
+        float b = pb[r];
+        if (k == (int64_t)cur) {
+          b = kTaken;
+        } else if (b != kTaken) {
+          b = fminf(b, dist2_rn(px[r], py[r], pz[r], cx, cy, cz));
+        }
+        pb[r] = b;
+        if (b != kTaken) take_max(mine, fps_key(b, (uint32_t)k), px[r], py[r], pz[r]);
       }
-      best[k] = b;
-      if (b != kTaken) mine = max_u64(mine, fps_key(b, (uint32_t)k));
+    } else {
+      for (int64_t k = first; k < n; k += stride) {
+        float b = best[k];
+        const float x = pts[3 * k], y = pts[3 * k + 1], z = pts[3 * k + 2];
+        if (k == (int64_t)cur) {
+          b = kTaken;
+        } else if (b != kTaken) {
+          b = fminf(b, dist2_rn(x, y, z, cx, cy, cz));
+        }
+        best[k] = b;
+        if (b != kTaken) take_max(mine, fps_key(b, (uint32_t)k), x, y, z);
+      }
     }
-    const unsigned long long bk = block_max(mine);
-    unsigned long long* bank = slots + (it & 1) * G;
-    if (threadIdx.x == 0) bank[blockIdx.x] = bk;
+    const FpsCand bk = block_max(mine);
+    FpsSlot* bank = slots + (it & 1) * G;
+    if (threadIdx.x == 0) bank[blockIdx.x] = FpsSlot{bk.key, bk.x, bk.y, bk.z, 0.0f};
     grid.sync();
-    unsigned long long w = 0ull;
-    for (int i = threadIdx.x; i < G; i += kFpsThreads) w = max_u64(w, bank[i]);
+    FpsCand w{0ull, 0.0f, 0.0f, 0.0f};
+    for (int i = threadIdx.x; i < G; i += kFpsThreads) {
+      const FpsSlot sl = bank[i];
+      take_max(w, sl.key, sl.x, sl.y, sl.z);
+    }
     w = block_max(w);
     // (a zero key cannot win while an untaken point remains, as m <= n)
-    cur = w == 0ull ? 0u : 0xFFFFFFFFu - (uint32_t)(w & 0xFFFFFFFFull);
+    cur = w.key == 0ull ? 0u : 0xFFFFFFFFu - (uint32_t)(w.key & 0xFFFFFFFFull);
+    cx = w.x;
+    cy = w.y;
+    cz = w.z;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       order[it + 1] = (int32_t)cur;
-      d2out[it + 1] = __uint_as_float((uint32_t)(w >> 32));
+      d2out[it + 1] = __uint_as_float((uint32_t)(w.key >> 32));
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) d2out[0] = m > 1 ? d2out[1] : 0.0f;
@@ -196,7 +260,7 @@ unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
 
-size_t fps_slot_bytes(int grid) { return sizeof(unsigned long long) * 2 * (size_t)grid; }
+size_t fps_slot_bytes(int grid) { return sizeof(FpsSlot) * 2 * (size_t)grid; }
 
 hipError_t fps_grid(int64_t n, int* grid) {
   int dev = 0, cus = 0, per_cu = 0;
@@ -212,9 +276,10 @@ hipError_t fps_grid(int64_t n, int* grid) {
   return hipSuccess;
 }
 
-hipError_t launch_fps(const float* pts, int64_t n, int64_t m, float* best, unsigned long long* slots, int grid,
-                      int32_t* order, float* d2, hipStream_t s) {
+hipError_t launch_fps(const float* pts, int64_t n, int64_t m, float* best, void* slots_bytes, int grid, int32_t* order,
+                      float* d2, hipStream_t s) {
   if (n <= 0 || m <= 0) return hipSuccess;
+  FpsSlot* slots = static_cast<FpsSlot*>(slots_bytes);
   void* args[] = {(void*)&pts, (void*)&n, (void*)&m, (void*)&best, (void*)&slots, (void*)&order, (void*)&d2};
   return hipLaunchCooperativeKernel((const void*)fps_kernel, dim3(grid), dim3(kFpsThreads), args, 0, s);
 }

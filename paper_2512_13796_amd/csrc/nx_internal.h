@@ -182,11 +182,12 @@ hipError_t launch_aux_losses(int64_t P, int K, const float* W, const float* tex,
 
 // Adaptive density control. FPS: one cooperative launch of `grid`
 // workgroups (fps_grid: the co-resident maximum, at most what n needs);
-// best: n floats of scratch, slots: fps_slot_bytes(grid) bytes.
+// best: n floats of scratch, slots: fps_slot_bytes(grid) bytes (16-byte
+// aligned).
 size_t fps_slot_bytes(int grid);
 hipError_t fps_grid(int64_t n, int* grid);
-hipError_t launch_fps(const float* pts, int64_t n, int64_t m, float* best, unsigned long long* slots, int grid,
-                      int32_t* order, float* d2, hipStream_t s);
+hipError_t launch_fps(const float* pts, int64_t n, int64_t m, float* best, void* slots, int grid, int32_t* order,
+                      float* d2, hipStream_t s);
 // Split selection: chosen[i] = 1 for the k smallest keys err/draw (finite
 // keys only); keys, ids, tmp_* are n words, hist radix_hist_words(n).
 hipError_t launch_split_select(int64_t n, int64_t k, const float* err, const float* draws, uint32_t* keys,
