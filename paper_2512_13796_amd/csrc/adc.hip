@@ -83,8 +83,11 @@ __device__ FpsCand block_max(FpsCand v) {
 }
 
 // Points held in registers per thread when n <= grid * kFpsThreads * this;
-// larger inputs keep their distances in `best` (global memory) instead.
-constexpr int kFpsRegPoints = 4;
+// larger inputs keep their distances in `best` (global memory) instead. The
+// grid is sized so that n fits (fps_grid): each point taken costs one grid
+// barrier, whose price grows with the number of workgroups, while the
+// distance updates cost little.
+constexpr int kFpsRegPoints = 8;
 
 // One cooperative launch runs all m iterations: every workgroup updates the
 // nearest-taken distances of its points against the point taken last, finds
@@ -269,8 +272,9 @@ hipError_t fps_grid(int64_t n, int* grid) {
   if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
   if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fps_kernel, kFpsThreads, 0)) != hipSuccess) return e;
   if (per_cu < 1) return hipErrorCooperativeLaunchTooLarge;
-  int64_t g = cus;  // one workgroup per CU (co-resident, as the grid barrier needs)
-  const int64_t need = (n + kFpsThreads - 1) / kFpsThreads;
+  int64_t g = cus;  // at most one workgroup per CU (co-resident, as the grid barrier needs)
+  const int64_t per_wg = (int64_t)kFpsThreads * kFpsRegPoints;
+  const int64_t need = (n + per_wg - 1) / per_wg;  // as few as hold every point in registers
   if (g > need) g = need;
   *grid = (int)(g > 0 ? g : 1);
   return hipSuccess;

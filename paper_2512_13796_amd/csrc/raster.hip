@@ -211,25 +211,31 @@ __global__ __launch_bounds__(256) void raster_forward_kernel(const float4* __res
   n_iter[p] = last;
 }
 
-// Sum of v[0..15] over the wavefront with 17 exchanges: each halving step
-// keeps half of the values. Lane l ends with the total of value
-// 8*b5 + 4*b4 + 2*b3 + b2 (b = bits of l); lanes with l % 4 == 0 hold them.
+// Sum of v[0..15] over the wavefront: each halving step keeps half of the
+// values. Lane l ends with the total of value 8*b5 + 4*b4 + 2*b3 + b2
+// (b = bits of l); lanes with l % 4 == 0 hold them. The exchanges across
+// 32- and 16-lane halves are register swaps between two values (gfx950's
+// permlane swaps: the upper half of the first value trades places with the
+// lower half of the second), so each step is one swap and one add per pair;
+// the steps within 16 lanes use DPP and the swizzle unit, no LDS permute.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
 __device__ __forceinline__ float wave_transpose_sum16(float v[16], int lane, int* which) {
   float a8[8];
-  const bool h32 = lane & 32;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    const float send = h32 ? v[i] : v[i + 8];
-    const float keep = h32 ? v[i + 8] : v[i];
-    a8[i] = keep + __shfl_xor(send, 32, 64);
+    // lanes 0-31 end with v[i] of lanes l and l + 32, lanes 32-63 with v[i + 8]
+    const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 8]), false, false);
+    a8[i] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
   }
   float a4[4];
-  const bool h16 = lane & 16;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const float send = h16 ? a8[i] : a8[i + 4];
-    const float keep = h16 ? a8[i + 4] : a8[i];
-    a4[i] = keep + __shfl_xor(send, 16, 64);
+    // even rows of 16 lanes end with a8[i] of rows r and r + 1, odd rows with a8[i + 4]
+    const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(a8[i]), __float_as_uint(a8[i + 4]), false, false);
+    a4[i] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
   }
   float a2[2];
   const bool h8 = lane & 8;
@@ -237,13 +243,15 @@ __device__ __forceinline__ float wave_transpose_sum16(float v[16], int lane, int
   for (int i = 0; i < 2; ++i) {
     const float send = h8 ? a4[i] : a4[i + 2];
     const float keep = h8 ? a4[i + 2] : a4[i];
-    a2[i] = keep + __shfl_xor(send, 8, 64);
+    a2[i] = keep + dpp_mov<0x128>(send);  // row_ror:8 = lane ^ 8
   }
   const bool h4 = lane & 4;
-  float x = (h4 ? a2[1] : a2[0]) + __shfl_xor(h4 ? a2[0] : a2[1], 4, 64);
-  x += __shfl_xor(x, 2, 64);
-  x += __shfl_xor(x, 1, 64);
-  *which = (h32 ? 8 : 0) + (h16 ? 4 : 0) + (h8 ? 2 : 0) + (h4 ? 1 : 0);
+  const float send = h4 ? a2[0] : a2[1];
+  float x = (h4 ? a2[1] : a2[0]) +
+            __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(send), (4 << 10) | 0x1F));  // lane ^ 4
+  x += dpp_mov<0x4E>(x);  // quad_perm [2,3,0,1] = lane ^ 2
+  x += dpp_mov<0xB1>(x);  // quad_perm [1,0,3,2] = lane ^ 1
+  *which = ((lane & 32) ? 8 : 0) + ((lane & 16) ? 4 : 0) + (h8 ? 2 : 0) + (h4 ? 1 : 0);
   return x;
 }
 
