@@ -386,7 +386,7 @@ int nx_workspace_layout(nx_ctx *ctx, int64_t n_surfels, const nx_camera *cams, i
                         int64_t n_instances, nx_ws_layout *layout);
 
 /* Diagnostics: limits that force the hash-grid gradient's fallback paths,
- * which the default sizes leave idle. slab_records > 0 caps the records a
+ * which the default sizes use rarely. slab_records > 0 caps the records a
  * workgroup files per bucket slab (records beyond go straight to the table
  * with float atomics); cas_rounds > 0 caps the reduction's LDS
  * compare-and-swap retries (a record that loses them is added with a global
