@@ -58,6 +58,14 @@ def test_invalid_arguments_are_rejected_on_the_host(lib):
                                  None) == L.NX_ERR_INVALID
     assert lib.nx_render_backward(None, None, None, 1, None, None, None, None, 0, None, None, None, None,
                                   None) == L.NX_ERR_INVALID
+    batch = ctypes.c_int32()
+    assert lib.nx_autotune_raster(None, None, None, 1, None, None, 0, 3, ctypes.byref(batch),
+                                  None) == L.NX_ERR_INVALID
+    assert lib.nx_fps(None, None, 10, 5, None, None, None, 0, None) != L.NX_OK
+    assert lib.nx_aux_losses(None, 10, None, None, None, 0, None, None, None, None, None, None, None, None,
+                             None) == L.NX_ERR_INVALID
+    assert lib.nx_debug_limits(None, 0, 0) == L.NX_ERR_INVALID
+    assert lib.nx_set_sh_degree(None, 3) == L.NX_ERR_INVALID
     assert lib.nx_destroy(None) == L.NX_OK
     assert lib.nx_version() >= 100
 
