@@ -82,3 +82,18 @@ def test_aux_losses_of_a_forward(nx):
     G = wl.target[0].reshape(-1, 3).double().numpy() if wl.target[0] is not None else np.zeros((W.shape[0], 3))
     _check(nx, ctx, W, X, G, wl.scene.opacities.double().numpy(), wl.grid.table,
            np.asarray(wl.grid.level_scales, dtype=np.float32), "c1 forward")
+
+
+@pytest.mark.parametrize("K", [1, 8, 16])
+def test_aux_losses_other_slot_counts(nx, K):
+    rng = np.random.default_rng(10 + K)
+    P, N = 3000, 500
+    W = rng.uniform(0.0, 0.4 / K * 4, (P, K))
+    W[rng.random(P) < 0.1] = 0.0
+    X = rng.uniform(0.0, 1.0, (P, K, 3))
+    G = rng.uniform(0.0, 1.0, (P, 3))
+    o = rng.uniform(0.0, 1.0, N)
+    table = torch.from_numpy(rng.uniform(-1.0, 1.0, (4, 1 << 8, 2))).float()
+    scales = (16.0 * 1.5 ** np.arange(4)).astype(np.float32)
+    ctx = nx.Context(K, torch.float32, torch.float32)
+    _check(nx, ctx, W, X, G, o, table, scales, f"K={K}")

@@ -54,3 +54,36 @@ def test_sh_bf16_form_sampled(nx):
                      max_nd=3e-3)
     for nm in ("means", "quats", "scales", "opacities", "gammas", "colors"):
         assert rep[nm]["rel_l2"] <= 1e-3, f"{nm}: {rep[nm]['rel_l2']:.2e}"
+
+
+def test_sh_joint_cameras_equal_single_calls(nx):
+    """Several cameras in one call with the SH appearance: each camera's plain colours are decoded along its
+    own view directions, so the joint forward must equal the single-camera calls bit for bit, and the joint
+    backward (SH coefficients included) their summed gradients up to float32 atomic order."""
+    from tests.gpu_helpers import device_inputs
+    wl = scenes.with_sh(scenes.make_workload(4, seed=2, n_surfels=20_000))
+    cams = wl.cameras[:3]
+    surf, table, weights = device_inputs(wl)
+    ctx = nx.Context(wl.K, table.dtype, weights[0].dtype, sh_degree=3)
+    res = nx.render_forward(ctx, surf, cams, table, wl.grid.level_scales, weights)
+    P = res.image.shape[0]
+    gi = torch.randn(P, 3, device="cuda", generator=torch.Generator(device="cuda").manual_seed(4))
+    z = lambda t: torch.zeros(t.shape, device=t.device, dtype=torch.float32)
+    joint = {"means": z(surf[0]), "colors": z(surf[5]), "table": z(table)}
+    nx.render_backward(ctx, surf, res, table, wl.grid.level_scales, weights, gi, None, None, joint)
+    single = {k: z(v) for k, v in joint.items()}
+    off = 0
+    for cam in cams:
+        n = cam.width * cam.height
+        one = nx.render_forward(ctx, surf, cam, table, wl.grid.level_scales, weights)
+        torch.cuda.synchronize()
+        for nm in ("image", "plain", "tex"):
+            assert torch.equal(getattr(res, nm)[off:off + n], getattr(one, nm)), nm
+        nx.render_backward(ctx, surf, one, table, wl.grid.level_scales, weights, gi[off:off + n].contiguous(), None,
+                           None, single)
+        off += n
+    torch.cuda.synchronize()
+    for k in joint:
+        a, b = joint[k].double(), single[k].double()
+        rel = float((a - b).norm() / max(float(b.norm()), 1e-30))
+        assert rel <= 1e-4, f"{k}: joint vs summed single-camera gradients rel {rel:.2e}"
