@@ -116,13 +116,18 @@ def rooflines(phases, steps, st, form):
 
 
 def kernel_source_digest():
-    """SHA-256 of the HIP sources; hardware byte counts are only quoted for the code they were taken on."""
+    """SHA-256 of the HIP sources with comments and blank lines removed (a comment edit does not change the
+    kernels); hardware byte counts are only quoted for the code they were taken on."""
     import hashlib
+    import re
     h = hashlib.sha256()
     src = os.path.join(ROOT, "paper_2512_13796_amd", "csrc")
     for name in sorted(os.listdir(src)):
         if name.endswith((".hip", ".h")):
-            h.update(open(os.path.join(src, name), "rb").read())
+            t = open(os.path.join(src, name), encoding="utf-8").read()
+            t = re.sub(r"/\*.*?\*/", "", t, flags=re.S)
+            t = re.sub(r"//[^\n]*", "", t)
+            h.update("\n".join(ln.rstrip() for ln in t.splitlines() if ln.strip()).encode())
     return h.hexdigest()
 
 

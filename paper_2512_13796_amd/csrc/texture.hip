@@ -9,7 +9,8 @@
 // scaled by Delta_l = 1 - exp(-(f / (s_l D))^2 / (2 pi)) (eq. downweighting).
 // The sample position gets a gradient through the interpolation
 // (supplementary, Other details). MLP: hidden layers without bias, ReLU; the
-// RGB head uses a sigmoid.
+// RGB head uses a sigmoid, the SH head's 48 outputs (degree 3) are decoded
+// along the pixel's unit ray (Representation, Appearance).
 //
 // Work split: one wavefront handles 16 samples at a time. Lane (g, c), with
 // g = lane / 16 and c = lane % 16, owns sample c and the four levels
@@ -29,7 +30,8 @@
 // global memory once. It writes each sample's per-level feature gradients;
 // the hash-grid gradient is then formed level by level without floating-point
 // global atomics (scatter_bin files corner records into per-workgroup slabs,
-// scatter_reduce sums each bucket's records in LDS).
+// one launch per level over all cameras of a call; scatter_reduce sums each
+// bucket's records in LDS).
 #include <hip/hip_fp16.h>
 #include <type_traits>
 #include <math.h>
