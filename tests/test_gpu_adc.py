@@ -105,3 +105,16 @@ def test_densify_equals_oracle(nx, ctx, n, frac):
     assert np.array_equal(parent.cpu().numpy(), ref_parent)
     for a, b in zip(out, ref):
         assert np.array_equal(a.cpu().numpy(), b.astype(np.float32))
+
+
+def test_fps_beyond_register_capacity_equals_oracle(nx, ctx):
+    """More points than the registers of a full grid hold (256 CUs x 1024 threads x 8 points): FPS keeps the
+    nearest distances in global memory instead; the order and distances must still equal the oracle's."""
+    rng = np.random.default_rng(21)
+    n, m = 2_200_000, 60
+    pts = _clustered(rng, n)
+    o_gpu, d_gpu = _gpu_fps(nx, ctx, pts, m)
+    o_ref, d_ref = farthest_point_sampling(pts, m)
+    log(f"fps n={n} m={m} (distances in global memory): last d2 {d_gpu[-1]:.4g}")
+    assert np.array_equal(o_gpu, o_ref)
+    assert np.array_equal(d_gpu.view(np.uint32), d_ref.view(np.uint32))
