@@ -1246,7 +1246,7 @@ int nx_render_backward(nx_ctx* ctx, const nx_surfels* surfels, const nx_camera* 
       NX_CHECK_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_bin[a], 0));
       {
         PhaseTimer pt(ctx, "scatter_reduce", ctx->side);
-        NX_CHECK_HIP(nx::launch_hash_scatter_reduce(gd0, l, grads->table, SH.rows, tab, rk, rv, ctx->debug_cas,
+        NX_CHECK_HIP(nx::launch_hash_scatter_reduce(gd0, l, grads->table, SH.rows, SH.blocks, tab, rk, rv, ctx->debug_cas,
                                                     ctx->side));
       }
       NX_CHECK_HIP(hipEventRecord(ctx->ev_red[a], ctx->side));

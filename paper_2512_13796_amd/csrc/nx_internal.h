@@ -167,9 +167,8 @@ hipError_t launch_hash_scatter_bin(int K, const ScatterCam& cam0, const ScatterC
                                    const GridDev& grid0, int level, float* g_table, int64_t n_rows, uint2* slab_table,
                                    uint16_t* rec_key, float2* rec_val, int64_t slab_cap, hipStream_t s);
 hipError_t launch_hash_scatter_reduce(const GridDev& grid, int level, float* g_table, int64_t n_rows,
-                                      const uint2* slab_table, const uint16_t* rec_key, const float2* rec_val,
-                                      int cas_rounds,
-                                      hipStream_t s);
+                                      int64_t n_blocks, const uint2* slab_table, const uint16_t* rec_key,
+                                      const float2* rec_val, int cas_rounds, hipStream_t s);
 
 // Auxiliary losses (L_alpha, L_texture over P pixels with K slots; L_opacity
 // over n surfels; L_grid over the table): gradients scaled by the lambdas are

@@ -78,7 +78,13 @@ __device__ __forceinline__ float2 load_pair(const void* table, uint32_t idx) {
   }
 }
 
-__device__ __forceinline__ uint32_t map_positive(int z) { return z > 0 ? (uint32_t)(2 * z - 1) : (uint32_t)(-2 * z); }
+// MapPositive (supplementary, Implementation Details): z > 0 -> 2z - 1,
+// z <= 0 -> -2z, i.e. the zigzag code of -z. Written with shifts: the
+// compiler turns the two-armed select into a branch on the execution mask.
+__device__ __forceinline__ uint32_t map_positive(int z) {
+  const uint32_t n = 0u - (uint32_t)z;
+  return (n << 1) ^ (uint32_t)((int32_t)n >> 31);
+}
 
 // Feature index (0..31) held by lane group g in element e of a layer-1 operand.
 __device__ __forceinline__ int feat_index(int g, int e) { return e < 4 ? 4 * g + e : 16 + 4 * g + (e - 4); }
@@ -1285,7 +1291,7 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
     uint2* __restrict__ slab_table, uint16_t* __restrict__ rec_key, float2* __restrict__ rec_val) {
   // LDS: the per-sample stage (corner values, cells, sort keys) and, once
   // those are in registers, the block's records grouped by bucket share one
-  // region; per-bucket counters follow it (dynamic size: 3 nb words).
+  // region; per-bucket counters follow it (dynamic size: 4 nb words).
   extern __shared__ __attribute__((aligned(16))) unsigned char scat_lds[];
   // [e.x, e.y, fx, fy, fz][sample]: feature gradient and position in the cell
   auto& sfeat = *reinterpret_cast<float(*)[5][kBlockSamples]>(scat_lds);
@@ -1295,8 +1301,10 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
   float2* st_v = reinterpret_cast<float2*>(scat_lds + sizeof(uint32_t) * kBlockRecords);  // record: 2 values
   const int nb = 1 << (log2_size - bucket_log2);
   uint32_t* hist = reinterpret_cast<uint32_t*>(scat_lds + kScatStageBytes);  // count, then local offset
-  uint32_t* gdelta = hist + nb;  // slab slot minus local position
-  uint32_t* wcur = gdelta + nb;  // records this workgroup has filed per bucket
+  // per bucket: (record slot of local position 0, first local position that
+  // no longer fits the slab)
+  uint2* gslot = reinterpret_cast<uint2*>(hist + nb);
+  uint32_t* wcur = hist + 3 * nb;  // records this workgroup has filed per bucket
   __shared__ uint32_t wsum[kScatThreads / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, c = lane & 15;
   const int row = threadIdx.x >> 4;
@@ -1309,6 +1317,7 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
   const int G = gridDim.x;
   const int wg = (G % 8 == 0) ? (int)(blockIdx.x % 8) * (G / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
   const size_t slab_base = (size_t)wg * nb * slab;  // this workgroup's slab of bucket 0
+  const uint32_t slab_base32 = (uint32_t)slab_base;  // the launch keeps every slot below 2^32
   for (int i = threadIdx.x; i < nb; i += kScatThreads) wcur[i] = 0u;
   int cam = 0;  // blocks ascend, so the camera only moves forward
   for (int64_t blk = wg; blk < n_blocks; blk += G) {
@@ -1460,7 +1469,10 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
       for (int i = 0; i < kScatMaxBuckets / kScatThreads; ++i) {
         if (i < per && b0 + i < nb) {
           const uint32_t used = wcur[b0 + i];
-          gdelta[b0 + i] = used - off;
+          // a record at local position i goes to slot i + used - off of the
+          // bucket's slab, if that is below slab
+          gslot[b0 + i] = make_uint2(slab_base32 + (uint32_t)(b0 + i) * slab + used - off,
+                                     (uint32_t)((int)off + (int)slab - (int)used));
           wcur[b0 + i] = used + cnt[i];
           hist[b0 + i] = off;  // from here on: the bucket's local offset
           off += cnt[i];
@@ -1494,19 +1506,32 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
       }
     }
     __syncthreads();
-    // 7. consecutive records of a bucket go to consecutive global slots
-    for (uint32_t i = threadIdx.x; i < n_rec; i += kScatThreads) {
-      const uint32_t h = st_h[i];
-      const float2 v = st_v[i];
-      const uint32_t bk = h >> bucket_log2;
-      const uint32_t pos = i + gdelta[bk];
-      if (pos < slab) {
-        const size_t at = slab_base + (size_t)bk * slab + pos;
-        rec_key[at] = (uint16_t)(h & emask);
-        rec_val[at] = v;
-      } else {  // slab full: add straight into the table
-        unsafeAtomicAdd(&g_level[2 * (size_t)h], v.x);
-        unsafeAtomicAdd(&g_level[2 * (size_t)h + 1], v.y);
+    // 7. consecutive records of a bucket go to consecutive global slots (four
+    // records per thread in flight)
+    for (uint32_t i0 = threadIdx.x; i0 < n_rec; i0 += 4 * kScatThreads) {
+      uint32_t h[4];
+      float2 v[4];
+      uint2 gs[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t i = i0 + u * kScatThreads;
+        h[u] = i < n_rec ? st_h[i] : 0u;
+        v[u] = i < n_rec ? st_v[i] : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) gs[u] = gslot[h[u] >> bucket_log2];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t i = i0 + u * kScatThreads;
+        if (i >= n_rec) continue;
+        if ((int)i < (int)gs[u].y) {
+          const uint32_t at = gs[u].x + i;
+          rec_key[at] = (uint16_t)(h[u] & emask);
+          rec_val[at] = v[u];
+        } else {  // slab full: add straight into the table
+          unsafeAtomicAdd(&g_level[2 * (size_t)h[u]], v[u].x);
+          unsafeAtomicAdd(&g_level[2 * (size_t)h[u] + 1], v[u].y);
+        }
       }
     }
     __syncthreads();
@@ -1544,6 +1569,7 @@ __device__ __forceinline__ void wave_sort_by_key(uint32_t& key, float& a, float&
 #undef NX_WS_STAGE
 }
 
+template <int KR>
 __global__ __launch_bounds__(kReduceThreads) void scatter_reduce_kernel(int bucket_log2, int coarse, int cas_rounds,
                                                                        int64_t n_rows,
                                                                        const uint2* __restrict__ slab_table,
@@ -1587,30 +1613,44 @@ __global__ __launch_bounds__(kReduceThreads) void scatter_reduce_kernel(int buck
       }
     }
   } else {
-  // fine level: four records in flight per lane
-  constexpr int kU = 4;
-  for (int64_t r = grp; r < n_rows; r += kGroups) {
-    const uint2 sl = col[r];
-    const uint16_t* rk = rec_key + sl.x;
-    const float2* rv = rec_val + sl.x;
-    for (uint32_t i0 = c; i0 < sl.y; i0 += 16 * kU) {
-      uint32_t k[kU];
-      float2 v[kU];
+    // Fine level: a group keeps up to kU records of each of KR rows in
+    // flight. Where a slab row holds only a few dozen records (a few blocks
+    // per binning workgroup), walking one row at a time would wait on two
+    // dependent memory reads (the row's slab entry, then its records) per few
+    // dozen records, so KR = 4; longer rows keep a group busy with KR = 1.
+    constexpr int kU = 4, kR = KR;
+    for (int64_t r0 = grp; r0 < n_rows; r0 += (int64_t)kGroups * kR) {
+      uint2 sl[kR];
+      uint32_t most = 0;
 #pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        const uint32_t i = i0 + 16 * u;
-        k[u] = i < sl.y ? rk[i] : 0u;
-        v[u] = i < sl.y ? rv[i] : make_float2(0.f, 0.f);
+      for (int q = 0; q < kR; ++q) {
+        const int64_t r = r0 + (int64_t)q * kGroups;
+        sl[q] = r < n_rows ? col[r] : make_uint2(0u, 0u);
+        most = max(most, sl[q].y);
       }
+      for (uint32_t i0 = c; i0 < most; i0 += 16 * kU) {
+        uint32_t k[kR][kU];
+        float2 v[kR][kU];
 #pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        if (i0 + 16 * u < sl.y && !lds_add_pair(&acc[k[u]], v[u].x, v[u].y, cas_rounds)) {
-          unsafeAtomicAdd(&out[k[u]].x, v[u].x);
-          unsafeAtomicAdd(&out[k[u]].y, v[u].y);
-        }
+        for (int q = 0; q < kR; ++q)
+#pragma unroll
+          for (int u = 0; u < kU; ++u) {
+            const uint32_t i = i0 + 16 * u;
+            const bool ok = i < sl[q].y;
+            k[q][u] = ok ? (uint32_t)rec_key[sl[q].x + i] : 0u;
+            v[q][u] = ok ? rec_val[sl[q].x + i] : make_float2(0.f, 0.f);
+          }
+#pragma unroll
+        for (int q = 0; q < kR; ++q)
+#pragma unroll
+          for (int u = 0; u < kU; ++u) {
+            if (i0 + 16 * u < sl[q].y && !lds_add_pair(&acc[k[q][u]], v[q][u].x, v[q][u].y, cas_rounds)) {
+              unsafeAtomicAdd(&out[k[q][u]].x, v[q][u].x);
+              unsafeAtomicAdd(&out[k[q][u]].y, v[q][u].y);
+            }
+          }
       }
     }
-  }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < n_e; i += kReduceThreads) {
@@ -1816,7 +1856,7 @@ hipError_t launch_hash_scatter_bin(int K, const ScatterCam& cam0, const ScatterC
   if (!scatter_launch(grid0, &sl)) return hipErrorInvalidValue;
   const ScatterSlabs sb = scatter_slabs_blocks(n_blocks, sl.nb);
   if (sb.wgs > n_rows || sb.wgs * sl.nb * sb.slab > 0xFFFFFFFFll) return hipErrorInvalidValue;
-  const size_t lds = kScatStageBytes + 3 * sizeof(uint32_t) * sl.nb;
+  const size_t lds = kScatStageBytes + 4 * sizeof(uint32_t) * sl.nb;
   // a smaller slab (diagnostics) stays inside the records laid out for the full one
   const int64_t slab = slab_cap > 0 && slab_cap < sb.slab ? slab_cap : sb.slab;
   if (n_cams == 1) {
@@ -1833,8 +1873,8 @@ hipError_t launch_hash_scatter_bin(int K, const ScatterCam& cam0, const ScatterC
 }
 
 hipError_t launch_hash_scatter_reduce(const GridDev& grid, int level, float* g_table, int64_t n_rows,
-                                      const uint2* slab_table, const uint16_t* rec_key, const float2* rec_val,
-                                      int cas_rounds, hipStream_t s) {
+                                      int64_t n_blocks, const uint2* slab_table, const uint16_t* rec_key,
+                                      const float2* rec_val, int cas_rounds, hipStream_t s) {
   if (level < 0 || level >= grid.levels || n_rows <= 0) return hipSuccess;
   ScatterLaunch sl;
   if (!scatter_launch(grid, &sl)) return hipErrorInvalidValue;
@@ -1844,8 +1884,16 @@ hipError_t launch_hash_scatter_reduce(const GridDev& grid, int level, float* g_t
   const int coarse = corners < 65536.0f ? 1 : 0;
   const size_t lds = sizeof(unsigned long long) << sl.bl;
   const int rounds = cas_rounds > 0 ? cas_rounds : kMaxCasRounds;
-  hipLaunchKernelGGL(scatter_reduce_kernel, dim3((unsigned)sl.nb), dim3(kReduceThreads), lds, s, sl.bl, coarse, rounds,
-                     n_rows, slab_table, rec_key, rec_val, g_table + 2 * ((size_t)level << grid.log2_size));
+  float* g_level = g_table + 2 * ((size_t)level << grid.log2_size);
+  // measured: four rows at once pays at 8 blocks per binning workgroup (one
+  // 1080p camera) and costs at about 60 (sixteen cameras)
+  if (n_blocks <= 16 * n_rows) {
+    hipLaunchKernelGGL(scatter_reduce_kernel<4>, dim3((unsigned)sl.nb), dim3(kReduceThreads), lds, s, sl.bl, coarse,
+                       rounds, n_rows, slab_table, rec_key, rec_val, g_level);
+  } else {
+    hipLaunchKernelGGL(scatter_reduce_kernel<1>, dim3((unsigned)sl.nb), dim3(kReduceThreads), lds, s, sl.bl, coarse,
+                       rounds, n_rows, slab_table, rec_key, rec_val, g_level);
+  }
   return hipGetLastError();
 }
 
