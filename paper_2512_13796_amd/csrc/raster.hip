@@ -58,7 +58,9 @@ __device__ __forceinline__ bool eval_pair(const float4& r0, const float4& r1, co
   e.t = r2.z * e.inv;
   e.u = fmaf(e.dx, r1.x, e.dy * r1.y) * e.inv;
   e.v = fmaf(e.dx, r1.z, e.dy * r1.w) * e.inv;
-  if (!(e.t > near_z && fabsf(e.u) <= kSupport && fabsf(e.v) <= kSupport)) return false;
+  // one combined test (bitwise, not short-circuit: each && would become a
+  // branch on the execution mask)
+  if (!((e.t > near_z) & (fabsf(e.u) <= kSupport) & (fabsf(e.v) <= kSupport))) return false;
   if (r3.x == 1.0f && r3.y == 1.0f) {
     e.pu = e.u * e.u;
     e.pv = e.v * e.v;
@@ -160,12 +162,12 @@ __global__ __launch_bounds__(256) void raster_forward_kernel(const float4* __res
           int wi = kid[0], ws = 0;
 #pragma unroll
           for (int s = 1; s < KB; ++s) {
-            const bool worse = kw[s] < ww || (kw[s] == ww && kid[s] > wi);
+            const bool worse = (kw[s] < ww) | ((kw[s] == ww) & (kid[s] > wi));
             ww = worse ? kw[s] : ww;
             wi = worse ? kid[s] : wi;
             ws = worse ? s : ws;
           }
-          if (w > ww || (w == ww && id < wi)) {
+          if ((w > ww) | ((w == ww) & (id < wi))) {
 #pragma unroll
             for (int s = 0; s < KB - 1; ++s)
               if (s >= ws) {
