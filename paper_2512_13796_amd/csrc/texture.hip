@@ -1347,7 +1347,7 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
       const SampleInfo si = sample_ray_xy(gd, K, in ? qx : 0, in ? qy : 0, j, c, depths);
       float2 e = make_float2(0.f, 0.f);
       if (in && si.valid) e = feat_grad[((int64_t)level * nqK + ((int64_t)qy * npx + qx) * K + j) * 16 + c];
-      const bool act = in && si.valid && (e.x != 0.f || e.y != 0.f);
+      const bool act = in & si.valid & ((e.x != 0.f) | (e.y != 0.f));
       const LevelGeom lg = level_geom(L, si);
       sfeat[0][smp] = act ? e.x : 0.f;
       sfeat[1][smp] = act ? e.y : 0.f;
@@ -1380,7 +1380,9 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
       const uint32_t h0 = key[0] >> 7, h1 = key[1] >> 7;
       const uint32_t below = dpp_u<kDppRowShl2>(h0), next_slot = dpp_u<kDppRowShl8>(h0);
       const bool live0 = h0 != kInactiveKey;
-      const bool shared = live0 && (h0 == h1 || ((lane & 15) < 14 && h0 == below) || ((lane & 15) < 8 && h0 == next_slot));
+      // bitwise, not short-circuit (each && or || would be a branch on the execution mask)
+      const bool shared =
+          live0 & ((h0 == h1) | (((lane & 15) < 14) & (h0 == below)) | (((lane & 15) < 8) & (h0 == next_slot)));
       if (__any(shared)) bitonic_sort_regs<2>(key, p0);
     }
     // 3. segments of equal cells along the sorted order, summed within each wave
@@ -1408,12 +1410,12 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
       }
     }
     // element 1 continues element 0's segment?
-    const bool same01 = live[0] == live[1] && cx[0] == cx[1] && cy[0] == cy[1] && cz[0] == cz[1];
+    const bool same01 = (live[0] == live[1]) & (cx[0] == cx[1]) & (cy[0] == cy[1]) & (cz[0] == cz[1]);
     // previous lane's last element continues into this lane's element 0?
     const int pcx = (int)dpp_u<kDppWaveShr1>((uint32_t)cx[1]), pcy = (int)dpp_u<kDppWaveShr1>((uint32_t)cy[1]);
     const int pcz = (int)dpp_u<kDppWaveShr1>((uint32_t)cz[1]);
     const bool plive = dpp_u<kDppWaveShr1>(live[1] ? 1u : 0u) != 0u;
-    const bool cont0 = lane > 0 && plive == live[0] && pcx == cx[0] && pcy == cy[0] && pcz == cz[0];
+    const bool cont0 = (lane > 0) & (plive == live[0]) & (pcx == cx[0]) & (pcy == cy[0]) & (pcz == cz[0]);
     // next lane's element 0 continues element 1's segment?
     const bool next_cont = dpp_u<kDppWaveShl1>(cont0 ? 1u : 0u) != 0u;
     const bool tail1 = lane == 63 || !next_cont;
@@ -1422,17 +1424,18 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
     // two values are zero is filed like any other). Which records exist is
     // known before their values, so they are counted first: the count's old
     // value is the record's rank among the block's records of its bucket.
-    const bool emit[2] = {tail0 && live[0], tail1 && live[1]};
-    uint32_t rh[2][8], rank[2][8];
+    const bool emit[2] = {(bool)(tail0 & live[0]), (bool)(tail1 & live[1])};
+    uint32_t rh[2][8], rank[2][8];  // rank: only where emit
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       const uint32_t hx0 = map_positive(cx[e]), hx1 = map_positive(cx[e] + 1);
       const uint32_t hy0 = map_positive(cy[e]) * kPrime1, hy1 = map_positive(cy[e] + 1) * kPrime1;
       const uint32_t hz0 = map_positive(cz[e]) * kPrime2, hz1 = map_positive(cz[e] + 1) * kPrime2;
 #pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        rh[e][b] = ((b & 1 ? hx1 : hx0) ^ (b & 2 ? hy1 : hy0) ^ (b & 4 ? hz1 : hz0)) & mask;
-        rank[e][b] = emit[e] ? atomicAdd(&hist[rh[e][b] >> bucket_log2], 1u) : 0u;
+      for (int b = 0; b < 8; ++b) rh[e][b] = ((b & 1 ? hx1 : hx0) ^ (b & 2 ? hy1 : hy0) ^ (b & 4 ? hz1 : hz0)) & mask;
+      if (emit[e]) {  // one branch for the element's 8 counts
+#pragma unroll
+        for (int b = 0; b < 8; ++b) rank[e][b] = atomicAdd(&hist[rh[e][b] >> bucket_log2], 1u);
       }
     }
     __syncthreads();
