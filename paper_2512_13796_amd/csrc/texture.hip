@@ -836,14 +836,22 @@ struct UnitTiles {
 // read from wop in global memory (L2-resident; hidden width 128, whose slots
 // do not fit in LDS next to the activation tiles).
 //
-// Weight gradients: every round each of the 4 waves handles one unit (16
+// Weight gradients: every round each of the NW waves handles one unit (16
 // samples at one slot of a 4x4-pixel patch) and writes its activation tiles
-// to LDS; after a barrier every wave multiplies the tiles of all 4 units into
-// its own quarter of dW1, dW2 and dW3 (row tiles split across the waves),
-// which it keeps in MFMA accumulator registers for the whole launch and adds
-// to global memory once at the end.
+// to LDS; after a barrier every wave multiplies the tiles of all NW units into
+// its own share of dW1, dW2 and dW3 (row tiles split across the waves), which
+// it keeps in MFMA accumulator registers for the whole launch and adds to
+// global memory once at the end. NW = 4, except BF16 at hidden width 128,
+// which runs 8 waves (one workgroup per CU, 143 KB of tiles): a wave's share
+// of the 128 x 128 dW2 then fits its registers beside the activations
+// (with 4 waves it holds twice as much and spills).
+constexpr int bwd_waves(bool bf, int hid) { return (bf && hid == 128) ? 8 : 4; }
+// workgroups per CU the launch bounds ask for: two, or one where a workgroup
+// is 8 waves or FP32 at hidden width 128
+constexpr int bwd_blocks(bool bf, int hid) { return bwd_waves(bf, hid) == 8 ? 1 : ((hid <= 64 || bf) ? 2 : 1); }
+
 template <int TDT, bool BF, int HID, bool SH, bool WLDS>
-__global__ __launch_bounds__(kTexThreads, (HID <= 64 || BF) ? 2 : 1) void texture_backward_kernel(
+__global__ __launch_bounds__(64 * bwd_waves(BF, HID), bwd_blocks(BF, HID)) void texture_backward_kernel(
     GridDev gd, const void* __restrict__ table, const void* w1, const void* w2, const void* w3,
     const unsigned char* __restrict__ wop, int in_dim, int K,
     int log2K, int64_t n_samples, const int32_t* __restrict__ ids, const float* __restrict__ depths,
@@ -853,11 +861,13 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 || BF) ? 2 : 1) void textur
   using UT = UnitTiles<BF, HID, SH>;
   constexpr int MT = LY::MT;
   constexpr int OT = LY::OT;
-  constexpr int RT = MT / kWaves;           // row tiles of dW1 / dW2 per wave
-  constexpr int CT3 = MT / kWaves;          // column tiles of dW3 per wave
-  static_assert(RT >= 1 && RT * kWaves == MT, "hidden width must be a multiple of 64");
+  constexpr int NW = bwd_waves(BF, HID);
+  constexpr int RT = MT / NW;   // row tiles of dW1 / dW2 per wave
+  constexpr int CT3 = MT / NW;  // column tiles of dW3 per wave
+  static_assert(RT >= 1 && RT * NW == MT, "hidden width must be a multiple of 16 NW");
+  static_assert(!WLDS || NW == kWaves, "weights are staged in LDS by 4-wave workgroups only");
   __shared__ __attribute__((aligned(16))) unsigned char lds[WLDS ? LY::nAll * LY::slot_bytes : 16];
-  __shared__ __attribute__((aligned(16))) unsigned char tiles[kWaves * UT::bytes];
+  __shared__ __attribute__((aligned(16))) unsigned char tiles[NW * UT::bytes];
   const unsigned char* W;
   if constexpr (WLDS) {
     stage_weights<BF, HID, SH>(lds, LY::nAll, w1, w2, w3, in_dim);
@@ -883,8 +893,8 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 || BF) ? 2 : 1) void textur
 #pragma unroll
   for (int i = 0; i < RT * 2; ++i) accW1[i] = zero;
 
-  const int64_t first = xcd_local_block() * kWaves;
-  const int64_t stride = (int64_t)gridDim.x * kWaves;
+  const int64_t first = xcd_local_block() * NW;
+  const int64_t stride = (int64_t)gridDim.x * NW;
   const int64_t n_rounds = first < n_units ? (n_units - first + stride - 1) / stride : 0;
   for (int64_t round = 0; round < n_rounds; ++round) {
     if constexpr (!WLDS) {
@@ -1061,9 +1071,9 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 || BF) ? 2 : 1) void textur
       for (int i = lane; i < UT::bytes / 4; i += 64) reinterpret_cast<uint32_t*>(T)[i] = 0u;
     }
     __syncthreads();
-    // ---- this wave's quarter of the weight gradients over the round's 4 units
+    // ---- this wave's share of the weight gradients over the round's NW units
 #pragma unroll 1
-    for (int u = 0; u < kWaves; ++u) {
+    for (int u = 0; u < NW; ++u) {
       const unsigned char* U = tiles + u * UT::bytes;
       weight_grad_accum<BF, PAD, OT, CT3>(row_ptr(U, UT::oY3), row_ptr(U, UT::oX3 + 16 * CT3 * wave), accW3, lane);
       weight_grad_accum<BF, PAD, RT, MT>(row_ptr(U, UT::oY2 + 16 * RT * wave), row_ptr(U, UT::oX2), accW2, lane);
@@ -1700,15 +1710,19 @@ hipError_t bwd_inst(const GridDev& gd, const void* table, const MlpDev& mlp, int
   // operand slots in LDS for the BF16 hidden-64 RGB form; the others read them
   // from the workspace (L2-resident), leaving LDS to the activation tiles
   constexpr bool kWlds = HID <= 64 && BF && !SH;
+  constexpr int NW = bwd_waves(BF, HID);
   const int64_t n_q = n_patches(gd) * K;
-  int64_t grid = (n_q + kWaves - 1) / kWaves;
-  if (grid > 1024) grid = 1024;
+  int64_t grid = (n_q + NW - 1) / NW;
+  // about two workgroups' worth per resident slot (two per CU with 4 waves,
+  // one with 8)
+  const int64_t max_grid = NW == 8 ? 512 : 1024;
+  if (grid > max_grid) grid = max_grid;
   if (grid < 1) grid = 1;
   if constexpr (!kWlds) {
     hipLaunchKernelGGL((stage_weight_operands_kernel<BF, HID, SH>), dim3(64), dim3(256), 0, s, wop, mlp.w[0],
                        mlp.w[1], mlp.w[2], mlp.in_dim);
   }
-  hipLaunchKernelGGL((texture_backward_kernel<TDT, BF, HID, SH, kWlds>), dim3((unsigned)grid), dim3(kTexThreads), 0,
+  hipLaunchKernelGGL((texture_backward_kernel<TDT, BF, HID, SH, kWlds>), dim3((unsigned)grid), dim3(64 * NW), 0,
                      s, gd, table, mlp.w[0], mlp.w[1], mlp.w[2], wop, mlp.in_dim, K, ilog2(K), n_samples, ids, depths,
                      weights, grad_image, grad_tex, feat_grad, g0, g1, g2, grad_depth);
   return hipGetLastError();
