@@ -8,7 +8,8 @@ ids bit-exact on decisive pixels, image / textures within 1e-5 (FP32 form),
 gradients (including the 48 coefficients per surfel, the centre's gradient
 through the view direction and the 48-row head) within relative L2 1e-3 and
 the per-element rule; the BF16 form against the BF16 bar. Covered: K = 0
-(colours only), K = 4, hidden width 64 and 128, FP32 and BF16 forms.
+(colours only), K = 4, hidden width 64 and 128, FP32 and BF16 forms (both at
+hidden width 128).
 """
 from __future__ import annotations
 
@@ -43,6 +44,15 @@ def test_sh_backward_hidden128_fp32(nx):
     wl = scenes.with_sh(wl, seed=9)
     pix = _sample_pixels(wl.cameras[0], 3, per_block=16, full_tiles=2)
     _grad_case(nx, wl, label="sh h128 fp32", pixels=pix)
+
+
+def test_sh_backward_hidden128_bf16(nx):
+    """The 48-output head at hidden width 128 in the BF16 form (BF16 grid and MLP): the texture backward runs
+    8-wave workgroups there. BF16 bars as for the RGB head at this width."""
+    wl = scenes.make_workload(5, seed=11, n_surfels=40_000, width=160, height=90)
+    wl = scenes.with_sh(wl, seed=11)
+    pix = _sample_pixels(wl.cameras[0], 5, per_block=16, full_tiles=2)
+    _grad_case(nx, wl, label="sh h128 bf16", pixels=pix, rel_tol=5e-2, bf16_bound=BF16_VIOL, tol_fwd=1e-3)
 
 
 def test_sh_bf16_form_sampled(nx):
