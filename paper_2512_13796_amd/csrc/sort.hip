@@ -258,13 +258,22 @@ __global__ __launch_bounds__(256) void duplicate_kernel(const uint32_t* __restri
   const uint32_t base = soff[wave][0];
   const uint32_t end = soff[wave][64] < cap ? soff[wave][64] : cap;
   const uint32_t total = end > base ? end - base : 0u;
+  // j: the last surfel whose range starts at or before o (non-empty: o < its
+  // end). A lane's instances only move forward, 64 at a time, and a surfel
+  // that covers thousands of tiles keeps every lane on it for many steps, so
+  // the search starts from the previous j and is skipped while o is still
+  // inside surfel j (one LDS read per step instead of six; the wave that
+  // holds the largest surfels sets the kernel's duration).
+  int j = 0;
   for (uint32_t k = lane; k < total; k += 64) {
     const uint32_t o = base + k;
-    // last surfel j whose range starts at or before o (non-empty: o < its end)
-    int j = 0;
+    if (soff[wave][j + 1] <= o) {  // soff[wave][64] is the wave's end, above every o
+      int lo = j + 1;
 #pragma unroll
-    for (int step = 32; step >= 1; step >>= 1)
-      if (soff[wave][j + step] <= o) j += step;
+      for (int step = 32; step >= 1; step >>= 1)
+        if (lo + step <= 63 && soff[wave][lo + step] <= o) lo += step;
+      j = lo;
+    }
     const int4 r = srect[wave][j];
     const uint32_t w = (uint32_t)(r.z - r.x + 1);
     const uint32_t t = o - soff[wave][j];
