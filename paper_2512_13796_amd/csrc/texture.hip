@@ -586,30 +586,26 @@ __device__ __forceinline__ void gather_lane(const GridDev& gd, const void* table
       // p = s (o + D d), so dp/dD = s d; the trilinear weight's derivative
       // along an axis is the product of the other two weights with sign + / -
       // for the upper / lower corner; Delta = 1 - exp(-kappa/D^2) gives
-      // dDelta/dD = -(1 - Delta) 2 kappa / D^3.
+      // dDelta/dD = -(1 - Delta) 2 kappa / D^3. Each corner's weight is
+      // differentiated along d first (one scalar per corner), so the entries
+      // enter as in the interpolation: 16 multiply-adds on the stored values.
       const GridLevel& L = gd.lv[lane_level(g, i) < gd.levels ? lane_level(g, i) : 0];
       const float wx[2] = {1.f - lg[i].frx, lg[i].frx}, wy[2] = {1.f - lg[i].fry, lg[i].fry};
       const float wz[2] = {1.f - lg[i].frz, lg[i].frz};
-      float ax0 = 0.f, ax1 = 0.f, ay0 = 0.f, ay1 = 0.f, az0 = 0.f, az1 = 0.f;
+      float ax0 = 0.f, ax1 = 0.f;  // sum over corners of entry x (d w_b / d p . d)
 #pragma unroll
-      for (int u = 0; u < 2; ++u)
-#pragma unroll
-        for (int v = 0; v < 2; ++v) {
-          const float2 x0 = entry_value<TDT>(E.ent[i][2 * u + 4 * v]), x1 = entry_value<TDT>(E.ent[i][1 + 2 * u + 4 * v]);
-          const float2 y0 = entry_value<TDT>(E.ent[i][u + 4 * v]), y1 = entry_value<TDT>(E.ent[i][u + 2 + 4 * v]);
-          const float2 z0 = entry_value<TDT>(E.ent[i][u + 2 * v]), z1 = entry_value<TDT>(E.ent[i][u + 2 * v + 4]);
-          const float cx = wy[u] * wz[v], cy = wx[u] * wz[v], cz = wx[u] * wy[v];
-          ax0 = fmaf(cx, x1.x - x0.x, ax0);
-          ax1 = fmaf(cx, x1.y - x0.y, ax1);
-          ay0 = fmaf(cy, y1.x - y0.x, ay0);
-          ay1 = fmaf(cy, y1.y - y0.y, ay1);
-          az0 = fmaf(cz, z1.x - z0.x, az0);
-          az1 = fmaf(cz, z1.y - z0.y, az1);
-        }
+      for (int b = 0; b < 8; ++b) {
+        const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
+        const float gx = wy[by] * wz[bz], gy = wx[bx] * wz[bz], gz = wx[bx] * wy[by];
+        const float dw = fmaf(bz ? gz : -gz, si.dz, fmaf(by ? gy : -gy, si.dy, (bx ? gx : -gx) * si.dx));
+        const float2 th = entry_value<TDT>(E.ent[i][b]);
+        ax0 = fmaf(dw, th.x, ax0);
+        ax1 = fmaf(dw, th.y, ax1);
+      }
       const float ds = lg[i].delta * L.scale;
       const float ddelta = -lg[i].expo * 2.0f * L.kappa * rcp(si.D * si.D * si.D);
-      const float c0 = ds * (ax0 * si.dx + ay0 * si.dy + az0 * si.dz) + ddelta * f0;
-      const float c1 = ds * (ax1 * si.dx + ay1 * si.dy + az1 * si.dz) + ddelta * f1;
+      const float c0 = ds * ax0 + ddelta * f0;
+      const float c1 = ds * ax1 + ddelta * f1;
       dcoef[2 * i] = E.act[i] ? c0 : 0.f;
       dcoef[2 * i + 1] = E.act[i] ? c1 : 0.f;
       // keep the coefficients here, so that the entries die now rather than
