@@ -257,9 +257,14 @@ __device__ __forceinline__ s8 pack_tiles(f4 a, f4 b) {
   const u4v w = {pack_bf16x2(a[0], a[1]), pack_bf16x2(a[2], a[3]), pack_bf16x2(b[0], b[1]), pack_bf16x2(b[2], b[3])};
   return __builtin_bit_cast(s8, w);
 }
+// max(x, 0) as one integer max on the bit pattern (a float with the sign bit
+// set is a negative integer; -0 becomes +0): fmaxf takes two instructions
+// here, the first of which only quiets a signalling NaN.
+__device__ __forceinline__ float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
 __device__ __forceinline__ f4 relu4(f4 x) {
 #pragma unroll
-  for (int e = 0; e < 4; ++e) x[e] = fmaxf(x[e], 0.0f);
+  for (int e = 0; e < 4; ++e) x[e] = relu(x[e]);
   return x;
 }
 
@@ -685,7 +690,7 @@ __global__ __launch_bounds__(kTexThreads, (HID <= 64 && BF && TDT != NX_F32 && !
         sh_basis16(si.dx * inv, si.dy * inv, si.dz * inv, Y);
         sh_decode(o, Y, g, raw);
 #pragma unroll
-        for (int r = 0; r < 3; ++r) tv[r] = fmaxf(raw[r], 0.0f);
+        for (int r = 0; r < 3; ++r) tv[r] = relu(raw[r]);
       } else {
 #pragma unroll
         for (int r = 0; r < 3; ++r) tv[r] = rcp(1.0f + __expf(-o[0][r]));
