@@ -352,7 +352,10 @@ __global__ __launch_bounds__(256) void raster_backward_kernel(
         }
         S -= w * Gi;
         const float one_m = 1.0f - e.alpha;
-        const float dLda = T * Gi - S / one_m;
+        // 1 - alpha >= 0.01 (alpha is clamped at 0.99): the hardware reciprocal
+        // (1 ulp) instead of a correctly rounded division, a tenth of the
+        // pair's instructions
+        const float dLda = T * Gi - S * __builtin_amdgcn_rcpf(one_m);
         const float dLdraw = e.araw > kAlphaMax ? 0.0f : dLda;
         gv[9] = dLdraw * e.G;
         const float dLdE = -0.5f * e.G * r2.w * dLdraw;
