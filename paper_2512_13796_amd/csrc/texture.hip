@@ -1265,13 +1265,15 @@ __device__ __forceinline__ void segmented_scan(float (&v)[N], bool head) {
   const unsigned long long upto = heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
   const int d = lane - (63 - __clzll(upto));  // lanes back to the segment start
   uint32_t h = head ? 1u : 0u;
+  // a step adds the shifted value times keep (0 at a segment head, else 1):
+  // one multiply-add per value, the same sum as a select between v and
+  // v + shifted (x * 1 + v rounds once, like x + v)
 #define NX_SEG_STEP(CTRL, MASK, NEEDED)                          \
   if (__any(NEEDED)) {                                           \
     const uint32_t sh = dpp_u<CTRL, MASK>(h);                    \
-    _Pragma("unroll") for (int q = 0; q < N; ++q) {              \
-      const float sv = dpp_f<CTRL, MASK>(v[q]);                  \
-      v[q] = h ? v[q] : v[q] + sv;                               \
-    }                                                            \
+    const float keep = h ? 0.0f : 1.0f;                          \
+    _Pragma("unroll") for (int q = 0; q < N; ++q)                \
+      v[q] = fmaf(dpp_f<CTRL, MASK>(v[q]), keep, v[q]);          \
     h |= sh;                                                     \
   }
   NX_SEG_STEP(kDppRowShr1, 0xF, d >= 1)
