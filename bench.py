@@ -37,7 +37,7 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # tested pairs of the 1080p frame: the forward evaluates the pair (27 on the gamma = 1 path up to the alpha
 # threshold) and updates the K-buffer and colour of composited pairs; the backward re-evaluates the pair, forms
 # its 16 record gradients and sums them across the wave once per surfel.
-RASTER_OPS_PER_PAIR = {"raster_forward": 38, "raster_backward": 79}
+RASTER_OPS_PER_PAIR = {"raster_forward": 38, "raster_backward": 76}
 
 
 def log(*a):
