@@ -1346,6 +1346,7 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
     const int log2bw = __builtin_ctz((unsigned)bw);  // bw is a power of two
     const int npx = (gd.width + 3) >> 2, npy = (gd.height + 3) >> 2;
     const int64_t nqK = (int64_t)npx * npy * K;
+    const float2* __restrict__ fg_level = feat_grad + (size_t)level * (size_t)nqK * 16;
     const int64_t lb = blk - sc.blk0;
     for (int i = threadIdx.x; i < nb; i += kScatThreads) hist[i] = 0u;
     const int bx = (int)(lb % nbx), by = (int)(lb / nbx);
@@ -1359,7 +1360,9 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
       const bool in = qx < npx && qy < npy;
       const SampleInfo si = sample_ray_xy(gd, K, in ? qx : 0, in ? qy : 0, j, c, depths);
       float2 e = make_float2(0.f, 0.f);
-      if (in && si.valid) e = feat_grad[((int64_t)level * nqK + ((int64_t)qy * npx + qx) * K + j) * 16 + c];
+      // the level's rows start at fg_level; a unit's index within the level
+      // (patches x K, below 2^28) fits 32 bits
+      if (in && si.valid) e = fg_level[(size_t)((uint32_t)(qy * npx + qx) * (uint32_t)K + (uint32_t)j) * 16 + c];
       const bool act = in & si.valid & ((e.x != 0.f) | (e.y != 0.f));
       const LevelGeom lg = level_geom(L, si);
       sfeat[0][smp] = act ? e.x : 0.f;
@@ -1370,11 +1373,14 @@ __global__ __launch_bounds__(kScatThreads) void scatter_bin_kernel(
       scell[smp][0] = lg.cx;
       scell[smp][1] = lg.cy;
       scell[smp][2] = lg.cz;
-      // sort key: 24 bits of the cell's hash above the sample's index within
+      // sort key: the low 8 bits of the three cell coordinates (24 bits, no
+      // multiplies; two cells of one wave share them only if they differ by
+      // multiples of 256 on all three axes) above the sample's index within
       // its wave's 128; inactive samples get a larger prefix, sort last and
-      // form no records (two cells that share the 24 bits only form two
-      // segments, as the segments compare the cells themselves)
-      const uint32_t hk = act ? (lg.hx[0] ^ lg.hy[0] ^ lg.hz[0]) & 0xFFFFFFu : kInactiveKey;
+      // form no records. Two cells that share the 24 bits only form two
+      // segments, as the segments compare the cells themselves.
+      const uint32_t ck = ((uint32_t)lg.cx & 0xFFu) | (((uint32_t)lg.cy & 0xFFu) << 8) | (((uint32_t)lg.cz & 0xFFu) << 16);
+      const uint32_t hk = act ? ck : kInactiveKey;
       skey[smp] = (hk << 7) | (uint32_t)(smp & 127);
     }
     __syncthreads();
