@@ -229,7 +229,8 @@ inline int scatter_buckets(int log2_size) { return 1 << (log2_size - scatter_buc
 // Slabs of a bin launch: workgroups and records per (workgroup, bucket) slab,
 // sized for 5/4 of the worst case (every corner of every sample a record)
 // spread evenly over the buckets.
-constexpr int kScatWorkgroups = 2048;
+constexpr int kScatWorkgroups = 2048;       // up to 16 blocks each
+constexpr int kScatWorkgroupsLarge = 3072;  // calls with more blocks
 constexpr int kBlockRecords = 4096;  // at most 8 corner records per sample
 struct ScatterSlabs {
   int64_t wgs, slab;
@@ -243,7 +244,8 @@ inline int64_t scatter_blocks(int width, int height, int K) {
 inline ScatterSlabs scatter_slabs_blocks(int64_t nblk, int nb) {
   ScatterSlabs r{0, 0};
   if (nblk <= 0) return r;
-  r.wgs = nblk < kScatWorkgroups ? nblk : kScatWorkgroups;
+  r.wgs = nblk <= 16 * (int64_t)kScatWorkgroups ? (nblk < kScatWorkgroups ? nblk : kScatWorkgroups)
+                                                  : kScatWorkgroupsLarge;
   const int64_t per_wg = (nblk + r.wgs - 1) / r.wgs;
   r.slab = (per_wg * kBlockRecords * 5 / 4 + nb - 1) / nb;
   return r;
